@@ -1,0 +1,57 @@
+"""Real-space complement (1 - G_p(r)) / r^p summed over periodic images, FP64.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Methods, "Implementation details": the Fourier sum of Eq. Fourier is paired
+with the real-space term (1 - G_p)/r^p and the self-correction E_self for a
+complete decomposition of Eq. realLR:
+
+  E_total = E_real + E_k + E_0 - E_self,
+  E_real  = 1/2 sum_n sum'_{i,j} q_i q_j (1 - G_p(|r_ij + n L|)) / |r_ij + n L|^p
+
+with G_p from Eqs. G1, G6, G and the prime excluding i = j at n = 0.
+1 - G_p vanishes for r >= r_c, so only images within r_c contribute.
+
+Pins: used only inside the total-energy pins (Madelung, splitting
+independence, brute force, Ewald) of tests/test_oracle_invariants.py.
+"""
+import numpy as np
+
+from . import kernels, reciprocal
+
+
+def real_energy(pos, q, box, p, c, r_c):
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    nimg = np.ceil(r_c / box).astype(int) + 1
+    n = pos.shape[0]
+    E = 0.0
+    d0 = pos[:, None, :] - pos[None, :, :]
+    d0 -= box * np.round(d0 / box)            # nearest image, then shift
+    qq = q[:, None] * q[None, :]
+    for ix in range(-nimg[0], nimg[0] + 1):
+        for iy in range(-nimg[1], nimg[1] + 1):
+            for iz in range(-nimg[2], nimg[2] + 1):
+                sh = np.array([ix, iy, iz], dtype=np.float64) * box
+                d = d0 + sh
+                r = np.sqrt(np.sum(d * d, axis=2))
+                mask = r < r_c
+                if ix == 0 and iy == 0 and iz == 0:
+                    mask &= ~np.eye(n, dtype=bool)
+                if not np.any(mask):
+                    continue
+                rr = r[mask]
+                E += 0.5 * np.sum(qq[mask] * (1.0 - kernels.mollifier(p, rr, c, r_c)) / rr ** p)
+    return E
+
+
+def total_energy(pos, q, box, p, c, r_c):
+    """E_real + E_k + E_0 - E_self for one channel (Eq. realLR, split)."""
+    q = np.asarray(q, dtype=np.float64)
+    V = float(np.prod(box))
+    ek = reciprocal.reciprocal_channel(pos, q, box, p, c, r_c, forces=False,
+                                       potential=False, virial=False)["E"]
+    e0 = kernels.zero_mode_coefficient(p, c, r_c, V) * float(np.sum(q)) ** 2
+    es = kernels.self_coefficient(p, c, r_c) * float(np.sum(q * q))
+    return real_energy(pos, q, box, p, c, r_c) + ek + e0 - es
