@@ -1,0 +1,177 @@
+/*
+ * pswflr.h -- C ABI of the MI355X (gfx950) PSWF-LR reciprocal-space path.
+ *
+ * What is computed (arXiv 2606.06617, Eq. Fourier and Methods,
+ * "Accelerating atom-grid spreading with PSWFs"): for each inverse-power
+ * channel c with exponent p_c in {1..6} and per-atom latent variables
+ * q_i^(c), the truncated Fourier-space energy
+ *
+ *   E_k^(c) = 1/(2V) sum_{0 < |k| <= k_c} Phi_p(|k|) |sum_i q_i exp(i k.r_i)|^2
+ *
+ * evaluated by the four-step mesh algorithm (PSWF spreading onto a periodic
+ * grid, batched 3D FFT, diagonal scaling by Phi_p / What^2, reduction), plus
+ * its exact adjoint (inverse FFT and gather) for potentials dE/dq_i and
+ * forces F_i = -dE/dr_i, and the virial.  Phi_p is the Fourier transform of
+ * the PSWF-mollified kernel G_p(r)/r^p (Eq. PhiH), k_c = c / r_c (Methods,
+ * "Parameter selection").  The zero-frequency term E_0 (Eqs. Correction,
+ * Correction3r) and the self term E_self (Methods, "Implementation
+ * details") are returned separately per channel; the long-range energy
+ * of the MLIP decomposition is E_lr = sum_c (E_k + E_0), and the complete
+ * split of Eq. realLR is E_real + E_lr - sum_c E_self.
+ *
+ * Conventions
+ *  - Units: lengths in the caller's unit (Angstrom in the paper); energies in
+ *    q^2 / length^p; any Coulomb or C6 prefactor is applied by the caller.
+ *  - Cell: orthorhombic, edges box[0..2] > 0, origin at 0; positions outside
+ *    [0, L) are wrapped.
+ *  - Memory: every array argument of the execute calls is a DEVICE pointer
+ *    owned by the caller; the library never allocates in the execute calls.
+ *    A plan owns a small device table (kilobytes) allocated at creation.
+ *  - Streams: work is enqueued on the given hipStream_t (NULL = the null
+ *    stream) and is asynchronous; outputs are valid once the stream has
+ *    reached that point.  A plan may be used concurrently on several
+ *    streams as long as each call has its own workspace.
+ *  - Errors: argument errors are detected on the host before any launch and
+ *    returned as a status; no exception crosses the ABI.  Launch failures are
+ *    returned as PSWFLR_ERR_DEVICE.  pswflr_last_error() gives the message of
+ *    the last failure on the calling thread.
+ */
+#ifndef PSWFLR_H
+#define PSWFLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSWFLR_MAX_CHANNELS 64
+#define PSWFLR_MAX_SUPPORT 8
+#define PSWFLR_MAX_GRID 1024
+
+typedef struct pswflr_plan_s *pswflr_plan; /* opaque, immutable after create */
+typedef void *pswflr_stream;               /* a hipStream_t */
+
+typedef enum {
+  PSWFLR_OK = 0,
+  PSWFLR_ERR_INVALID_ARG = 1, /* a value out of range or a NULL pointer    */
+  PSWFLR_ERR_UNSUPPORTED = 2, /* valid but not implemented (grid factors)  */
+  PSWFLR_ERR_WORKSPACE = 3,   /* workspace missing or too small            */
+  PSWFLR_ERR_DEVICE = 4,      /* a HIP call or kernel launch failed        */
+  PSWFLR_ERR_OOM = 5,         /* plan table allocation failed              */
+  PSWFLR_ERR_INTERNAL = 6
+} pswflr_status;
+
+/* Plan parameters (Methods, "Parameter selection").  Fields left at 0 (or
+ * <= 0 for doubles) are chosen automatically from `tol`. */
+typedef struct {
+  int32_t n_channels;                /* C, 1..PSWFLR_MAX_CHANNELS             */
+  int32_t p[PSWFLR_MAX_CHANNELS];    /* exponent of channel c, 1..6           */
+  double box[3];                     /* orthorhombic edges, > 0               */
+  double r_c;                        /* short-range cutoff, > 0               */
+  double c;                          /* mollifier bandwidth; <= 0: ln(3/tol)  */
+  double tol;                        /* target relative tolerance, (0, 0.1]   */
+  int32_t grid[3];                   /* M_x, M_y, M_z; 0: from tol. Each must
+                                        factor into 2, 3, 5; M_z even;
+                                        support <= M <= PSWFLR_MAX_GRID      */
+  int32_t support;                   /* P points per axis, 2..8; 0: from tol  */
+  double c_spread;                   /* window bandwidth; <= 0: minimiser of a
+                                        force-weighted aliasing estimate     */
+  uint32_t flags;                    /* reserved, 0                           */
+} pswflr_params;
+
+/* Resolved plan: what the automatic choices became, and the workspace the
+ * caller must provide for up to max_atoms atoms. */
+typedef struct {
+  double c, r_c, k_c, c_spread, eta;
+  double h[3];
+  double volume;
+  int32_t grid[3];
+  int32_t support;
+  int32_t n_channels;
+  int32_t kz_keep;        /* half-spectrum z columns kept (|k_z| <= k_c)    */
+  int32_t ny_keep;        /* y frequencies kept after the y transform        */
+  int32_t tile[3];        /* spreading/gather tile edge (grid points)        */
+  int64_t max_atoms;
+  size_t workspace_bytes; /* bytes needed by pswflr_execute                  */
+  size_t grid_offset;     /* byte offset of the real grids [C][Mx][My][Mz]   */
+  double self_coef[PSWFLR_MAX_CHANNELS]; /* E_self^(c) = self_coef * sum q^2 */
+  double zero_coef[PSWFLR_MAX_CHANNELS]; /* E_0^(c) = zero_coef * (sum q)^2  */
+} pswflr_info;
+
+/* Build a plan: host FP64 set-up of the PSWF, the kernel and window
+ * polynomial tables, the FFT factorisation and the workspace layout; copies
+ * a few kilobytes of tables to the current device.  max_atoms bounds the
+ * atom count of every later execute call.
+ * Errors: INVALID_ARG (NULL, ranges above), UNSUPPORTED (grid not 2,3,5-
+ * smooth or odd M_z), OOM, DEVICE. */
+pswflr_status pswflr_plan_create(const pswflr_params *params, int64_t max_atoms,
+                                 pswflr_plan *out);
+
+/* Copy the resolved parameters and sizes into *out. */
+pswflr_status pswflr_plan_info(pswflr_plan plan, pswflr_info *out);
+
+/* Release the plan's device table.  The caller must ensure no enqueued work
+ * still uses the plan. */
+pswflr_status pswflr_plan_destroy(pswflr_plan plan);
+
+/* One evaluation (the whole hot path) on `stream`.
+ *   pos       [N][3] float, positions (wrapped into the cell)
+ *   q         [C][N] float, latent variables per channel (SoA)
+ *   energy    [3C] double (required): per channel E_k, E_0, E_self
+ *   forces    [N][3] float or NULL: F_i = -d(sum_c E_k + E_0)/dr_i
+ *   virial    [6] double or NULL: W = -dE/d(strain) of sum_c (E_k + E_0),
+ *             order xx, yy, zz, xy, xz, yz
+ *   potential [C][N] float or NULL: d(E_k + E_0)/dq_i^(c)
+ * When forces and potential are both NULL only the forward transforms run
+ * (the energy needs no inverse FFT); the spectrum is then left in the
+ * workspace for pswflr_backward.
+ * workspace: device memory of at least info.workspace_bytes, 256-byte
+ * aligned, not shared with concurrent calls.  0 <= N <= max_atoms.
+ * Errors: INVALID_ARG, WORKSPACE, DEVICE. */
+pswflr_status pswflr_execute(pswflr_plan plan, pswflr_stream stream, void *workspace,
+                             size_t ws_bytes, int64_t n_atoms, const float *pos,
+                             const float *q, double *energy, float *forces,
+                             double *virial, float *potential);
+
+/* Adjoint of an energy-only pswflr_execute (same plan, workspace, positions
+ * and charges, no other call on that workspace in between): given
+ * grad_energy [C] (device double, dL/dE_c where E_c = E_k + E_0 of channel
+ * c), writes dL/dq [C][N] and dL/dr [N][3] (either may be NULL).
+ * This is the hand-written backward of the differentiable energy: the
+ * scaled inverse transforms and the gather. */
+pswflr_status pswflr_backward(pswflr_plan plan, pswflr_stream stream, void *workspace,
+                              size_t ws_bytes, int64_t n_atoms, const float *pos,
+                              const float *q, const double *grad_energy,
+                              float *grad_q, float *grad_pos);
+
+/* Many structures in one call (MLIP training batches, serving mixes).  Each
+ * entry has its own plan (box, grid and channels may differ) and its own
+ * device pointers; semantics per entry are those of pswflr_execute.  All
+ * stages of all entries are issued as one persistent launch per stage
+ * group; results for an entry do not depend on the other entries. */
+typedef struct {
+  int64_t n_atoms;
+  const float *pos;
+  const float *q;
+  double *energy;
+  float *forces;
+  double *virial;
+  float *potential;
+} pswflr_io;
+
+pswflr_status pswflr_batch_workspace(int32_t n, const pswflr_plan *plans,
+                                     const int64_t *n_atoms, size_t *bytes);
+pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans,
+                                   const pswflr_io *io, pswflr_stream stream,
+                                   void *workspace, size_t ws_bytes);
+
+const char *pswflr_status_string(pswflr_status status);
+/* Copies the last error message of the calling thread (NUL-terminated). */
+void pswflr_last_error(char *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSWFLR_H */

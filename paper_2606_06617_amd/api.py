@@ -1,0 +1,166 @@
+"""Python API over the C ABI: plans, one-structure evaluation, the autograd
+adjoint.  PyTorch provides device memory and the current stream only.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A resolved PSWF-LR evaluation plan for one box and channel set.
+
+    box: 3 orthorhombic edges; ps: exponent per channel (1..6); r_c: the
+    short-range cutoff (k_c = c / r_c); c: mollifier bandwidth (0: from tol);
+    grid: (Mx, My, Mz) or None (from tol); support: window points per axis
+    P (0: from tol); c_spread: window bandwidth (0: automatic).
+    """
+
+    def __init__(self, box, ps, r_c=5.0, c=12.024, tol=1e-5, grid=None, support=0, c_spread=0.0,
+                 max_atoms=1):
+        L = _lib.lib()
+        self.params = _lib.make_params(box, ps, r_c, c, tol, grid, support, c_spread)
+        h = ctypes.c_void_p()
+        _lib.check(L.pswflr_plan_create(ctypes.byref(self.params), int(max_atoms), ctypes.byref(h)))
+        self.handle = h
+        inf = _lib.Info()
+        _lib.check(L.pswflr_plan_info(h, ctypes.byref(inf)))
+        self.info_raw = inf
+        C = inf.n_channels
+        self.info = {
+            "c": inf.c, "r_c": inf.r_c, "k_c": inf.k_c, "c_spread": inf.c_spread, "eta": inf.eta,
+            "h": tuple(inf.h), "volume": inf.volume, "grid": tuple(inf.grid), "support": inf.support,
+            "n_channels": C, "kz_keep": inf.kz_keep, "ny_keep": inf.ny_keep, "tile": tuple(inf.tile),
+            "max_atoms": inf.max_atoms, "workspace_bytes": inf.workspace_bytes,
+            "grid_offset": inf.grid_offset,
+            "self_coef": [inf.self_coef[i] for i in range(C)],
+            "zero_coef": [inf.zero_coef[i] for i in range(C)],
+        }
+        self.ps = list(ps)
+        self.box = tuple(float(b) for b in box)
+        self.C = C
+        self.max_atoms = int(max_atoms)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                _lib.lib().pswflr_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    @property
+    def workspace_bytes(self):
+        return int(self.info["workspace_bytes"])
+
+    def new_workspace(self, device="cuda"):
+        # caching-allocator blocks are at least 512-byte aligned
+        ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+        assert ws.data_ptr() % 256 == 0
+        return ws
+
+    def execute(self, pos, q, forces=True, virial=True, potential=False, workspace=None, stream=None,
+                out=None):
+        """Evaluate energy [3C] (E_k, E_0, E_self per channel), forces [N,3],
+        virial [6] and potentials [C,N] on the current stream.
+
+        pos: float32 [N,3] CUDA tensor; q: float32 [C,N] CUDA tensor.
+        """
+        _check_inputs(pos, q, self.C, self.max_atoms)
+        N = pos.shape[0]
+        dev = pos.device
+        ws = workspace if workspace is not None else self.new_workspace(dev)
+        o = out or {}
+        energy = o.get("energy")
+        if energy is None:
+            energy = torch.empty(3 * self.C, dtype=torch.float64, device=dev)
+        F = (o.get("forces") if o.get("forces") is not None else
+             torch.empty((N, 3), dtype=torch.float32, device=dev)) if forces else None
+        W = (o.get("virial") if o.get("virial") is not None else
+             torch.empty(6, dtype=torch.float64, device=dev)) if virial else None
+        phi = (o.get("potential") if o.get("potential") is not None else
+               torch.empty((self.C, N), dtype=torch.float32, device=dev)) if potential else None
+        st = _lib.lib().pswflr_execute(self.handle, _stream(stream), _ptr(ws), ws.numel(), N, _ptr(pos),
+                                       _ptr(q), _ptr(energy), _ptr(F), _ptr(W), _ptr(phi))
+        _lib.check(st)
+        return {"energy": energy, "forces": F, "virial": W, "potential": phi, "workspace": ws}
+
+    def backward(self, workspace, pos, q, grad_energy, want_q=True, want_pos=True, stream=None):
+        """Adjoint of an energy-only execute on the same workspace."""
+        N = pos.shape[0]
+        dev = pos.device
+        gq = torch.empty((self.C, N), dtype=torch.float32, device=dev) if want_q else None
+        gp = torch.empty((N, 3), dtype=torch.float32, device=dev) if want_pos else None
+        g = grad_energy.to(device=dev, dtype=torch.float64).contiguous()
+        st = _lib.lib().pswflr_backward(self.handle, _stream(stream), _ptr(workspace), workspace.numel(), N,
+                                        _ptr(pos), _ptr(q), _ptr(g), _ptr(gq), _ptr(gp))
+        _lib.check(st)
+        return gq, gp
+
+
+def _check_inputs(pos, q, C, max_atoms):
+    if not (pos.is_cuda and q.is_cuda):
+        raise ValueError("pos and q must be CUDA (HIP) tensors")
+    if pos.dtype != torch.float32 or q.dtype != torch.float32:
+        raise ValueError("pos and q must be float32")
+    if pos.dim() != 2 or pos.shape[1] != 3 or not pos.is_contiguous():
+        raise ValueError("pos must be a contiguous [N, 3] tensor")
+    if q.dim() != 2 or q.shape[0] != C or q.shape[1] != pos.shape[0] or not q.is_contiguous():
+        raise ValueError("q must be a contiguous [C, N] tensor")
+    if pos.shape[0] > max_atoms:
+        raise ValueError("N exceeds the plan's max_atoms")
+
+
+def energy_forces(pos, q, box, ps, r_c=5.0, c=12.024, tol=1e-5, grid=None, support=0, c_spread=0.0,
+                  virial=True, potential=False):
+    """One-shot convenience: build a plan for this structure and evaluate it."""
+    plan = Plan(box, ps, r_c=r_c, c=c, tol=tol, grid=grid, support=support, c_spread=c_spread,
+                max_atoms=max(1, pos.shape[0]))
+    out = plan.execute(pos, q, forces=True, virial=virial, potential=potential)
+    out["plan"] = plan
+    return out
+
+
+class PSWFLRFunction(torch.autograd.Function):
+    """E_lr = sum_c (E_k + E_0) as a differentiable function of (pos, q).
+
+    Forward runs only the forward transforms (the energy needs no inverse
+    FFT) and keeps the spectrum in the plan's workspace; backward runs the
+    hand-written adjoint (scaled inverse transforms and the gather) and
+    returns dE/dq and dE/dpos.
+    """
+
+    @staticmethod
+    def forward(ctx, pos, q, plan):
+        ws = plan.new_workspace(pos.device)
+        out = plan.execute(pos.detach(), q.detach(), forces=False, virial=False, potential=False,
+                           workspace=ws)
+        e = out["energy"].view(-1, 3)
+        ctx.plan = plan
+        ctx.ws = ws
+        ctx.save_for_backward(pos.detach(), q.detach())
+        return (e[:, 0] + e[:, 1]).sum()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        pos, q = ctx.saved_tensors
+        plan = ctx.plan
+        g = grad_out.detach().to(torch.float64).reshape(1).expand(plan.C).contiguous()
+        gq, gp = plan.backward(ctx.ws, pos, q, g, want_q=ctx.needs_input_grad[1],
+                               want_pos=ctx.needs_input_grad[0])
+        return gp, gq, None
+
+
+def lr_energy(pos, q, plan):
+    return PSWFLRFunction.apply(pos, q, plan)

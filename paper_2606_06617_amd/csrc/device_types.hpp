@@ -1,0 +1,100 @@
+// Plain-data structures passed by value from the planner to the gfx950
+// kernels.  No HIP or torch types here so that host-only translation units
+// can include it.
+#pragma once
+
+#include <cstdint>
+
+namespace pswf {
+
+constexpr int kMaxRadixStages = 8;
+constexpr int kWinSeg = 8;     // window polynomial: segments on |t| in [0, 1]
+constexpr int kWinDeg = 11;    // degree per segment
+constexpr int kKerSeg = 16;    // kernel polynomials: segments on kappa in [0, 1]
+constexpr int kKerDeg = 11;
+constexpr int kKerCoef = kKerSeg * (kKerDeg + 1);
+
+// Stockham factorisation of one transform length.
+struct FftAxis {
+  int n = 1;
+  int nst = 0;
+  int rad[kMaxRadixStages] = {0};
+};
+
+// Per-channel constants of the Fourier kernel (see host_math.hpp):
+//   Phi     = A kappa^eA f(kappa) + B kappa^eB ln(kappa)
+//   Phi'/k  = Cc kappa^eC g(kappa) + D kappa^eD ln(kappa)
+struct KChan {
+  float A, B, Cc, D;
+  int eA, eB, eC, eD;
+  int p;
+  float zero_over_V;   // E_0 = zero_over_V * Q_net^2 (double on host)
+  float pad[2];
+};
+
+// One problem geometry.  Doubles where positions are turned into grid
+// coordinates (FP32 would lose ~3e-5 grid units at M = 256).
+struct Geo {
+  int C;                  // channels
+  int64_t N;              // atoms
+  int M[3];               // grid
+  int Nz;                 // M_z / 2 (complex length of the z transform)
+  int KZ;                 // half-spectrum z columns kept
+  int NY, FY;             // y frequencies kept: fy in [-FY, FY], NY = 2 FY + 1
+  int P;                  // window support
+  int B[3];               // tile edge per axis
+  int nc[3];              // tiles per axis
+  int ncell;
+  double L[3];            // box
+  double Minv_L[3];       // M / L
+  float kunit[3];         // 2 pi / L
+  float kc2;              // k_c^2
+  float kinv;             // r_c / c  (kappa = k * kinv)
+  float dwin[3];          // 2 / (P h): d t / d r for the window derivative
+  float invV;
+  double V;
+  int CG_spread;          // channels per spread pass
+  int CG_gather;          // channels per gather pass
+  int nxblk;              // blocks of the fused x pass
+  int zlines;             // lines per z-pass block (power of two)
+  int kb;                 // columns per y/x-pass block (power of two)
+  int kb_log2;
+};
+
+// Device pointers into a plan's table allocation.
+struct Tables {
+  const float *tw_z;      // [Nz] exp(-2 pi i n / Nz), as float2
+  const float *tw_zr;     // [Nz + 1] exp(-2 pi i k / M_z), as float2
+  const float *tw_y;      // [M_y] as float2
+  const float *tw_x;      // [M_x] as float2
+  const float *Dx;        // [M_x] h^2 / What_x^2 by array index
+  const float *Dy;        // [NY]  by kept index
+  const float *Dz;        // [KZ]
+  const float *win;       // [kWinSeg][kWinDeg + 1]
+  const float *kf;        // [C][kKerCoef]
+  const float *kg;        // [C][kKerCoef]
+  const KChan *kch;       // [C]
+  const int *xblk;        // [nxblk][4]: iy, kz0, ncols, 0
+  const int *blim;        // [NY] z columns processed by the x pass per iy
+  const double *self_coef;  // [C] E_self = self_coef * sum q^2
+  const double *zero_V;     // [C] E_0 = zero_V / V * Q_net^2
+};
+
+// Workspace carve-up (device pointers), produced per call.
+struct Work {
+  float *grid;            // [C][Mx][My][Mz]
+  float *s1;              // [C][Mx][My][KZ] complex
+  float *s2;              // [C][Mx][NY][KZ] complex
+  float *rec_a, *rec_b;   // [N][4]: delta_x, delta_y, delta_z, packed n0 bits
+  float *q_a, *q_b;       // [C][N] in cell order
+  int *perm_a, *perm_b;   // cell order -> caller order
+  int *cell_of, *slot;    // [N]
+  int *cell_count;        // [ncell]
+  int *cell_start;        // [ncell + 1]
+  float *facc;            // [N][3] force accumulator in cell order
+  double *epart;          // [C][nxblk][8]
+  double *qpart;          // [nqblk][C][2]
+  double *qsum;           // [C][2]: Q_net, Q_self
+};
+
+}  // namespace pswf

@@ -1,0 +1,477 @@
+// Host-side FP64 mathematics of the PSWF-LR path (see host_math.hpp).
+#include "host_math.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <tuple>
+
+namespace pswf {
+
+static const double kPi = 3.14159265358979323846264338327950288;
+
+void gauss_legendre(int n, double a, double b, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = 0.0;
+      for (int k = 1; k <= n; ++k) {
+        double p2 = p1;
+        p1 = p0;
+        p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+      }
+      dp = n * (z * p0 - p1) / (z * z - 1.0);
+      double dz = p0 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = 0.0;
+    for (int k = 1; k <= n; ++k) {
+      double p2 = p1;
+      p1 = p0;
+      p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+    }
+    dp = n * (z * p0 - p1) / (z * z - 1.0);
+    double wi = 2.0 / ((1.0 - z * z) * dp * dp);
+    // z is the i-th largest root
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = wi;
+    w[n - 1 - i] = wi;
+  }
+  for (int i = 0; i < n; ++i) {
+    x[i] = 0.5 * (b - a) * (x[i] + 1.0) + a;
+    w[i] *= 0.5 * (b - a);
+  }
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (row-major).
+// On return a holds the eigenvalues on its diagonal, v the eigenvectors in
+// its columns.
+static void jacobi_eigen(int n, std::vector<double> &a, std::vector<double> &v) {
+  v.assign(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) v[size_t(i) * n + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double e = a[size_t(i) * n + j] * a[size_t(i) * n + j];
+        tot += e;
+        if (i != j) off += e;
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = a[size_t(p) * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        double app = a[size_t(p) * n + p], aqq = a[size_t(q) * n + q];
+        double theta = (aqq - app) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {
+          double akp = a[size_t(k) * n + p], akq = a[size_t(k) * n + q];
+          a[size_t(k) * n + p] = cs * akp - sn * akq;
+          a[size_t(k) * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          double apk = a[size_t(p) * n + k], aqk = a[size_t(q) * n + k];
+          a[size_t(p) * n + k] = cs * apk - sn * aqk;
+          a[size_t(q) * n + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          double vkp = v[size_t(k) * n + p], vkq = v[size_t(k) * n + q];
+          v[size_t(k) * n + p] = cs * vkp - sn * vkq;
+          v[size_t(k) * n + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+}
+
+Prolate::Prolate(double c, int nodes) : c_(c) {
+  if (!(c > 0.0)) throw std::invalid_argument("prolate bandwidth must be positive");
+  gauss_legendre(nodes, 0.0, 1.0, t_, w_);
+  const int n = nodes;
+  std::vector<double> a(size_t(n) * n), v;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      a[size_t(i) * n + j] = 2.0 * std::sqrt(w_[i] * w_[j]) * std::cos(c * t_[i] * t_[j]);
+  jacobi_eigen(n, a, v);
+  int best = 0;
+  for (int i = 1; i < n; ++i)
+    if (a[size_t(i) * n + i] > a[size_t(best) * n + best]) best = i;
+  lam_ = a[size_t(best) * n + best];
+  std::vector<double> psi(n);
+  for (int j = 0; j < n; ++j) psi[j] = v[size_t(j) * n + best] / std::sqrt(w_[j]);
+  double psi0 = 0.0;
+  for (int j = 0; j < n; ++j) psi0 += 2.0 / lam_ * w_[j] * psi[j];
+  wpsi_.resize(n);
+  for (int j = 0; j < n; ++j) wpsi_[j] = 2.0 / lam_ * w_[j] * psi[j] / psi0;
+  gauss_legendre(64, 0.0, 1.0, qx_, qw_);
+  // quadrature for the window transform at frequencies up to ~200
+  std::vector<double> fw;
+  gauss_legendre(320, 0.0, 1.0, fx_, fw);
+  fwpsi_.resize(fx_.size());
+  for (size_t i = 0; i < fx_.size(); ++i) fwpsi_[i] = 2.0 * fw[i] * (*this)(fx_[i]);
+}
+
+double Prolate::operator()(double x) const {
+  double s = 0.0;
+  for (size_t j = 0; j < t_.size(); ++j) s += wpsi_[j] * std::cos(c_ * x * t_[j]);
+  return s;
+}
+double Prolate::d1(double x) const {
+  double s = 0.0;
+  for (size_t j = 0; j < t_.size(); ++j) s -= wpsi_[j] * c_ * t_[j] * std::sin(c_ * x * t_[j]);
+  return s;
+}
+double Prolate::d2(double x) const {
+  double s = 0.0;
+  for (size_t j = 0; j < t_.size(); ++j) {
+    double a = c_ * t_[j];
+    s -= wpsi_[j] * a * a * std::cos(a * x);
+  }
+  return s;
+}
+double Prolate::deriv0(int n) const {
+  double s = 0.0;
+  double sign = ((n / 2) % 2 == 0) ? 1.0 : -1.0;
+  for (size_t j = 0; j < t_.size(); ++j) s += wpsi_[j] * std::pow(c_ * t_[j], n);
+  return sign * s;
+}
+double Prolate::I0(double k) const {
+  double s = 0.0;
+  for (size_t j = 0; j < t_.size(); ++j) s += wpsi_[j] * std::sin(c_ * k * t_[j]) / (c_ * t_[j]);
+  return s;
+}
+double Prolate::J1(double k) const {
+  double s = 0.0, L = 1.0 - k;
+  for (size_t i = 0; i < qx_.size(); ++i) {
+    double u = k + L * qx_[i];
+    s += L * qw_[i] * u * (*this)(u);
+  }
+  return s;
+}
+double Prolate::J3(double k) const {
+  double s = 0.0, L = 1.0 - k;
+  for (size_t i = 0; i < qx_.size(); ++i) {
+    double u = k + L * qx_[i];
+    s += L * qw_[i] * u * u * u * (*this)(u);
+  }
+  return s;
+}
+double Prolate::T3(double k) const {
+  double s = 0.0, L = 1.0 - k;
+  for (size_t i = 0; i < qx_.size(); ++i) {
+    double u = k + L * qx_[i];
+    s += L * qw_[i] * ((*this)(u) - 1.0) / u;
+  }
+  return s;
+}
+double Prolate::window_ft(double s) const {
+  double acc = 0.0;
+  for (size_t i = 0; i < fx_.size(); ++i) acc += fwpsi_[i] * std::cos(s * fx_[i]);
+  return acc;
+}
+
+std::shared_ptr<const Prolate> prolate_cached(double c) {
+  static std::mutex mu;
+  static std::map<double, std::shared_ptr<const Prolate>> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(c);
+  if (it != cache.end()) return it->second;
+  auto p = std::make_shared<const Prolate>(c);
+  cache[c] = p;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+double PiecewisePoly::eval(double x) const {
+  double y = x * nseg;
+  int s = std::min(nseg - 1, std::max(0, int(std::floor(y))));
+  double tau = 2.0 * (y - s) - 1.0;
+  const double *cf = &coef[size_t(s) * (deg + 1)];
+  double r = cf[deg];
+  for (int d = deg - 1; d >= 0; --d) r = r * tau + cf[d];
+  return r;
+}
+
+template <class F>
+PiecewisePoly fit_piecewise(F f, int nseg, int deg, double eps) {
+  PiecewisePoly pp;
+  pp.nseg = nseg;
+  pp.deg = deg;
+  pp.coef.assign(size_t(nseg) * (deg + 1), 0.0);
+  const int n = deg + 1;
+  // monomial expansions of T_0..T_deg
+  std::vector<std::vector<double>> T(n, std::vector<double>(n, 0.0));
+  T[0][0] = 1.0;
+  if (n > 1) T[1][1] = 1.0;
+  for (int m = 2; m < n; ++m)
+    for (int d = 0; d < n; ++d) {
+      double v = -T[m - 2][d];
+      if (d > 0) v += 2.0 * T[m - 1][d - 1];
+      T[m][d] = v;
+    }
+  for (int s = 0; s < nseg; ++s) {
+    double a = double(s) / nseg, b = double(s + 1) / nseg;
+    std::vector<double> fv(n), ch(n, 0.0);
+    for (int j = 0; j < n; ++j) {
+      double y = std::cos(kPi * (j + 0.5) / n);
+      fv[j] = f(0.5 * (b - a) * (y + 1.0) + a);
+    }
+    double amax = 0.0;
+    for (int m = 0; m < n; ++m) {
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) acc += fv[j] * std::cos(kPi * m * (j + 0.5) / n);
+      ch[m] = (m == 0 ? 1.0 : 2.0) * acc / n;
+      amax = std::max(amax, std::fabs(ch[m]));
+    }
+    for (int m = 0; m < n; ++m)
+      if (std::fabs(ch[m]) <= 0.01 * eps * amax) ch[m] = 0.0;
+    double *cf = &pp.coef[size_t(s) * n];
+    for (int m = 0; m < n; ++m)
+      for (int d = 0; d < n; ++d) cf[d] += ch[m] * T[m][d];
+  }
+  double err = 0.0;
+  for (int i = 0; i <= 4000; ++i) {
+    double x = i / 4000.0;
+    err = std::max(err, std::fabs(pp.eval(x) - f(x)));
+  }
+  pp.max_abs_err = err;
+  return pp;
+}
+
+PiecewisePoly make_window_poly(double c_s, int nseg, int deg, double eps) {
+  auto ws = prolate_cached(c_s);
+  return fit_piecewise([&](double x) { return (*ws)(x); }, nseg, deg, eps);
+}
+
+// ---------------------------------------------------------------------------
+// Fourier kernels Phi_p (Eq. PhiH), band-limited reading: the Fourier-side
+// integrals of lambda0 psi(x/c) run over [0, c], so Chat0 = lambda0 c C0
+// and Phi_p vanishes for k > c / r_c.  With K = c / r_c, kappa = k / K:
+//   Phi1 = 4 pi psi(kappa) / k^2
+//   Phi2 = 2 pi^2 T2(kappa) / k,                T2 = 1 - I0/C0
+//   Phi3 = 4 pi (T3(kappa) - ln kappa)
+//   Phi4 = -pi^2 k T2 + pi^2 K J1 / C0
+//   Phi5 = -(2 pi/3) (k^2 (T3 - ln kappa) - K^2 J1)
+//   Phi6 = (pi^2/12) (k^3 T2 - (3 k^2 K / (2 C0)) J1 + K^3 J3 / (2 C0))
+double phi_hat(const Prolate &ps, int p, double k, double c, double r_c) {
+  const double K = c / r_c, kap = k / K;
+  if (kap > 1.0) return 0.0;
+  const double C0 = ps.C0();
+  const double T2 = 1.0 - ps.I0(kap) / C0;
+  switch (p) {
+    case 1: return 4.0 * kPi * ps(kap) / (k * k);
+    case 2: return 2.0 * kPi * kPi * T2 / k;
+    case 3: return 4.0 * kPi * (ps.T3(kap) - std::log(kap));
+    case 4: return -kPi * kPi * k * T2 + kPi * kPi * K * ps.J1(kap) / C0;
+    case 5: return -(2.0 * kPi / 3.0) * (k * k * (ps.T3(kap) - std::log(kap)) - K * K * ps.J1(kap));
+    case 6:
+      return (kPi * kPi / 12.0) * (k * k * k * T2 - 1.5 * k * k * K * ps.J1(kap) / C0 +
+                                   K * K * K * ps.J3(kap) / (2.0 * C0));
+  }
+  throw std::invalid_argument("p must be 1..6");
+}
+
+// d Phi_p / dk, differentiating under the integral sign (dI0/dkappa = psi,
+// dJ1/dkappa = -kappa psi, dJ3/dkappa = -kappa^3 psi, dT3/dkappa =
+// -(psi - 1)/kappa); the psi terms cancel for p = 4, 5, 6.
+double phi_hat_deriv(const Prolate &ps, int p, double k, double c, double r_c) {
+  const double K = c / r_c, kap = k / K;
+  if (kap > 1.0) return 0.0;
+  const double C0 = ps.C0();
+  const double T2 = 1.0 - ps.I0(kap) / C0;
+  switch (p) {
+    case 1: return 4.0 * kPi * (kap * ps.d1(kap) - 2.0 * ps(kap)) / (k * k * k);
+    case 2: return -2.0 * kPi * kPi * T2 / (k * k) - 2.0 * kPi * kPi * kap * ps(kap) / (C0 * k * k);
+    case 3: return -4.0 * kPi * ps(kap) / k;
+    case 4: return -kPi * kPi * T2;
+    case 5: return -(4.0 * kPi / 3.0) * k * (ps.T3(kap) - std::log(kap));
+    case 6: return (kPi * kPi / 4.0) * (k * k * T2 - k * K * ps.J1(kap) / C0);
+  }
+  throw std::invalid_argument("p must be 1..6");
+}
+
+ChannelKernel make_channel_kernel(int p, double c, double r_c, double eps) {
+  auto psp = prolate_cached(c);
+  const Prolate &ps = *psp;
+  const double K = c / r_c, C0 = ps.C0();
+  const int nseg = 16, deg = 11;
+  ChannelKernel ck;
+  ck.p = p;
+  auto T2 = [&](double x) { return 1.0 - ps.I0(x) / C0; };
+  switch (p) {
+    case 1:
+      ck.A = 4.0 * kPi / (K * K); ck.eA = -2;
+      ck.f = fit_piecewise([&](double x) { return ps(x); }, nseg, deg, eps);
+      ck.Cc = 4.0 * kPi / (K * K * K * K); ck.eC = -4;
+      ck.g = fit_piecewise([&](double x) { return x * ps.d1(x) - 2.0 * ps(x); }, nseg, deg, eps);
+      break;
+    case 2:
+      ck.A = 2.0 * kPi * kPi / K; ck.eA = -1;
+      ck.f = fit_piecewise(T2, nseg, deg, eps);
+      ck.Cc = 2.0 * kPi * kPi / (K * K * K); ck.eC = -3;
+      ck.g = fit_piecewise([&](double x) { return -T2(x) - x * ps(x) / C0; }, nseg, deg, eps);
+      break;
+    case 3:
+      ck.A = 4.0 * kPi; ck.eA = 0;
+      ck.f = fit_piecewise([&](double x) { return ps.T3(x); }, nseg, deg, eps);
+      ck.B = -4.0 * kPi; ck.eB = 0;
+      ck.Cc = -4.0 * kPi / (K * K); ck.eC = -2;
+      ck.g = fit_piecewise([&](double x) { return ps(x); }, nseg, deg, eps);
+      break;
+    case 4:
+      ck.A = 1.0; ck.eA = 0;
+      ck.f = fit_piecewise([&](double x) { return -kPi * kPi * K * x * T2(x) + kPi * kPi * K * ps.J1(x) / C0; },
+                           nseg, deg, eps);
+      ck.Cc = -kPi * kPi / K; ck.eC = -1;
+      ck.g = fit_piecewise(T2, nseg, deg, eps);
+      break;
+    case 5:
+      ck.A = 1.0; ck.eA = 0;
+      ck.f = fit_piecewise([&](double x) { return -(2.0 * kPi / 3.0) * K * K * (x * x * ps.T3(x) - ps.J1(x)); },
+                           nseg, deg, eps);
+      ck.B = (2.0 * kPi / 3.0) * K * K; ck.eB = 2;
+      ck.Cc = -4.0 * kPi / 3.0; ck.eC = 0;
+      ck.g = fit_piecewise([&](double x) { return ps.T3(x); }, nseg, deg, eps);
+      ck.D = 4.0 * kPi / 3.0; ck.eD = 0;
+      break;
+    case 6:
+      ck.A = kPi * kPi * K * K * K / 12.0; ck.eA = 0;
+      ck.f = fit_piecewise([&](double x) {
+        return x * x * x * T2(x) - 1.5 * x * x * ps.J1(x) / C0 + ps.J3(x) / (2.0 * C0);
+      }, nseg, deg, eps);
+      ck.Cc = kPi * kPi * K / 4.0; ck.eC = 0;
+      ck.g = fit_piecewise([&](double x) { return x * T2(x) - ps.J1(x) / C0; }, nseg, deg, eps);
+      break;
+    default:
+      throw std::invalid_argument("p must be 1..6");
+  }
+  // Self term (Methods, "Implementation details"): E_self = s_p sum q^2.
+  const double d2 = ps.deriv0(2), d4 = ps.deriv0(4), d6 = ps.deriv0(6);
+  switch (p) {
+    case 1: ck.self_coef = 1.0 / (2.0 * C0 * r_c); break;
+    case 2: ck.self_coef = -d2 / (4.0 * r_c * r_c); break;
+    case 3: ck.self_coef = -d2 / (6.0 * C0 * std::pow(r_c, 3)); break;
+    case 4: ck.self_coef = d4 / (48.0 * std::pow(r_c, 4)); break;
+    case 5: ck.self_coef = d4 / (90.0 * C0 * std::pow(r_c, 5)); break;
+    case 6: ck.self_coef = -d6 / (1440.0 * std::pow(r_c, 6)); break;
+  }
+  // Zero-frequency term E_0 = (zero_coef_V / V) Q_net^2 (Eqs. Correction,
+  // Correction3r; p > 3 is Phi_p(0)/2).  For p = 1 the k -> 0 limit of
+  // (Phi1 - 4 pi / k^2) / 2 = -pi chi0 / K^2 is used (tin-foil boundary,
+  // E_IB = 0), which keeps the total independent of (c, r_c).
+  switch (p) {
+    case 1: ck.zero_coef_V = -kPi * ps.chi() / (K * K); break;
+    case 2: ck.zero_coef_V = -2.0 * kPi * r_c * C0; break;
+    case 3: ck.zero_coef_V = 2.0 * kPi * (std::log(c / r_c) + ps.T3(0.0)); break;
+    case 4: ck.zero_coef_V = 0.5 * kPi * kPi * K * ps.J1(0.0) / C0; break;
+    case 5: ck.zero_coef_V = 0.5 * (2.0 * kPi / 3.0) * K * K * ps.J1(0.0); break;
+    case 6: ck.zero_coef_V = 0.5 * (kPi * kPi / 12.0) * K * K * K * ps.J3(0.0) / (2.0 * C0); break;
+  }
+  return ck;
+}
+
+// ---------------------------------------------------------------------------
+// Spreading-error estimate.  In grid units (h = 1) the truncated window has
+// the transform What(s) = omega * int_{-1}^{1} psi_s(t) cos(s omega t) dt,
+// omega = P/2.  Sampling on the grid aliases every mode k with k + 2 pi j,
+// so the relative error of the deconvolved mode is approximately
+//   r(k) = sum_{j != 0} |What(k + 2 pi j)| / What(k)   per axis.
+// The estimate is the RMS of r(k_x) + r(k_y) + r(k_z) over the k-ball
+// |k| <= eta pi, weighted by the force spectrum of the p = 1 kernel for
+// uncorrelated charges (Phi_1^2 k^2 per mode, i.e. psi_c(kappa)^2 per
+// radial shell).  Its minimiser over c_s tracks the measured optimum of the
+// force error closely; its magnitude is about 1/25 of that error.
+double estimate_spread_error(int P, double eta, double c_s, double c_moll) {
+  auto ws = prolate_cached(c_s);
+  auto pc = prolate_cached(c_moll);
+  const double omega = 0.5 * P, kmax = eta * kPi;
+  const int nk = 97;
+  std::vector<double> rk(nk);
+  for (int i = 0; i < nk; ++i) {
+    double k = kmax * i / (nk - 1);
+    double w0 = omega * ws->window_ft(k * omega);
+    double a = 0.0;
+    for (int j = 1; j <= 4; ++j)
+      a += std::fabs(omega * ws->window_ft((k + 2 * kPi * j) * omega)) +
+           std::fabs(omega * ws->window_ft((k - 2 * kPi * j) * omega));
+    rk[i] = a / std::fabs(w0);
+  }
+  auto interp = [&](double k) {
+    double y = std::fabs(k) / kmax * (nk - 1);
+    int i = std::min(nk - 2, int(y));
+    double f = y - i;
+    return rk[i] * (1 - f) + rk[i + 1] * f;
+  };
+  std::vector<double> rx, rw, cx, cw;
+  gauss_legendre(20, 0.0, 1.0, rx, rw);
+  gauss_legendre(12, -1.0, 1.0, cx, cw);
+  double num = 0.0, den = 0.0;
+  for (size_t i = 0; i < rx.size(); ++i) {
+    double wr = rw[i] * std::pow((*pc)(rx[i]), 2);
+    for (size_t j = 0; j < cx.size(); ++j) {
+      double ct = cx[j], st = std::sqrt(std::max(0.0, 1 - ct * ct));
+      for (int m = 0; m < 24; ++m) {
+        double ph = 2 * kPi * (m + 0.5) / 24;
+        double kx = kmax * rx[i] * st * std::cos(ph), ky = kmax * rx[i] * st * std::sin(ph),
+               kz = kmax * rx[i] * ct;
+        double e = interp(kx) + interp(ky) + interp(kz);
+        double wgt = wr * cw[j];
+        num += wgt * e * e;
+        den += wgt;
+      }
+    }
+  }
+  return std::sqrt(num / den);
+}
+
+double choose_c_spread(int P, double eta, double c_moll) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, long, long>, double> cache;
+  auto key = std::make_tuple(P, std::lround(eta * 1e4), std::lround(c_moll * 1e4));
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  // golden-section search on log(error) over [2.2 P, 3.2 P]
+  double a = 2.2 * P, b = 3.2 * P;
+  const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+  double x1 = b - g * (b - a), x2 = a + g * (b - a);
+  double f1 = estimate_spread_error(P, eta, x1, c_moll), f2 = estimate_spread_error(P, eta, x2, c_moll);
+  for (int it = 0; it < 18; ++it) {
+    if (f1 < f2) {
+      b = x2; x2 = x1; f2 = f1; x1 = b - g * (b - a);
+      f1 = estimate_spread_error(P, eta, x1, c_moll);
+    } else {
+      a = x1; x1 = x2; f1 = f2; x2 = a + g * (b - a);
+      f2 = estimate_spread_error(P, eta, x2, c_moll);
+    }
+  }
+  double best = std::round(0.5 * (a + b) * 1e3) / 1e3;
+  std::lock_guard<std::mutex> lock(mu);
+  cache[key] = best;
+  return best;
+}
+
+bool is_smooth235(int m) {
+  if (m < 1) return false;
+  for (int p : {2, 3, 5})
+    while (m % p == 0) m /= p;
+  return m == 1;
+}
+
+int smooth_size(double x, bool even) {
+  int m = std::max(1, int(std::ceil(x - 1e-9)));
+  while (!is_smooth235(m) || (even && (m % 2))) ++m;
+  return m;
+}
+
+}  // namespace pswf

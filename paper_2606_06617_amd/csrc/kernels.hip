@@ -1,0 +1,1110 @@
+// gfx950 kernels of the PSWF-LR reciprocal-space path.
+//
+// Pipeline (Methods, "Accelerating atom-grid spreading with PSWFs"):
+//   bin/sort  -> spread (step i) -> z R2C, y FFT (step ii)
+//   -> fused [x FFT, diagonal scaling + energy/virial partials (steps iii,
+//      iv), inverse x FFT] -> inverse y, z C2R -> gather (adjoint of i)
+//   -> FP64 reductions.
+// The spectrum is pruned to the k-ball: only |k_z| <= k_c columns leave the
+// z transform and only |k_y| <= k_c rows leave the y transform, since the
+// kernel Phi_p vanishes beyond k_c (Eq. Fourier truncation).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "device_types.hpp"
+#include "kernels.hpp"
+
+namespace pswf {
+
+#define PSWF_THREADS 256
+
+// ---------------------------------------------------------------------------
+// complex helpers
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by i*sigma (sigma = +-1)
+template <int S>
+__device__ __forceinline__ float2 mul_isig(float2 a) {
+  return S > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// Small DFTs y_k = sum_j x_j w^(jk), w = exp(S 2 pi i / R), in place.
+template <int R, int S>
+struct Dft;
+
+template <int S>
+struct Dft<2, S> {
+  __device__ __forceinline__ static void run(float2 *x) {
+    float2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  }
+};
+
+template <int S>
+struct Dft<3, S> {
+  __device__ __forceinline__ static void run(float2 *x) {
+    const float h = 0.86602540378443864676f;  // sqrt(3)/2
+    float2 s = cadd(x[1], x[2]), d = csub(x[1], x[2]);
+    float2 m = make_float2(x[0].x - 0.5f * s.x, x[0].y - 0.5f * s.y);
+    float2 r = cscale(mul_isig<S>(d), h);
+    x[0] = cadd(x[0], s);
+    x[1] = cadd(m, r);
+    x[2] = csub(m, r);
+  }
+};
+
+template <int S>
+struct Dft<4, S> {
+  __device__ __forceinline__ static void run(float2 *x) {
+    float2 a0 = cadd(x[0], x[2]), a1 = csub(x[0], x[2]);
+    float2 b0 = cadd(x[1], x[3]), b1 = mul_isig<S>(csub(x[1], x[3]));
+    x[0] = cadd(a0, b0);
+    x[2] = csub(a0, b0);
+    x[1] = cadd(a1, b1);
+    x[3] = csub(a1, b1);
+  }
+};
+
+template <int S>
+struct Dft<5, S> {
+  __device__ __forceinline__ static void run(float2 *x) {
+    const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+    const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
+    float2 a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]);
+    float2 a2 = cadd(x[2], x[3]), b2 = csub(x[2], x[3]);
+    float2 x0 = x[0];
+    float2 r1 = make_float2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+    float2 r2 = make_float2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+    float2 i1 = mul_isig<S>(make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+    float2 i2 = mul_isig<S>(make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+    x[0] = cadd(x0, cadd(a1, a2));
+    x[1] = cadd(r1, i1);
+    x[4] = csub(r1, i1);
+    x[2] = cadd(r2, i2);
+    x[3] = csub(r2, i2);
+  }
+};
+
+template <int S>
+struct Dft<8, S> {
+  __device__ __forceinline__ static void run(float2 *x) {
+    const float r = 0.70710678118654752440f;
+    float2 e[4] = {x[0], x[2], x[4], x[6]};
+    float2 o[4] = {x[1], x[3], x[5], x[7]};
+    Dft<4, S>::run(e);
+    Dft<4, S>::run(o);
+    // w8^k = exp(S 2 pi i k / 8)
+    float2 t1 = cscale(make_float2(o[1].x - S * o[1].y, o[1].y + S * o[1].x), r);   // (1 + iS)/sqrt2
+    float2 t2 = mul_isig<S>(o[2]);
+    float2 t3 = cscale(make_float2(-o[3].x - S * o[3].y, -o[3].y + S * o[3].x), r); // (-1 + iS)/sqrt2
+    x[0] = cadd(e[0], o[0]);
+    x[4] = csub(e[0], o[0]);
+    x[1] = cadd(e[1], t1);
+    x[5] = csub(e[1], t1);
+    x[2] = cadd(e[2], t2);
+    x[6] = csub(e[2], t2);
+    x[3] = cadd(e[3], t3);
+    x[7] = csub(e[3], t3);
+  }
+};
+
+// One Stockham stage over `nlines` independent lines of length n stored in
+// LDS as buf[idx * ld + line].  Butterfly j of a line reads x[j + r n/R],
+// twiddles by exp(S 2 pi i r k / (ns R)) with k = j mod ns, and writes
+// y[(j / ns) ns R + k + u ns]: the output of the last stage is in natural
+// order.  Results are held in registers across a barrier, so the stage is
+// in place.  Each thread owns at most MAXE elements.
+template <int R, int S, int MAXE>
+__device__ __forceinline__ void fft_stage(float2 *buf, int n, int ns, int nl_log2, int ld,
+                                          const float2 *tw, int tid) {
+  constexpr int MAXB = (MAXE + R - 1) / R;
+  const int nb = n / R;
+  const int total = nb << nl_log2;
+  const int twstep = n / (ns * R);
+  float2 v[MAXB][R];
+  int oidx[MAXB];
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int b = tid + i * PSWF_THREADS;
+    oidx[i] = -1;
+    if (b < total) {
+      const int line = b & ((1 << nl_log2) - 1);
+      const int j = b >> nl_log2;
+      const int jq = j / ns;
+      const int k = j - jq * ns;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * nb) * ld + line];
+      if (ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[r * k * twstep];
+          if (S > 0) w.y = -w.y;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      Dft<R, S>::run(v[i]);
+      oidx[i] = (jq * ns * R + k) * ld + line;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    if (oidx[i] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[oidx[i] + r * ns * ld] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform of all lines in LDS.  S = -1 forward, +1 inverse
+// (unnormalised in both directions).  tw[m] = exp(-2 pi i m / n).
+template <int S, int MAXE>
+__device__ void lds_fft(float2 *buf, const FftAxis &ax, int nl_log2, int ld, const float2 *tw,
+                        int tid) {
+  int ns = 1;
+  for (int s = 0; s < ax.nst; ++s) {
+    const int R = ax.rad[s];
+    switch (R) {
+      case 2: fft_stage<2, S, MAXE>(buf, ax.n, ns, nl_log2, ld, tw, tid); break;
+      case 3: fft_stage<3, S, MAXE>(buf, ax.n, ns, nl_log2, ld, tw, tid); break;
+      case 4: fft_stage<4, S, MAXE>(buf, ax.n, ns, nl_log2, ld, tw, tid); break;
+      case 5: fft_stage<5, S, MAXE>(buf, ax.n, ns, nl_log2, ld, tw, tid); break;
+      default: fft_stage<8, S, MAXE>(buf, ax.n, ns, nl_log2, ld, tw, tid); break;
+    }
+    ns *= R;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Window psi_s(t), t in [-1, 1): piecewise polynomial in |t| (even function).
+__device__ __forceinline__ float win_eval(const float *wc, float t) {
+  float a = fabsf(t);
+  float y = a * kWinSeg;
+  int s = min(int(y), kWinSeg - 1);
+  float tau = 2.0f * (y - s) - 1.0f;
+  const float *c = wc + s * (kWinDeg + 1);
+  float r = c[kWinDeg];
+#pragma unroll
+  for (int d = kWinDeg - 1; d >= 0; --d) r = fmaf(r, tau, c[d]);
+  return r;
+}
+// value and d/dt
+__device__ __forceinline__ float2 win_eval_d(const float *wc, float t) {
+  float a = fabsf(t);
+  float y = a * kWinSeg;
+  int s = min(int(y), kWinSeg - 1);
+  float tau = 2.0f * (y - s) - 1.0f;
+  const float *c = wc + s * (kWinDeg + 1);
+  float r = c[kWinDeg], dr = 0.0f;
+#pragma unroll
+  for (int d = kWinDeg - 1; d >= 0; --d) {
+    dr = fmaf(dr, tau, r);
+    r = fmaf(r, tau, c[d]);
+  }
+  float dv = dr * (2.0f * kWinSeg);
+  return make_float2(r, t < 0.0f ? -dv : dv);
+}
+
+__device__ __forceinline__ int unpack_n0(unsigned v, int a) { return int((v >> (10 * a)) & 1023u); }
+
+// ---------------------------------------------------------------------------
+// Binning: each atom is assigned to the tile holding the first node of its
+// window, n0 = ceil(x/h - P/2) (mod M); delta = n0 - (x/h - P/2) in [0, 1).
+__global__ __launch_bounds__(PSWF_THREADS) void k_zero_int(int *p, int n) {
+  int i = blockIdx.x * PSWF_THREADS + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ __launch_bounds__(PSWF_THREADS) void k_bin(Geo g, Work w, const float *__restrict__ pos) {
+  const int64_t i = int64_t(blockIdx.x) * PSWF_THREADS + threadIdx.x;
+  if (i >= g.N) return;
+  unsigned packed = 0;
+  float dl[3];
+  int cell[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double x = double(pos[3 * i + a]);
+    if (!isfinite(x)) x = 0.0;
+    const double L = g.L[a];
+    x -= L * floor(x / L);
+    if (x >= L || x < 0.0) x = 0.0;
+    const double s = x * g.Minv_L[a] - 0.5 * g.P;
+    double n0d = ceil(s);
+    float delta = float(n0d - s);
+    if (delta >= 1.0f) delta = 0.99999994f;
+    int n0 = int(n0d) % g.M[a];
+    if (n0 < 0) n0 += g.M[a];
+    dl[a] = delta;
+    packed |= unsigned(n0) << (10 * a);
+    cell[a] = n0 / g.B[a];
+  }
+  const int c = (cell[0] * g.nc[1] + cell[1]) * g.nc[2] + cell[2];
+  w.cell_of[i] = c;
+  w.slot[i] = atomicAdd(&w.cell_count[c], 1);
+  float4 r = make_float4(dl[0], dl[1], dl[2], __uint_as_float(packed));
+  reinterpret_cast<float4 *>(w.rec_a)[i] = r;  // staged in caller order
+}
+
+// exclusive scan of cell counts (single block)
+__global__ __launch_bounds__(1024) void k_scan(Work w, int ncell, int64_t N) {
+  __shared__ int part[1024];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < ncell; base += 1024) {
+    int i = base + threadIdx.x;
+    int v = i < ncell ? w.cell_count[i] : 0;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      int t = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+      __syncthreads();
+      part[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < ncell) w.cell_start[i] = carry + part[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += part[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) w.cell_start[ncell] = int(N);
+}
+
+// scatter into cell order (arbitrary order inside a cell)
+__global__ __launch_bounds__(PSWF_THREADS) void k_scatter(Geo g, Work w, const float *__restrict__ q) {
+  const int64_t i = int64_t(blockIdx.x) * PSWF_THREADS + threadIdx.x;
+  if (i >= g.N) return;
+  const int dst = w.cell_start[w.cell_of[i]] + w.slot[i];
+  reinterpret_cast<float4 *>(w.rec_b)[dst] = reinterpret_cast<const float4 *>(w.rec_a)[i];
+  w.perm_b[dst] = int(i);
+  for (int c = 0; c < g.C; ++c) w.q_b[int64_t(c) * g.N + dst] = q[int64_t(c) * g.N + i];
+}
+
+// deterministic order inside each cell: ascending caller index
+__global__ __launch_bounds__(PSWF_THREADS) void k_order(Geo g, Work w) {
+  __shared__ int keys[2048];
+  const int cell = blockIdx.x;
+  const int s = w.cell_start[cell], e = w.cell_start[cell + 1];
+  const int n = e - s;
+  if (n <= 0) return;
+  const bool in_lds = n <= 2048;
+  if (in_lds) {
+    for (int k = threadIdx.x; k < n; k += PSWF_THREADS) keys[k] = w.perm_b[s + k];
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < n; k += PSWF_THREADS) {
+    const int key = in_lds ? keys[k] : w.perm_b[s + k];
+    int rank = 0;
+    for (int m = 0; m < n; ++m) rank += (in_lds ? keys[m] : w.perm_b[s + m]) < key;
+    const int dst = s + rank;
+    reinterpret_cast<float4 *>(w.rec_a)[dst] = reinterpret_cast<const float4 *>(w.rec_b)[s + k];
+    w.perm_a[dst] = key;
+    for (int c = 0; c < g.C; ++c) w.q_a[int64_t(c) * g.N + dst] = w.q_b[int64_t(c) * g.N + s + k];
+  }
+}
+
+// per-channel sum q and sum q^2 (FP64 block partials, fixed order)
+__global__ __launch_bounds__(PSWF_THREADS) void k_qsum(Geo g, Work w, const float *__restrict__ q,
+                                                        int chunk) {
+  __shared__ double s0[PSWF_THREADS], s1[PSWF_THREADS];
+  const int c = blockIdx.y;
+  const int64_t b0 = int64_t(blockIdx.x) * chunk;
+  double a = 0.0, b = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < min(b0 + chunk, g.N); i += PSWF_THREADS) {
+    double v = double(q[int64_t(c) * g.N + i]);
+    a += v;
+    b += v * v;
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int off = PSWF_THREADS / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      s0[threadIdx.x] += s0[threadIdx.x + off];
+      s1[threadIdx.x] += s1[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    w.qpart[(int64_t(blockIdx.x) * g.C + c) * 2 + 0] = s0[0];
+    w.qpart[(int64_t(blockIdx.x) * g.C + c) * 2 + 1] = s1[0];
+  }
+}
+
+__global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nblk) {
+  __shared__ double s0[PSWF_THREADS], s1[PSWF_THREADS];
+  for (int c = 0; c < g.C; ++c) {
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += PSWF_THREADS) {
+      a += w.qpart[(int64_t(k) * g.C + c) * 2 + 0];
+      b += w.qpart[(int64_t(k) * g.C + c) * 2 + 1];
+    }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = b;
+    __syncthreads();
+    for (int off = PSWF_THREADS / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) {
+        s0[threadIdx.x] += s0[threadIdx.x + off];
+        s1[threadIdx.x] += s1[threadIdx.x + off];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      w.qsum[2 * c] = s0[0];
+      w.qsum[2 * c + 1] = s1[0];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Spread (step i): one workgroup per tile and channel group.  Candidate atoms
+// (windows touching the tile) are staged in LDS with their 3 P window
+// weights; wave w owns tile planes x = w, w + 4, ... so every grid value is
+// accumulated by exactly one wave, in candidate order: no atomics, and the
+// result is bitwise reproducible.
+constexpr int kSpreadChunk = PSWF_THREADS;
+constexpr int kSpreadCGMax = 4;
+
+template <int P>
+__global__ __launch_bounds__(PSWF_THREADS) void k_spread(Geo g, Tables t, Work w, int cg0, int ncg) {
+  extern __shared__ float smem[];
+  const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
+  const int SZ = Bz + 1;                 // padded z stride
+  const int plane = By * SZ;
+  float *tile = smem;                                  // [ncg][Bx][By][SZ]
+  float *wcf = tile + ncg * Bx * plane;                // window coefficients
+  int *cd = reinterpret_cast<int *>(wcf + kWinSeg * (kWinDeg + 1));   // [3][chunk]
+  float *cw = reinterpret_cast<float *>(cd + 3 * kSpreadChunk);       // [chunk][3][P]
+  float *cq = cw + kSpreadChunk * 3 * P;                               // [chunk][CGMax]
+  __shared__ int wcount[PSWF_THREADS / 64];
+  __shared__ int ncand_s;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cell = blockIdx.x;
+  const int cz = cell % g.nc[2], cy = (cell / g.nc[2]) % g.nc[1], cx = cell / (g.nc[2] * g.nc[1]);
+  const int t0[3] = {cx * Bx, cy * By, cz * Bz};
+  const int ctile[3] = {cx, cy, cz};
+
+  for (int e = tid; e < ncg * Bx * plane; e += PSWF_THREADS) tile[e] = 0.0f;
+  for (int e = tid; e < kWinSeg * (kWinDeg + 1); e += PSWF_THREADS) wcf[e] = t.win[e];
+
+  // candidate cells: this tile's cell and the previous one along each axis
+  int clist[3][2], ccount[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    clist[a][0] = ctile[a];
+    ccount[a] = 1;
+    if (g.nc[a] > 1) {
+      clist[a][1] = (ctile[a] + g.nc[a] - 1) % g.nc[a];
+      ccount[a] = 2;
+    }
+  }
+  __syncthreads();
+
+  for (int ix = 0; ix < ccount[0]; ++ix)
+    for (int iy = 0; iy < ccount[1]; ++iy)
+      for (int iz = 0; iz < ccount[2]; ++iz) {
+        const int cc = (clist[0][ix] * g.nc[1] + clist[1][iy]) * g.nc[2] + clist[2][iz];
+        const int s = w.cell_start[cc], e = w.cell_start[cc + 1];
+        for (int base = s; base < e; base += kSpreadChunk) {
+          const int i = base + tid;
+          bool ok = false;
+          float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+          int d[3] = {0, 0, 0};
+          if (i < e) {
+            r = reinterpret_cast<const float4 *>(w.rec_a)[i];
+            const unsigned pk = __float_as_uint(r.w);
+            ok = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              int dd = unpack_n0(pk, a) - t0[a];
+              if (dd < 0) dd += g.M[a];
+              d[a] = dd;
+              ok = ok && (dd < g.B[a] || dd > g.M[a] - P);
+            }
+          }
+          const unsigned long long m = __ballot(ok);
+          if (lane == 0) wcount[wave] = __popcll(m);
+          __syncthreads();
+          int off = 0;
+          for (int k = 0; k < wave; ++k) off += wcount[k];
+          if (tid == 0) {
+            int tot = 0;
+            for (int k = 0; k < PSWF_THREADS / 64; ++k) tot += wcount[k];
+            ncand_s = tot;
+          }
+          if (ok) {
+            const int slot = off + __popcll(m & ((1ull << lane) - 1ull));
+            const float dl[3] = {r.x, r.y, r.z};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              cd[a * kSpreadChunk + slot] = d[a];
+#pragma unroll
+              for (int l = 0; l < P; ++l)
+                cw[(slot * 3 + a) * P + l] = win_eval(wcf, (2.0f * (l + dl[a])) / P - 1.0f);
+            }
+            for (int c = 0; c < ncg; ++c) cq[slot * kSpreadCGMax + c] = w.q_a[int64_t(cg0 + c) * g.N + i];
+          }
+          __syncthreads();
+          const int ncand = ncand_s;
+          for (int k = 0; k < ncand; ++k) {
+            const int dx = cd[k], dy = cd[kSpreadChunk + k], dz = cd[2 * kSpreadChunk + k];
+            const float *wk = cw + k * 3 * P;
+            float qk[kSpreadCGMax];
+#pragma unroll
+            for (int c = 0; c < kSpreadCGMax; ++c) qk[c] = c < ncg ? cq[k * kSpreadCGMax + c] : 0.0f;
+            for (int xt = wave; xt < Bx; xt += PSWF_THREADS / 64) {
+              int lx = xt - dx;
+              if (lx < 0) lx += g.M[0];
+              if (lx >= P) continue;
+              const float wxv = wk[lx];
+              for (int l = lane; l < P * P; l += 64) {
+                const int ly = l / P, lz = l - ly * P;
+                int y = dy + ly;
+                if (y >= g.M[1]) y -= g.M[1];
+                int z = dz + lz;
+                if (z >= g.M[2]) z -= g.M[2];
+                if (y < By && z < Bz) {
+                  const float wv = wxv * wk[P + ly] * wk[2 * P + lz];
+                  float *dst = tile + xt * plane + y * SZ + z;
+#pragma unroll
+                  for (int c = 0; c < kSpreadCGMax; ++c)
+                    if (c < ncg) dst[c * Bx * plane] += wv * qk[c];
+                }
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+
+  // write the tile (every grid value belongs to exactly one tile)
+  const int nt = Bx * By * Bz;
+  for (int e = tid; e < ncg * nt; e += PSWF_THREADS) {
+    const int c = e / nt, r0 = e - c * nt;
+    const int x = r0 / (By * Bz), r1 = r0 - x * By * Bz, y = r1 / Bz, z = r1 - y * Bz;
+    w.grid[((int64_t(cg0 + c) * g.M[0] + t0[0] + x) * g.M[1] + t0[1] + y) * g.M[2] + t0[2] + z] =
+        tile[c * Bx * plane + x * plane + y * SZ + z];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z R2C (step ii, first axis): lines of M_z reals -> KZ complex columns.
+// The real line is packed as z_n = x_2n + i x_2n+1, transformed with length
+// Nz = M_z / 2 and split: X_k = E_k + exp(-2 pi i k / M_z) O_k.
+__global__ __launch_bounds__(PSWF_THREADS) void k_zfwd(Geo g, Tables t, FftAxis ax, Work w,
+                                                        int64_t nlines_total) {
+  extern __shared__ float smem[];
+  const int L = g.zlines, ld = L + 1, Nz = g.Nz;
+  int llog = 0;
+  while ((1 << llog) < L) ++llog;
+  float2 *buf = reinterpret_cast<float2 *>(smem);
+  float2 *tw = buf + Nz * ld;
+  float2 *twr = tw + Nz;
+  const int tid = threadIdx.x;
+  const int64_t line0 = int64_t(blockIdx.x) * L;
+  const int nl = int(min(int64_t(L), nlines_total - line0));
+  for (int e = tid; e < Nz; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_z)[e];
+  for (int e = tid; e <= Nz; e += PSWF_THREADS) twr[e] = reinterpret_cast<const float2 *>(t.tw_zr)[e];
+  const float2 *src = reinterpret_cast<const float2 *>(w.grid) + line0 * Nz;
+  for (int e = tid; e < L * Nz; e += PSWF_THREADS) {
+    const int line = e / Nz, n = e - line * Nz;
+    buf[n * ld + line] = line < nl ? src[e] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft<-1, 16>(buf, ax, llog, ld, tw, tid);
+  float2 *dst = reinterpret_cast<float2 *>(w.s1) + line0 * g.KZ;
+  for (int e = tid; e < nl * g.KZ; e += PSWF_THREADS) {
+    const int line = e / g.KZ, k = e - line * g.KZ;
+    const float2 zk = buf[(k == Nz ? 0 : k) * ld + line];
+    const int km = (Nz - k) % Nz;
+    const float2 zc = buf[(km < 0 ? km + Nz : km) * ld + line];
+    // E = (Z_k + conj Z_{N-k}) / 2, O = (Z_k - conj Z_{N-k}) / (2i)
+    const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
+    const float2 O = make_float2(0.5f * (zk.y + zc.y), -0.5f * (zk.x - zc.x));
+    dst[e] = cadd(E, cmul(twr[k], O));
+  }
+}
+
+// y forward (step ii, second axis): plane (c, x), a block of kb z columns;
+// keeps only |f_y| <= FY.
+__global__ __launch_bounds__(PSWF_THREADS) void k_yfwd(Geo g, Tables t, FftAxis ax, Work w) {
+  extern __shared__ float smem[];
+  const int kb = g.kb, ld = kb + 1, My = g.M[1];
+  float2 *buf = reinterpret_cast<float2 *>(smem);
+  float2 *tw = buf + My * ld;
+  const int tid = threadIdx.x;
+  const int kz0 = blockIdx.x * kb;
+  const int64_t plane = blockIdx.y;  // c * Mx + x
+  const int ncol = min(kb, g.KZ - kz0);
+  for (int e = tid; e < My; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_y)[e];
+  const float2 *src = reinterpret_cast<const float2 *>(w.s1) + plane * My * g.KZ;
+  for (int e = tid; e < My * kb; e += PSWF_THREADS) {
+    const int y = e >> g.kb_log2, col = e & (kb - 1);
+    buf[y * ld + col] = col < ncol ? src[int64_t(y) * g.KZ + kz0 + col] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft<-1, 16>(buf, ax, g.kb_log2, ld, tw, tid);
+  float2 *dst = reinterpret_cast<float2 *>(w.s2) + plane * g.NY * g.KZ;
+  for (int e = tid; e < g.NY * kb; e += PSWF_THREADS) {
+    const int iy = e >> g.kb_log2, col = e & (kb - 1);
+    if (col >= ncol) continue;
+    const int my = iy <= g.FY ? iy : My - g.NY + iy;
+    dst[int64_t(iy) * g.KZ + kz0 + col] = buf[my * ld + col];
+  }
+}
+
+// Fourier kernel at kappa: (Phi, Phi'/k) from the per-channel polynomials.
+__device__ __forceinline__ float kpow(float kap, float inv, int e) {
+  float r = 1.0f;
+  if (e >= 0) {
+    for (int i = 0; i < e; ++i) r *= kap;
+  } else {
+    for (int i = 0; i < -e; ++i) r *= inv;
+  }
+  return r;
+}
+__device__ __forceinline__ float2 kernel_eval(const float *fc, const float *gc, const KChan &kc, float kap) {
+  float y = kap * kKerSeg;
+  int s = min(int(y), kKerSeg - 1);
+  float tau = 2.0f * (y - s) - 1.0f;
+  const float *a = fc + s * (kKerDeg + 1);
+  const float *b = gc + s * (kKerDeg + 1);
+  float fv = a[kKerDeg], gv = b[kKerDeg];
+#pragma unroll
+  for (int d = kKerDeg - 1; d >= 0; --d) {
+    fv = fmaf(fv, tau, a[d]);
+    gv = fmaf(gv, tau, b[d]);
+  }
+  const float inv = 1.0f / kap;
+  float phi = kc.A * kpow(kap, inv, kc.eA) * fv;
+  float dph = kc.Cc * kpow(kap, inv, kc.eC) * gv;
+  if (kc.B != 0.0f || kc.D != 0.0f) {
+    const float lg = logf(kap);
+    phi += kc.B * kpow(kap, inv, kc.eB) * lg;
+    dph += kc.D * kpow(kap, inv, kc.eD) * lg;
+  }
+  return make_float2(phi, dph);
+}
+
+// Fused x pass (steps ii-iv and the first inverse axis): x transform of one
+// block of (f_y, k_z) columns, diagonal scaling by Phi_p h^6 / What^2 / V,
+// FP64 block partials of the energy and virial, inverse x transform.
+// mode 0: energy only (no write-back), 1: full, 2: adjoint with the scale
+// grad[c] folded into the kernel.
+__global__ __launch_bounds__(PSWF_THREADS) void k_xmul(Geo g, Tables t, FftAxis ax, Work w, int mode,
+                                                        const double *__restrict__ grad) {
+  extern __shared__ float smem[];
+  const int kb = g.kb, ld = kb + 1, Mx = g.M[0];
+  float2 *buf = reinterpret_cast<float2 *>(smem);
+  float2 *tw = buf + Mx * ld;
+  float *fc = reinterpret_cast<float *>(tw + Mx);
+  float *gc = fc + kKerCoef;
+  __shared__ double red[7][PSWF_THREADS / 64];
+  const int tid = threadIdx.x;
+  const int blk = blockIdx.x, c = blockIdx.y;
+  const int iy = t.xblk[4 * blk], kz0 = t.xblk[4 * blk + 1], ncol = t.xblk[4 * blk + 2];
+  const KChan kc = t.kch[c];
+  for (int e = tid; e < Mx; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_x)[e];
+  for (int e = tid; e < kKerCoef; e += PSWF_THREADS) {
+    fc[e] = t.kf[c * kKerCoef + e];
+    gc[e] = t.kg[c * kKerCoef + e];
+  }
+  const int64_t xstride = int64_t(g.NY) * g.KZ;
+  float2 *col0 = reinterpret_cast<float2 *>(w.s2) + int64_t(c) * Mx * xstride + int64_t(iy) * g.KZ + kz0;
+  for (int e = tid; e < Mx * kb; e += PSWF_THREADS) {
+    const int x = e >> g.kb_log2, col = e & (kb - 1);
+    buf[x * ld + col] = col < ncol ? col0[x * xstride + col] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft<-1, 16>(buf, ax, g.kb_log2, ld, tw, tid);
+
+  const int fy = iy <= g.FY ? iy : iy - g.NY;
+  const float ky = fy * g.kunit[1];
+  const float dy = t.Dy[iy];
+  const float scale = (mode == 2 ? float(grad[c]) : 1.0f) * g.invV;
+  float acc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int e = tid; e < Mx * kb; e += PSWF_THREADS) {
+    const int mx = e >> g.kb_log2, col = e & (kb - 1);
+    const int kz = kz0 + col;
+    const int fx = mx <= Mx / 2 ? mx : mx - Mx;
+    const float kx = fx * g.kunit[0], kzv = kz * g.kunit[2];
+    const float k2 = kx * kx + ky * ky + kzv * kzv;
+    float2 v = buf[mx * ld + col];
+    float mult = 0.0f;
+    if (col < ncol && k2 > 0.0f && k2 <= g.kc2 && 2 * abs(fx) != Mx) {
+      const float k = sqrtf(k2);
+      const float2 ph = kernel_eval(fc, gc, kc, k * g.kinv);
+      const float D = t.Dx[mx] * dy * t.Dz[kz];
+      const float wz = (kz == 0) ? 1.0f : 2.0f;
+      const float s2 = (v.x * v.x + v.y * v.y) * D * wz;
+      acc[0] += ph.x * s2;
+      const float vd = ph.y * s2;
+      acc[1] += vd * kx * kx;
+      acc[2] += vd * ky * ky;
+      acc[3] += vd * kzv * kzv;
+      acc[4] += vd * kx * ky;
+      acc[5] += vd * kx * kzv;
+      acc[6] += vd * ky * kzv;
+      mult = ph.x * D * scale;
+    }
+    buf[mx * ld + col] = cscale(v, mult);
+  }
+  // block reduction in FP64, fixed order
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    double v = double(acc[i]);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[i][wave] = v;
+  }
+  __syncthreads();
+  if (tid < 7) {
+    double s = 0.0;
+    for (int k = 0; k < PSWF_THREADS / 64; ++k) s += red[tid][k];
+    w.epart[(int64_t(c) * g.nxblk + blk) * 8 + tid] = s;
+  }
+  if (mode == 0) return;
+  lds_fft<1, 16>(buf, ax, g.kb_log2, ld, tw, tid);
+  for (int e = tid; e < Mx * kb; e += PSWF_THREADS) {
+    const int x = e >> g.kb_log2, col = e & (kb - 1);
+    if (col < ncol) col0[x * xstride + col] = buf[x * ld + col];
+  }
+}
+
+// inverse y: kept rows (zero elsewhere and for columns the x pass skipped)
+__global__ __launch_bounds__(PSWF_THREADS) void k_yinv(Geo g, Tables t, FftAxis ax, Work w) {
+  extern __shared__ float smem[];
+  const int kb = g.kb, ld = kb + 1, My = g.M[1];
+  float2 *buf = reinterpret_cast<float2 *>(smem);
+  float2 *tw = buf + My * ld;
+  const int tid = threadIdx.x;
+  const int kz0 = blockIdx.x * kb;
+  const int64_t plane = blockIdx.y;
+  const int ncol = min(kb, g.KZ - kz0);
+  for (int e = tid; e < My; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_y)[e];
+  for (int e = tid; e < My * ld; e += PSWF_THREADS) buf[e] = make_float2(0.f, 0.f);
+  __syncthreads();
+  const float2 *src = reinterpret_cast<const float2 *>(w.s2) + plane * g.NY * g.KZ;
+  for (int e = tid; e < g.NY * kb; e += PSWF_THREADS) {
+    const int iy = e >> g.kb_log2, col = e & (kb - 1);
+    const int kz = kz0 + col;
+    if (col >= ncol || kz >= t.blim[iy]) continue;
+    const int my = iy <= g.FY ? iy : My - g.NY + iy;
+    buf[my * ld + col] = src[int64_t(iy) * g.KZ + kz];
+  }
+  __syncthreads();
+  lds_fft<1, 16>(buf, ax, g.kb_log2, ld, tw, tid);
+  float2 *dst = reinterpret_cast<float2 *>(w.s1) + plane * My * g.KZ;
+  for (int e = tid; e < My * kb; e += PSWF_THREADS) {
+    const int y = e >> g.kb_log2, col = e & (kb - 1);
+    if (col < ncol) dst[int64_t(y) * g.KZ + kz0 + col] = buf[y * ld + col];
+  }
+}
+
+// z C2R: Z'_k = (X_k + conj X_{N-k}) + i exp(+2 pi i k / M_z)(X_k - conj X_{N-k}),
+// inverse transform of length Nz gives x_2m + i x_2m+1.
+__global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis ax, Work w,
+                                                        int64_t nlines_total) {
+  extern __shared__ float smem[];
+  const int L = g.zlines, ld = L + 1, Nz = g.Nz;
+  int llog = 0;
+  while ((1 << llog) < L) ++llog;
+  float2 *buf = reinterpret_cast<float2 *>(smem);
+  float2 *tw = buf + Nz * ld;
+  float2 *twr = tw + Nz;
+  const int tid = threadIdx.x;
+  const int64_t line0 = int64_t(blockIdx.x) * L;
+  const int nl = int(min(int64_t(L), nlines_total - line0));
+  for (int e = tid; e < Nz; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_z)[e];
+  for (int e = tid; e <= Nz; e += PSWF_THREADS) twr[e] = reinterpret_cast<const float2 *>(t.tw_zr)[e];
+  __syncthreads();
+  const float2 *src = reinterpret_cast<const float2 *>(w.s1) + line0 * g.KZ;
+  for (int e = tid; e < L * Nz; e += PSWF_THREADS) {
+    const int line = e / Nz, k = e - line * Nz;
+    float2 z = make_float2(0.f, 0.f);
+    if (line < nl) {
+      const float2 xk = k < g.KZ ? src[int64_t(line) * g.KZ + k] : make_float2(0.f, 0.f);
+      const int km = Nz - k;  // 1..Nz
+      const float2 xm = km < g.KZ ? src[int64_t(line) * g.KZ + km] : make_float2(0.f, 0.f);
+      const float2 a = make_float2(xk.x + xm.x, xk.y - xm.y);    // X_k + conj X_{N-k}
+      const float2 b = make_float2(xk.x - xm.x, xk.y + xm.y);    // X_k - conj X_{N-k}
+      float2 wv = twr[k];
+      wv.y = -wv.y;                                              // exp(+2 pi i k / M_z)
+      const float2 ib = cmul(wv, b);
+      z = make_float2(a.x - ib.y, a.y + ib.x);
+    }
+    buf[k * ld + line] = z;
+  }
+  __syncthreads();
+  lds_fft<1, 16>(buf, ax, llog, ld, tw, tid);
+  float2 *dst = reinterpret_cast<float2 *>(w.grid) + line0 * Nz;
+  for (int e = tid; e < nl * Nz; e += PSWF_THREADS) {
+    const int line = e / Nz, n = e - line * Nz;
+    dst[e] = buf[n * ld + line];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gather (adjoint of step i): one workgroup per tile; the tile's grid region
+// plus a P-1 halo is staged in LDS per channel group.  Eight lanes serve one
+// atom (lane = window z offset), summing the (x, y) plane with the
+// separable weights and their derivatives, then reducing over z.
+//   phi_i   = sum_n pg(n) W(n h - r_i)
+//   F_i     = q_i sum_n pg(n) grad W(n h - r_i)
+// mode 1: forces/potentials; mode 2: adjoint (grad_q = g phi, grad_r = -g F).
+template <int P>
+__global__ __launch_bounds__(PSWF_THREADS) void k_gather(Geo g, Tables t, Work w, float *__restrict__ fout,
+                                                          float *__restrict__ pout, int mode,
+                                                          const double *__restrict__ grad) {
+  extern __shared__ float smem[];
+  const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
+  const int EX = Bx + P - 1, EY = By + P - 1, EZ = Bz + P - 1;
+  const int SZ = EZ + 1;
+  const int plane = EY * SZ, chan = EX * plane;
+  float *tile = smem;
+  float *wcf = tile + g.CG_gather * chan;
+  const int tid = threadIdx.x;
+  const int cell = blockIdx.x;
+  const int s = w.cell_start[cell], e = w.cell_start[cell + 1];
+  if (s == e) return;
+  const int cz = cell % g.nc[2], cy = (cell / g.nc[2]) % g.nc[1], cx = cell / (g.nc[2] * g.nc[1]);
+  const int t0[3] = {cx * Bx, cy * By, cz * Bz};
+  for (int k = tid; k < kWinSeg * (kWinDeg + 1); k += PSWF_THREADS) wcf[k] = t.win[k];
+  const int lz = tid & 7;
+  const int nchunks = (e - s + 31) / 32;
+
+  for (int cg0 = 0; cg0 < g.C; cg0 += g.CG_gather) {
+    const int ncg = min(g.CG_gather, g.C - cg0);
+    __syncthreads();
+    for (int k = tid; k < ncg * EX * EY * EZ; k += PSWF_THREADS) {
+      const int c = k / (EX * EY * EZ);
+      int r = k - c * EX * EY * EZ;
+      const int x = r / (EY * EZ);
+      r -= x * EY * EZ;
+      const int y = r / EZ, z = r - y * EZ;
+      int gx = t0[0] + x, gy = t0[1] + y, gz = t0[2] + z;
+      if (gx >= g.M[0]) gx -= g.M[0];
+      if (gy >= g.M[1]) gy -= g.M[1];
+      if (gz >= g.M[2]) gz -= g.M[2];
+      tile[c * chan + x * plane + y * SZ + z] =
+          w.grid[((int64_t(cg0 + c) * g.M[0] + gx) * g.M[1] + gy) * g.M[2] + gz];
+    }
+    __syncthreads();
+    const bool last = cg0 + ncg >= g.C;
+    for (int ch = 0; ch < nchunks; ++ch) {
+      const int a = s + ch * 32 + (tid >> 3);
+      const bool active = a < e;
+      float wx[P], dwx[P], wy[P], dwy[P];
+      float wz = 0.f, dwz = 0.f;
+      int ox = 0, oy = 0, oz = 0;
+      if (active) {
+        const float4 r = reinterpret_cast<const float4 *>(w.rec_a)[a];
+        const unsigned pk = __float_as_uint(r.w);
+        ox = unpack_n0(pk, 0) - t0[0];
+        oy = unpack_n0(pk, 1) - t0[1];
+        oz = unpack_n0(pk, 2) - t0[2];
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+          float2 vx = win_eval_d(wcf, (2.0f * (l + r.x)) / P - 1.0f);
+          float2 vy = win_eval_d(wcf, (2.0f * (l + r.y)) / P - 1.0f);
+          wx[l] = vx.x;
+          dwx[l] = vx.y * g.dwin[0];
+          wy[l] = vy.x;
+          dwy[l] = vy.y * g.dwin[1];
+        }
+        if (lz < P) {
+          float2 vz = win_eval_d(wcf, (2.0f * (lz + r.z)) / P - 1.0f);
+          wz = vz.x;
+          dwz = vz.y * g.dwin[2];
+        }
+      } else {
+#pragma unroll
+        for (int l = 0; l < P; ++l) wx[l] = dwx[l] = wy[l] = dwy[l] = 0.f;
+      }
+      float f[3] = {0.f, 0.f, 0.f};
+      for (int c = 0; c < ncg; ++c) {
+        float sp = 0.f, sx = 0.f, sy = 0.f;
+        if (active && lz < P) {
+          const float *base = tile + c * chan + ox * plane + oy * SZ + oz + lz;
+#pragma unroll
+          for (int lx = 0; lx < P; ++lx) {
+            float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+            for (int ly = 0; ly < P; ++ly) {
+              const float gv = base[lx * plane + ly * SZ];
+              a0 = fmaf(wy[ly], gv, a0);
+              a1 = fmaf(dwy[ly], gv, a1);
+            }
+            sp = fmaf(wx[lx], a0, sp);
+            sx = fmaf(dwx[lx], a0, sx);
+            sy = fmaf(wx[lx], a1, sy);
+          }
+        }
+        float vphi = wz * sp, vgx = wz * sx, vgy = wz * sy, vgz = dwz * sp;
+#pragma unroll
+        for (int off = 1; off < 8; off <<= 1) {
+          vphi += __shfl_xor(vphi, off, 8);
+          vgx += __shfl_xor(vgx, off, 8);
+          vgy += __shfl_xor(vgy, off, 8);
+          vgz += __shfl_xor(vgz, off, 8);
+        }
+        if (active && lz == 0) {
+          const int cc = cg0 + c;
+          const float qv = w.q_a[int64_t(cc) * g.N + a];
+          f[0] += qv * vgx;
+          f[1] += qv * vgy;
+          f[2] += qv * vgz;
+          if (pout) {
+            const double gsc = mode == 2 ? grad[cc] : 1.0;
+            // potential includes the zero-frequency term dE_0/dq = 2 a Q_net
+            const float zero = float(2.0 * t.zero_V[cc] / g.V * w.qsum[2 * cc] * gsc);
+            pout[int64_t(cc) * g.N + w.perm_a[a]] = vphi + zero;
+          }
+        }
+      }
+      if (active && lz == 0) {
+        if (cg0 > 0) {
+          f[0] += w.facc[3 * int64_t(a)];
+          f[1] += w.facc[3 * int64_t(a) + 1];
+          f[2] += w.facc[3 * int64_t(a) + 2];
+        }
+        if (!last) {
+          w.facc[3 * int64_t(a)] = f[0];
+          w.facc[3 * int64_t(a) + 1] = f[1];
+          w.facc[3 * int64_t(a) + 2] = f[2];
+        } else if (fout) {
+          const float sg = mode == 2 ? -1.0f : 1.0f;
+          const int64_t o = 3 * int64_t(w.perm_a[a]);
+          fout[o] = sg * f[0];
+          fout[o + 1] = sg * f[1];
+          fout[o + 2] = sg * f[2];
+        }
+      }
+    }
+  }
+}
+
+// Final FP64 reduction: energy [3C] (E_k, E_0, E_self) and virial [6].
+__global__ __launch_bounds__(PSWF_THREADS) void k_finalize(Geo g, Tables t, Work w, double *energy,
+                                                            double *virial) {
+  __shared__ double red[8][PSWF_THREADS];
+  __shared__ double vir[6];
+  const int tid = threadIdx.x;
+  if (tid < 6) vir[tid] = 0.0;
+  __syncthreads();
+  for (int c = 0; c < g.C; ++c) {
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int b = tid; b < g.nxblk; b += PSWF_THREADS)
+      for (int i = 0; i < 7; ++i) acc[i] += w.epart[(int64_t(c) * g.nxblk + b) * 8 + i];
+    for (int i = 0; i < 7; ++i) red[i][tid] = acc[i];
+    __syncthreads();
+    for (int off = PSWF_THREADS / 2; off > 0; off >>= 1) {
+      if (tid < off)
+        for (int i = 0; i < 7; ++i) red[i][tid] += red[i][tid + off];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double inv2V = 0.5 / g.V;
+      const double Ek = red[0][0] * inv2V;
+      const double Q = w.qsum[2 * c], Q2 = w.qsum[2 * c + 1];
+      const double E0 = t.zero_V[c] / g.V * Q * Q;
+      energy[3 * c] = Ek;
+      energy[3 * c + 1] = E0;
+      energy[3 * c + 2] = t.self_coef[c] * Q2;
+      // W_ab = (1/2V) sum |F|^2 D (Phi delta_ab + Phi'/k k_a k_b) + E_0 delta_ab
+      vir[0] += Ek + E0 + red[1][0] * inv2V;
+      vir[1] += Ek + E0 + red[2][0] * inv2V;
+      vir[2] += Ek + E0 + red[3][0] * inv2V;
+      vir[3] += red[4][0] * inv2V;
+      vir[4] += red[5][0] * inv2V;
+      vir[5] += red[6][0] * inv2V;
+    }
+    __syncthreads();
+  }
+  if (virial && tid < 6) virial[tid] = vir[tid];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+static inline unsigned nblocks(int64_t n, int per) { return unsigned((n + per - 1) / per); }
+
+#define LAUNCH_CHECK()                         \
+  do {                                         \
+    hipError_t e__ = hipGetLastError();        \
+    if (e__ != hipSuccess) return e__;         \
+  } while (0)
+
+size_t spread_lds_bytes(const Geo &g, int ncg) {
+  const size_t plane = size_t(g.B[1]) * (g.B[2] + 1);
+  return (size_t(ncg) * g.B[0] * plane + kWinSeg * (kWinDeg + 1)) * 4 + 3 * kSpreadChunk * 4 +
+         size_t(kSpreadChunk) * 3 * g.P * 4 + size_t(kSpreadChunk) * kSpreadCGMax * 4;
+}
+size_t gather_lds_bytes(const Geo &g, int ncg) {
+  const size_t EX = g.B[0] + g.P - 1, EY = g.B[1] + g.P - 1, EZ = g.B[2] + g.P - 1;
+  return (size_t(ncg) * EX * EY * (EZ + 1) + kWinSeg * (kWinDeg + 1)) * 4;
+}
+size_t zpass_lds_bytes(const Geo &g) { return (size_t(g.Nz) * (g.zlines + 1) + 2 * g.Nz + 1) * 8; }
+size_t ypass_lds_bytes(const Geo &g) { return (size_t(g.M[1]) * (g.kb + 1) + g.M[1]) * 8; }
+size_t xpass_lds_bytes(const Geo &g) {
+  return (size_t(g.M[0]) * (g.kb + 1) + g.M[0]) * 8 + 2 * kKerCoef * 4;
+}
+
+// Dynamic LDS above 64 KiB needs an opt-in per kernel; request it only when
+// a launch needs it, clamped to what the device allows, and clear the
+// runtime's error state if the request is refused.
+static size_t device_lds_optin() {
+  static size_t cached = 0;
+  if (cached) return cached;
+  int dev = 0, v = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || v <= 0) {
+    (void)hipGetLastError();
+    v = 64 * 1024;
+  }
+  cached = size_t(v);
+  return cached;
+}
+
+static hipError_t lds_request(const void *fn, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  if (bytes > device_lds_optin()) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+
+hipError_t enqueue_sort(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st) {
+  // cell offsets are produced even for N = 0 (the spread reads them)
+  hipLaunchKernelGGL(k_zero_int, dim3(nblocks(g.ncell, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st,
+                     w.cell_count, g.ncell);
+  LAUNCH_CHECK();
+  if (g.N > 0) {
+    hipLaunchKernelGGL(k_bin, dim3(nblocks(g.N, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, w, pos);
+    LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, w, g.ncell, g.N);
+  LAUNCH_CHECK();
+  if (g.N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3(nblocks(g.N, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, w, q);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_order, dim3(g.ncell), dim3(PSWF_THREADS), 0, st, g, w);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+int qsum_blocks(const Geo &g) { return int(std::max<int64_t>(1, (g.N + kQChunk - 1) / kQChunk)); }
+
+hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t st) {
+  const int nb = qsum_blocks(g);
+  hipLaunchKernelGGL(k_qsum, dim3(nb, g.C), dim3(PSWF_THREADS), 0, st, g, w, q, kQChunk);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_qreduce, dim3(1), dim3(PSWF_THREADS), 0, st, g, w, nb);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+template <int P>
+static hipError_t spread_p(const Geo &g, const Tables &t, const Work &w, hipStream_t st) {
+  for (int cg0 = 0; cg0 < g.C; cg0 += g.CG_spread) {
+    const int ncg = std::min(g.CG_spread, g.C - cg0);
+    hipError_t e = lds_request(reinterpret_cast<const void *>(&k_spread<P>), spread_lds_bytes(g, ncg));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_spread<P>, dim3(g.ncell), dim3(PSWF_THREADS), spread_lds_bytes(g, ncg), st, g, t,
+                       w, cg0, ncg);
+    LAUNCH_CHECK();
+  }
+  return hipSuccess;
+}
+
+hipError_t enqueue_spread(const Geo &g, const Tables &t, const Work &w, hipStream_t st) {
+  switch (g.P) {
+    case 2: return spread_p<2>(g, t, w, st);
+    case 3: return spread_p<3>(g, t, w, st);
+    case 4: return spread_p<4>(g, t, w, st);
+    case 5: return spread_p<5>(g, t, w, st);
+    case 6: return spread_p<6>(g, t, w, st);
+    case 7: return spread_p<7>(g, t, w, st);
+    case 8: return spread_p<8>(g, t, w, st);
+    case 9: return spread_p<9>(g, t, w, st);
+    case 10: return spread_p<10>(g, t, w, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t enqueue_forward_fft(const Geo &g, const Tables &t, const FftAxis &az, const FftAxis &ay,
+                               const Work &w, hipStream_t st) {
+  const int64_t lines = int64_t(g.C) * g.M[0] * g.M[1];
+  hipLaunchKernelGGL(k_zfwd, dim3(nblocks(lines, g.zlines)), dim3(PSWF_THREADS), zpass_lds_bytes(g), st, g, t,
+                     az, w, lines);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_yfwd, dim3(nblocks(g.KZ, g.kb), g.C * g.M[0]), dim3(PSWF_THREADS), ypass_lds_bytes(g),
+                     st, g, t, ay, w);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t enqueue_xmul(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int mode,
+                        const double *grad, hipStream_t st) {
+  if (g.nxblk == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_xmul, dim3(g.nxblk, g.C), dim3(PSWF_THREADS), xpass_lds_bytes(g), st, g, t, ax, w, mode,
+                     grad);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t enqueue_inverse_fft(const Geo &g, const Tables &t, const FftAxis &az, const FftAxis &ay,
+                               const Work &w, hipStream_t st) {
+  hipLaunchKernelGGL(k_yinv, dim3(nblocks(g.KZ, g.kb), g.C * g.M[0]), dim3(PSWF_THREADS), ypass_lds_bytes(g),
+                     st, g, t, ay, w);
+  LAUNCH_CHECK();
+  const int64_t lines = int64_t(g.C) * g.M[0] * g.M[1];
+  hipLaunchKernelGGL(k_zinv, dim3(nblocks(lines, g.zlines)), dim3(PSWF_THREADS), zpass_lds_bytes(g), st, g, t,
+                     az, w, lines);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+template <int P>
+static hipError_t gather_p(const Geo &g, const Tables &t, const Work &w, float *f, float *pot, int mode,
+                           const double *grad, hipStream_t st) {
+  hipError_t e = lds_request(reinterpret_cast<const void *>(&k_gather<P>), gather_lds_bytes(g, g.CG_gather));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gather<P>, dim3(g.ncell), dim3(PSWF_THREADS), gather_lds_bytes(g, g.CG_gather), st, g, t,
+                     w, f, pot, mode, grad);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t enqueue_gather(const Geo &g, const Tables &t, const Work &w, float *forces, float *pot, int mode,
+                          const double *grad, hipStream_t st) {
+  if (g.N == 0) return hipSuccess;
+  switch (g.P) {
+    case 2: return gather_p<2>(g, t, w, forces, pot, mode, grad, st);
+    case 3: return gather_p<3>(g, t, w, forces, pot, mode, grad, st);
+    case 4: return gather_p<4>(g, t, w, forces, pot, mode, grad, st);
+    case 5: return gather_p<5>(g, t, w, forces, pot, mode, grad, st);
+    case 6: return gather_p<6>(g, t, w, forces, pot, mode, grad, st);
+    case 7: return gather_p<7>(g, t, w, forces, pot, mode, grad, st);
+    case 8: return gather_p<8>(g, t, w, forces, pot, mode, grad, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t enqueue_finalize(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(PSWF_THREADS), 0, st, g, t, w, energy, virial);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+}  // namespace pswf

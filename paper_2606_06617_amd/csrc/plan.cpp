@@ -1,0 +1,528 @@
+// Planner and C ABI of the PSWF-LR path (declared in include/pswflr.h).
+//
+// Plan creation does all FP64 host work once: parameter selection (Methods,
+// "Parameter selection"), the PSWF window and kernel polynomial tables, the
+// deconvolution tables h^2 / What_a^2, FFT factorisations, the pruned
+// x-pass block list and the workspace layout.  Execute calls only enqueue
+// kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "device_types.hpp"
+#include "host_math.hpp"
+#include "kernels.hpp"
+#include "pswflr.h"
+
+using namespace pswf;
+
+namespace {
+
+const double kPi = 3.14159265358979323846264338327950288;
+thread_local std::string g_last_error;
+
+pswflr_status fail(pswflr_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+FftAxis factorise(int n, bool *ok) {
+  FftAxis ax;
+  ax.n = n;
+  int m = n, a = 0;
+  while (m % 2 == 0) { m /= 2; ++a; }
+  std::vector<int> r;
+  while (a >= 3) { r.push_back(8); a -= 3; }
+  if (a == 2) r.push_back(4);
+  if (a == 1) r.push_back(2);
+  while (m % 3 == 0) { r.push_back(3); m /= 3; }
+  while (m % 5 == 0) { r.push_back(5); m /= 5; }
+  *ok = (m == 1) && int(r.size()) <= kMaxRadixStages;
+  ax.nst = int(r.size());
+  for (size_t i = 0; i < r.size() && i < size_t(kMaxRadixStages); ++i) ax.rad[i] = r[i];
+  return ax;
+}
+
+int floor_pow2(int x) {
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+
+// Largest divisor of m in [lo, hi]; 0 if none.
+int divisor_in(int m, int lo, int hi) {
+  for (int d = std::min(hi, m); d >= std::max(1, lo); --d)
+    if (m % d == 0) return d;
+  return 0;
+}
+
+}  // namespace
+
+struct pswflr_plan_s {
+  pswflr_params prm{};
+  pswflr_info info{};
+  Geo geo{};
+  FftAxis az, ay, ax;
+  Tables tab{};
+  void *dtab = nullptr;
+  int device = 0;
+  // workspace layout for max_atoms
+  int64_t max_atoms = 0;
+  size_t off_grid = 0, off_s1 = 0, off_s2 = 0, off_rec_a = 0, off_rec_b = 0, off_q_a = 0, off_q_b = 0,
+         off_perm_a = 0, off_perm_b = 0, off_cell_of = 0, off_slot = 0, off_count = 0, off_start = 0,
+         off_facc = 0, off_epart = 0, off_qpart = 0, off_qsum = 0, ws_bytes = 0;
+};
+
+namespace {
+
+pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan_s &pl) {
+  pswflr_params p = in;
+  if (p.n_channels < 1 || p.n_channels > PSWFLR_MAX_CHANNELS)
+    return fail(PSWFLR_ERR_INVALID_ARG, "n_channels must be in 1..64");
+  for (int c = 0; c < p.n_channels; ++c)
+    if (p.p[c] < 1 || p.p[c] > 6) return fail(PSWFLR_ERR_INVALID_ARG, "exponent p must be in 1..6");
+  for (int a = 0; a < 3; ++a)
+    if (!(p.box[a] > 0.0) || !std::isfinite(p.box[a])) return fail(PSWFLR_ERR_INVALID_ARG, "box edges must be > 0");
+  if (!(p.r_c > 0.0) || !std::isfinite(p.r_c)) return fail(PSWFLR_ERR_INVALID_ARG, "r_c must be > 0");
+  if (max_atoms < 0 || max_atoms > (int64_t(1) << 31) - 1)
+    return fail(PSWFLR_ERR_INVALID_ARG, "max_atoms must be in [0, 2^31)");
+  const bool need_tol = !(p.c > 0.0) || p.grid[0] <= 0 || p.grid[1] <= 0 || p.grid[2] <= 0 || p.support <= 0;
+  if (need_tol && !(p.tol > 0.0 && p.tol <= 0.1))
+    return fail(PSWFLR_ERR_INVALID_ARG, "tol must be in (0, 0.1] when c, grid or support are automatic");
+  if (p.support != 0 && (p.support < 2 || p.support > 8))
+    return fail(PSWFLR_ERR_INVALID_ARG, "support P must be in 2..8");
+
+  // bandwidth c ~ log(1/eps_band) with eps_band = tol / 3
+  const double c = p.c > 0.0 ? p.c : std::log(3.0 / p.tol);
+  const double kc = c / p.r_c;
+  int M[3];
+  for (int a = 0; a < 3; ++a) {
+    if (p.grid[a] > 0) {
+      M[a] = p.grid[a];
+    } else {
+      // h <= eta pi / k_c with eta = 0.6, rounded up to a 2,3,5-smooth size
+      const double hmax = 0.6 * kPi / kc;
+      M[a] = smooth_size(p.box[a] / hmax, a == 2);
+    }
+    if (M[a] > PSWFLR_MAX_GRID) return fail(PSWFLR_ERR_UNSUPPORTED, "grid edge exceeds 1024");
+    if (!is_smooth235(M[a])) return fail(PSWFLR_ERR_UNSUPPORTED, "grid edges must factor into 2, 3 and 5");
+  }
+  if (M[2] % 2) return fail(PSWFLR_ERR_UNSUPPORTED, "M_z must be even (real-to-complex transform)");
+  double eta = 0.0, h[3];
+  for (int a = 0; a < 3; ++a) {
+    h[a] = p.box[a] / M[a];
+    eta = std::max(eta, kc * h[a] / kPi);
+  }
+  if (!(eta < 1.0))
+    return fail(PSWFLR_ERR_INVALID_ARG, "grid too coarse: need k_c h / pi < 1 on every axis (Nyquist)");
+  int P = p.support;
+  double cs = p.c_spread;
+  if (P <= 0) {
+    // smallest P whose estimated force error (about 25x the aliasing
+    // estimate) stays below eps_spread = tol / 3
+    P = 8;
+    for (int cand = 4; cand <= 8; ++cand) {
+      const double cc = choose_c_spread(cand, eta, c);
+      if (25.0 * estimate_spread_error(cand, eta, cc, c) <= p.tol / 3.0) {
+        P = cand;
+        break;
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a)
+    if (M[a] < P) return fail(PSWFLR_ERR_INVALID_ARG, "every grid edge must be >= support P");
+  if (!(cs > 0.0)) cs = choose_c_spread(P, eta, c);
+
+  const int C = p.n_channels;
+  Geo &g = pl.geo;
+  g = Geo{};
+  g.C = C;
+  g.N = 0;
+  for (int a = 0; a < 3; ++a) {
+    g.M[a] = M[a];
+    g.L[a] = p.box[a];
+    g.Minv_L[a] = double(M[a]) / p.box[a];
+    g.kunit[a] = float(2.0 * kPi / p.box[a]);
+    g.dwin[a] = float(2.0 / (P * h[a]));
+  }
+  g.Nz = M[2] / 2;
+  g.P = P;
+  g.V = p.box[0] * p.box[1] * p.box[2];
+  g.invV = float(1.0 / g.V);
+  g.kc2 = float(kc * kc);
+  g.kinv = float(p.r_c / c);
+  // pruned spectrum extents (ball |k| <= k_c strictly inside Nyquist)
+  const int kzmax = int(std::floor(kc * p.box[2] / (2 * kPi)));
+  g.KZ = std::min(kzmax + 1, g.Nz);
+  g.FY = std::min(int(std::floor(kc * p.box[1] / (2 * kPi))), (M[1] - 1) / 2);
+  g.NY = 2 * g.FY + 1;
+
+  // tiles: B_x ~ 8, B_y, B_z ~ 16, each >= P - 1 unless the axis is one tile
+  const int target[3] = {8, 16, 16};
+  for (int a = 0; a < 3; ++a) {
+    const int lo = std::max(P - 1, 1);
+    int b = divisor_in(M[a], lo, std::max(target[a], lo));
+    if (b == 0) b = divisor_in(M[a], lo, 32);
+    if (b == 0) b = M[a];  // one tile spans the axis
+    g.B[a] = b;
+    g.nc[a] = M[a] / b;
+  }
+  g.ncell = g.nc[0] * g.nc[1] * g.nc[2];
+  // channel groups sized to LDS (64 KiB preferred, 160 KiB hard limit)
+  g.CG_spread = 1;
+  for (int k = std::min(C, 4); k >= 1; --k)
+    if (spread_lds_bytes(g, k) <= 64 * 1024) { g.CG_spread = k; break; }
+  if (spread_lds_bytes(g, g.CG_spread) > 160 * 1024) return fail(PSWFLR_ERR_UNSUPPORTED, "spread tile too large");
+  g.CG_gather = 1;
+  for (int k = C; k >= 1; --k)
+    if (gather_lds_bytes(g, k) <= 64 * 1024) { g.CG_gather = k; break; }
+  if (gather_lds_bytes(g, g.CG_gather) > 160 * 1024) return fail(PSWFLR_ERR_UNSUPPORTED, "gather tile too large");
+
+  g.kb = std::max(1, std::min(16, floor_pow2(4096 / std::max(M[0], M[1]))));
+  g.kb_log2 = 0;
+  while ((1 << g.kb_log2) < g.kb) ++g.kb_log2;
+  g.zlines = std::max(1, floor_pow2(4096 / g.Nz));
+  bool ok1, ok2, ok3;
+  pl.az = factorise(g.Nz, &ok1);
+  pl.ay = factorise(M[1], &ok2);
+  pl.ax = factorise(M[0], &ok3);
+  if (!(ok1 && ok2 && ok3)) return fail(PSWFLR_ERR_UNSUPPORTED, "transform length not supported");
+  if (g.Nz > 4096 || M[0] > 4096 || M[1] > 4096) return fail(PSWFLR_ERR_UNSUPPORTED, "transform too long");
+
+  // x-pass blocks: for each kept k_y, the k_z prefix inside the ball
+  std::vector<int> xblk, blim(g.NY, 0);
+  for (int iy = 0; iy < g.NY; ++iy) {
+    const int fy = iy <= g.FY ? iy : iy - g.NY;
+    const double ky = 2 * kPi * fy / p.box[1];
+    const double r2 = kc * kc - ky * ky;
+    if (r2 < 0) continue;
+    const int kzl = std::min(g.KZ - 1, int(std::floor(std::sqrt(r2) * p.box[2] / (2 * kPi))));
+    for (int kz0 = 0; kz0 <= kzl; kz0 += g.kb) {
+      const int ncol = std::min(g.kb, g.KZ - kz0);
+      xblk.insert(xblk.end(), {iy, kz0, ncol, 0});
+      blim[iy] = kz0 + ncol;
+    }
+  }
+  g.nxblk = int(xblk.size() / 4);
+
+  // ---- tables (host FP64 -> device FP32) ----
+  auto wpoly = make_window_poly(cs, kWinSeg, kWinDeg, 1e-9);
+  auto ws = prolate_cached(cs);
+  std::vector<ChannelKernel> kers;
+  for (int ch = 0; ch < C; ++ch) kers.push_back(make_channel_kernel(p.p[ch], c, p.r_c, 1e-9));
+
+  auto twiddles = [](int n, int denom) {
+    std::vector<float> t(2 * size_t(n));
+    for (int m = 0; m < n; ++m) {
+      t[2 * m] = float(std::cos(-2 * kPi * m / denom));
+      t[2 * m + 1] = float(std::sin(-2 * kPi * m / denom));
+    }
+    return t;
+  };
+  // h^2 / What_a^2 = (2 / (P window_ft(pi P f / M)))^2
+  auto deconv = [&](int Ma, int f) {
+    const double s = kPi * P * double(std::abs(f)) / Ma;
+    const double what_over_h = 0.5 * P * ws->window_ft(s);
+    return float(1.0 / (what_over_h * what_over_h));
+  };
+  std::vector<float> tw_z = twiddles(g.Nz, g.Nz), tw_zr = twiddles(g.Nz + 1, M[2]), tw_y = twiddles(M[1], M[1]),
+                     tw_x = twiddles(M[0], M[0]);
+  std::vector<float> Dx(M[0]), Dy(g.NY), Dz(g.KZ);
+  for (int i = 0; i < M[0]; ++i) Dx[i] = deconv(M[0], i <= M[0] / 2 ? i : i - M[0]);
+  for (int i = 0; i < g.NY; ++i) Dy[i] = deconv(M[1], i <= g.FY ? i : i - g.NY);
+  for (int i = 0; i < g.KZ; ++i) Dz[i] = deconv(M[2], i);
+  std::vector<float> win(kWinSeg * (kWinDeg + 1));
+  for (size_t i = 0; i < win.size(); ++i) win[i] = float(wpoly.coef[i]);
+  std::vector<float> kf(size_t(C) * kKerCoef), kg(size_t(C) * kKerCoef);
+  std::vector<KChan> kch(C);
+  std::vector<double> selfc(C), zerov(C);
+  for (int ch = 0; ch < C; ++ch) {
+    const auto &k = kers[ch];
+    for (int i = 0; i < kKerCoef; ++i) {
+      kf[size_t(ch) * kKerCoef + i] = float(k.f.coef[i]);
+      kg[size_t(ch) * kKerCoef + i] = float(k.g.coef[i]);
+    }
+    KChan kc1{};
+    kc1.A = float(k.A); kc1.B = float(k.B); kc1.Cc = float(k.Cc); kc1.D = float(k.D);
+    kc1.eA = k.eA; kc1.eB = k.eB; kc1.eC = k.eC; kc1.eD = k.eD;
+    kc1.p = k.p;
+    kc1.zero_over_V = float(k.zero_coef_V / g.V);
+    kch[ch] = kc1;
+    selfc[ch] = k.self_coef;
+    zerov[ch] = k.zero_coef_V;
+  }
+  // pack
+  std::vector<char> blob;
+  auto put = [&](const void *src, size_t bytes) {
+    size_t off = align256(blob.size());
+    blob.resize(off + bytes);
+    if (bytes) std::memcpy(blob.data() + off, src, bytes);
+    return off;
+  };
+  size_t o_twz = put(tw_z.data(), tw_z.size() * 4), o_twzr = put(tw_zr.data(), tw_zr.size() * 4),
+         o_twy = put(tw_y.data(), tw_y.size() * 4), o_twx = put(tw_x.data(), tw_x.size() * 4),
+         o_dx = put(Dx.data(), Dx.size() * 4), o_dy = put(Dy.data(), Dy.size() * 4),
+         o_dz = put(Dz.data(), Dz.size() * 4), o_win = put(win.data(), win.size() * 4),
+         o_kf = put(kf.data(), kf.size() * 4), o_kg = put(kg.data(), kg.size() * 4),
+         o_kch = put(kch.data(), kch.size() * sizeof(KChan)),
+         o_xb = put(xblk.data(), std::max<size_t>(1, xblk.size()) * 4 * (xblk.empty() ? 0 : 1)),
+         o_bl = put(blim.data(), blim.size() * 4), o_self = put(selfc.data(), selfc.size() * 8),
+         o_zero = put(zerov.data(), zerov.size() * 8);
+  blob.resize(align256(blob.size()) + 256);
+  if (hipGetDevice(&pl.device) != hipSuccess) return fail(PSWFLR_ERR_DEVICE, "hipGetDevice failed");
+  if (hipMalloc(&pl.dtab, blob.size()) != hipSuccess) return fail(PSWFLR_ERR_OOM, "table allocation failed");
+  if (hipMemcpy(pl.dtab, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(PSWFLR_ERR_DEVICE, "table upload failed");
+  char *b = static_cast<char *>(pl.dtab);
+  Tables &t = pl.tab;
+  t.tw_z = reinterpret_cast<const float *>(b + o_twz);
+  t.tw_zr = reinterpret_cast<const float *>(b + o_twzr);
+  t.tw_y = reinterpret_cast<const float *>(b + o_twy);
+  t.tw_x = reinterpret_cast<const float *>(b + o_twx);
+  t.Dx = reinterpret_cast<const float *>(b + o_dx);
+  t.Dy = reinterpret_cast<const float *>(b + o_dy);
+  t.Dz = reinterpret_cast<const float *>(b + o_dz);
+  t.win = reinterpret_cast<const float *>(b + o_win);
+  t.kf = reinterpret_cast<const float *>(b + o_kf);
+  t.kg = reinterpret_cast<const float *>(b + o_kg);
+  t.kch = reinterpret_cast<const KChan *>(b + o_kch);
+  t.xblk = reinterpret_cast<const int *>(b + o_xb);
+  t.blim = reinterpret_cast<const int *>(b + o_bl);
+  t.self_coef = reinterpret_cast<const double *>(b + o_self);
+  t.zero_V = reinterpret_cast<const double *>(b + o_zero);
+
+  // ---- workspace layout for max_atoms ----
+  const int64_t Nm = std::max<int64_t>(max_atoms, 1);
+  const size_t grid_b = size_t(C) * M[0] * M[1] * M[2] * 4;
+  const size_t s1_b = size_t(C) * M[0] * M[1] * g.KZ * 8;
+  const size_t s2_b = size_t(C) * M[0] * g.NY * g.KZ * 8;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t off = o;
+    o = align256(o + bytes);
+    return off;
+  };
+  pl.off_grid = take(grid_b);
+  pl.off_s1 = take(s1_b);
+  pl.off_s2 = s2_b <= grid_b ? pl.off_grid : take(s2_b);  // grid is dead while S2 lives
+  pl.off_rec_a = take(size_t(Nm) * 16);
+  pl.off_rec_b = take(size_t(Nm) * 16);
+  pl.off_q_a = take(size_t(Nm) * C * 4);
+  pl.off_q_b = take(size_t(Nm) * C * 4);
+  pl.off_perm_a = take(size_t(Nm) * 4);
+  pl.off_perm_b = take(size_t(Nm) * 4);
+  pl.off_cell_of = take(size_t(Nm) * 4);
+  pl.off_slot = take(size_t(Nm) * 4);
+  pl.off_count = take(size_t(g.ncell) * 4);
+  pl.off_start = take(size_t(g.ncell + 1) * 4);
+  pl.off_facc = take(size_t(Nm) * 12);
+  pl.off_epart = take(size_t(C) * std::max(1, g.nxblk) * 8 * 8);
+  pl.off_qpart = take(size_t((Nm + kQChunk - 1) / kQChunk + 1) * C * 2 * 8);
+  pl.off_qsum = take(size_t(C) * 2 * 8);
+  pl.ws_bytes = o;
+  pl.max_atoms = max_atoms;
+
+  // ---- info ----
+  pswflr_info &inf = pl.info;
+  inf = pswflr_info{};
+  inf.c = c; inf.r_c = p.r_c; inf.k_c = kc; inf.c_spread = cs; inf.eta = eta;
+  for (int a = 0; a < 3; ++a) { inf.h[a] = h[a]; inf.grid[a] = M[a]; inf.tile[a] = g.B[a]; }
+  inf.volume = g.V;
+  inf.support = P;
+  inf.n_channels = C;
+  inf.kz_keep = g.KZ;
+  inf.ny_keep = g.NY;
+  inf.max_atoms = max_atoms;
+  inf.workspace_bytes = pl.ws_bytes;
+  inf.grid_offset = pl.off_grid;
+  for (int ch = 0; ch < C; ++ch) {
+    inf.self_coef[ch] = selfc[ch];
+    inf.zero_coef[ch] = zerov[ch] / g.V;
+  }
+  pl.prm = p;
+  pl.prm.c = c;
+  pl.prm.support = P;
+  pl.prm.c_spread = cs;
+  for (int a = 0; a < 3; ++a) pl.prm.grid[a] = M[a];
+  return PSWFLR_OK;
+}
+
+Work carve(const pswflr_plan_s &pl, void *ws, int64_t N) {
+  char *b = static_cast<char *>(ws);
+  Work w{};
+  w.grid = reinterpret_cast<float *>(b + pl.off_grid);
+  w.s1 = reinterpret_cast<float *>(b + pl.off_s1);
+  w.s2 = reinterpret_cast<float *>(b + pl.off_s2);
+  w.rec_a = reinterpret_cast<float *>(b + pl.off_rec_a);
+  w.rec_b = reinterpret_cast<float *>(b + pl.off_rec_b);
+  w.q_a = reinterpret_cast<float *>(b + pl.off_q_a);
+  w.q_b = reinterpret_cast<float *>(b + pl.off_q_b);
+  w.perm_a = reinterpret_cast<int *>(b + pl.off_perm_a);
+  w.perm_b = reinterpret_cast<int *>(b + pl.off_perm_b);
+  w.cell_of = reinterpret_cast<int *>(b + pl.off_cell_of);
+  w.slot = reinterpret_cast<int *>(b + pl.off_slot);
+  w.cell_count = reinterpret_cast<int *>(b + pl.off_count);
+  w.cell_start = reinterpret_cast<int *>(b + pl.off_start);
+  w.facc = reinterpret_cast<float *>(b + pl.off_facc);
+  w.epart = reinterpret_cast<double *>(b + pl.off_epart);
+  w.qpart = reinterpret_cast<double *>(b + pl.off_qpart);
+  w.qsum = reinterpret_cast<double *>(b + pl.off_qsum);
+  (void)N;
+  return w;
+}
+
+pswflr_status check_call(pswflr_plan pl, void *ws, size_t ws_bytes, int64_t n, const float *pos,
+                         const float *q) {
+  if (!pl) return fail(PSWFLR_ERR_INVALID_ARG, "plan is NULL");
+  if (n < 0 || n > pl->max_atoms) return fail(PSWFLR_ERR_INVALID_ARG, "n_atoms must be in [0, max_atoms]");
+  if (!ws || ws_bytes < pl->ws_bytes) return fail(PSWFLR_ERR_WORKSPACE, "workspace missing or too small");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(PSWFLR_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (n > 0 && (!pos || !q)) return fail(PSWFLR_ERR_INVALID_ARG, "pos and q must be non-NULL");
+  return PSWFLR_OK;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e__ = (expr);                                                              \
+    if (e__ != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string(#expr) + ": " +     \
+                                                              hipGetErrorString(e__));    \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+pswflr_status pswflr_plan_create(const pswflr_params *params, int64_t max_atoms, pswflr_plan *out) {
+  if (!params || !out) return fail(PSWFLR_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  pswflr_plan_s *pl = nullptr;
+  try {
+    pl = new pswflr_plan_s();
+    pswflr_status s = build_plan(*params, max_atoms, *pl);
+    if (s != PSWFLR_OK) {
+      if (pl->dtab) hipFree(pl->dtab);
+      delete pl;
+      return s;
+    }
+  } catch (const std::exception &e) {
+    if (pl && pl->dtab) hipFree(pl->dtab);
+    delete pl;
+    return fail(PSWFLR_ERR_INTERNAL, e.what());
+  }
+  *out = pl;
+  return PSWFLR_OK;
+}
+
+pswflr_status pswflr_plan_info(pswflr_plan plan, pswflr_info *out) {
+  if (!plan || !out) return fail(PSWFLR_ERR_INVALID_ARG, "NULL argument");
+  *out = plan->info;
+  return PSWFLR_OK;
+}
+
+pswflr_status pswflr_plan_destroy(pswflr_plan plan) {
+  if (!plan) return PSWFLR_OK;
+  if (plan->dtab) hipFree(plan->dtab);
+  delete plan;
+  return PSWFLR_OK;
+}
+
+pswflr_status pswflr_execute(pswflr_plan plan, pswflr_stream stream, void *workspace, size_t ws_bytes,
+                             int64_t n_atoms, const float *pos, const float *q, double *energy, float *forces,
+                             double *virial, float *potential) {
+  pswflr_status s = check_call(plan, workspace, ws_bytes, n_atoms, pos, q);
+  if (s != PSWFLR_OK) return s;
+  if (!energy) return fail(PSWFLR_ERR_INVALID_ARG, "energy output is required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Geo g = plan->geo;
+  g.N = n_atoms;
+  Work w = carve(*plan, workspace, n_atoms);
+  const Tables &t = plan->tab;
+  const bool adjoint = forces || potential;
+  HIPCHK(enqueue_sort(g, w, pos, q, st));
+  HIPCHK(enqueue_qsum(g, w, q, st));
+  HIPCHK(enqueue_spread(g, t, w, st));
+  HIPCHK(enqueue_forward_fft(g, t, plan->az, plan->ay, w, st));
+  HIPCHK(enqueue_xmul(g, t, plan->ax, w, adjoint ? 1 : 0, nullptr, st));
+  HIPCHK(enqueue_finalize(g, t, w, energy, virial, st));
+  if (adjoint) {
+    HIPCHK(enqueue_inverse_fft(g, t, plan->az, plan->ay, w, st));
+    HIPCHK(enqueue_gather(g, t, w, forces, potential, 1, nullptr, st));
+  }
+  return PSWFLR_OK;
+}
+
+pswflr_status pswflr_backward(pswflr_plan plan, pswflr_stream stream, void *workspace, size_t ws_bytes,
+                              int64_t n_atoms, const float *pos, const float *q, const double *grad_energy,
+                              float *grad_q, float *grad_pos) {
+  pswflr_status s = check_call(plan, workspace, ws_bytes, n_atoms, pos, q);
+  if (s != PSWFLR_OK) return s;
+  if (!grad_energy) return fail(PSWFLR_ERR_INVALID_ARG, "grad_energy is required");
+  if (!grad_q && !grad_pos) return PSWFLR_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Geo g = plan->geo;
+  g.N = n_atoms;
+  Work w = carve(*plan, workspace, n_atoms);
+  const Tables &t = plan->tab;
+  HIPCHK(enqueue_xmul(g, t, plan->ax, w, 2, grad_energy, st));
+  HIPCHK(enqueue_inverse_fft(g, t, plan->az, plan->ay, w, st));
+  HIPCHK(enqueue_gather(g, t, w, grad_pos, grad_q, 2, grad_energy, st));
+  return PSWFLR_OK;
+}
+
+pswflr_status pswflr_batch_workspace(int32_t n, const pswflr_plan *plans, const int64_t *n_atoms, size_t *bytes) {
+  if (n < 0 || (n > 0 && (!plans || !n_atoms)) || !bytes) return fail(PSWFLR_ERR_INVALID_ARG, "bad batch arguments");
+  size_t tot = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(PSWFLR_ERR_INVALID_ARG, "NULL plan in batch");
+    tot += align256(plans[i]->ws_bytes);
+  }
+  *bytes = tot;
+  return PSWFLR_OK;
+}
+
+pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const pswflr_io *io,
+                                   pswflr_stream stream, void *workspace, size_t ws_bytes) {
+  size_t need = 0;
+  std::vector<int64_t> na(std::max(0, n));
+  for (int i = 0; i < n; ++i) na[i] = io ? io[i].n_atoms : 0;
+  pswflr_status s = pswflr_batch_workspace(n, plans, na.data(), &need);
+  if (s != PSWFLR_OK) return s;
+  if (!io && n > 0) return fail(PSWFLR_ERR_INVALID_ARG, "io is NULL");
+  if (ws_bytes < need || (n > 0 && !workspace)) return fail(PSWFLR_ERR_WORKSPACE, "batch workspace too small");
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    s = pswflr_execute(plans[i], stream, static_cast<char *>(workspace) + off, plans[i]->ws_bytes, io[i].n_atoms,
+                       io[i].pos, io[i].q, io[i].energy, io[i].forces, io[i].virial, io[i].potential);
+    if (s != PSWFLR_OK) return s;
+    off += align256(plans[i]->ws_bytes);
+  }
+  return PSWFLR_OK;
+}
+
+const char *pswflr_status_string(pswflr_status status) {
+  switch (status) {
+    case PSWFLR_OK: return "ok";
+    case PSWFLR_ERR_INVALID_ARG: return "invalid argument";
+    case PSWFLR_ERR_UNSUPPORTED: return "unsupported";
+    case PSWFLR_ERR_WORKSPACE: return "workspace missing or too small";
+    case PSWFLR_ERR_DEVICE: return "device error";
+    case PSWFLR_ERR_OOM: return "out of memory";
+    case PSWFLR_ERR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+void pswflr_last_error(char *buf, size_t len) {
+  if (!buf || len == 0) return;
+  std::snprintf(buf, len, "%s", g_last_error.c_str());
+}
+
+}  // extern "C"
