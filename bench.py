@@ -1,0 +1,192 @@
+"""Throughput benchmark of the PSWF-LR reciprocal-space path on one MI355X.
+
+A step is one whole evaluation (sort, spread, forward FFT with the fused
+kernel scaling and energy/virial reduction, inverse FFT, gather of forces)
+of the default workload, the 1e6-atom ionic frame (12 channels, 256^3
+grid, P = 8), with inputs resident in HBM.  Prints one JSON line with the
+throughput (atoms/s), the roofline fraction of the dominant kernel from
+HIP events recorded around every launch during the timed steps, and the
+FP64 oracle timed on a bounded sample of the same workload on the host.
+
+  python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload ionic_1m]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "LR energy+force atoms/s at ≤1e-4 rel force err; served p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+STAGES = ["sort", "qsum", "spread", "fft_z", "fft_y", "fft_x_scale", "reduce", "ifft_y", "ifft_z", "gather"]
+C_MOL, R_C = 12.024, 5.0
+
+
+def workload(name):
+    from paper_2606_06617_amd import workloads as wl
+    if name == "ionic_1m":
+        return wl.ionic()
+    if name == "water_3000":
+        return wl.water()
+    if name == "nacl_512":
+        return wl.nacl()
+    raise SystemExit("unknown workload %s" % name)
+
+
+def algorithmic_bytes(info, N, C, cg_spread):
+    """HBM bytes each kernel must move per launch (reads + writes of the
+    data it consumes and produces once), the roofline numerator."""
+    Mx, My, Mz = info["grid"]
+    M = Mx * My * Mz
+    KZ, NY, xcols = info["kz_keep"], info["ny_keep"], info["xcols"]
+    s1 = 8 * C * Mx * My * KZ
+    s2 = 8 * C * Mx * NY * KZ
+    return {
+        "spread": 16 * N + 4 * cg_spread * N + 4 * cg_spread * M,
+        "fft_z": 4 * C * M + s1,
+        "fft_y": s1 + s2,
+        "fft_x_scale": 2 * 8 * C * Mx * xcols,
+        "ifft_y": 8 * C * Mx * xcols + s1,
+        "ifft_z": s1 + 4 * C * M,
+        "gather": 4 * C * M + N * (16 + 4 * C) + 12 * N,
+    }
+
+
+def cpu_baseline(w, n_sample=48):
+    """The FP64 oracle (direct structure-factor sum over the same k-ball with
+    energy, forces and virial) timed single-threaded on a bounded sample:
+    one channel of each distinct exponent, first with no atoms (the fixed
+    cost of enumerating the k-ball and evaluating the kernels) and then with
+    the first n_sample atoms (the per-atom cost).  The oracle's cost is
+    linear in atoms and channels, so the full-frame time is
+    (C / C_s) (t_0 + N (t_n - t_0) / n), and value = N / that."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import reciprocal
+
+    chans = []
+    for i, p in enumerate(w["ps"]):
+        if p not in [w["ps"][j] for j in chans]:
+            chans.append(i)
+    ps = [w["ps"][i] for i in chans]
+
+    def run(n):
+        pos = w["pos"][:n].astype(np.float64)
+        q = w["q"][chans, :n].astype(np.float64)
+        t0 = time.perf_counter()
+        reciprocal.evaluate(pos, q, w["box"], ps, C_MOL, R_C)
+        return time.perf_counter() - t0
+
+    with threadpool_limits(limits=1):
+        t0 = run(0)
+        tn = run(n_sample)
+    N, C = w["pos"].shape[0], len(w["ps"])
+    full = (C / len(chans)) * (t0 + N * (tn - t0) / n_sample)
+    return {"value": N / full, "unit": "atoms/s", "cores": 1, "kind": "oracle",
+            "sample": ("channels %s (one per exponent p=%s) with 0 and the first %d atoms, full k-ball "
+                       "|k|<=c/r_c, E+F+W, FP64 numpy on 1 thread: t_0=%.2f s, t_n=%.2f s; "
+                       "extrapolated to %d atoms x %d channels = %.3g s"
+                       % (chans, ps, n_sample, t0, tn, N, C, full))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="ionic_1m")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the sharded design is "
+              "described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import ctypes
+
+    import torch
+
+    from paper_2606_06617_amd import _lib
+    from paper_2606_06617_amd.api import Plan
+
+    w = workload(args.workload)
+    N = w["pos"].shape[0]
+    C = len(w["ps"])
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(w["pos"]).to(dev)
+    q = torch.from_numpy(w["q"]).to(dev)
+    plan = Plan(w["box"], w["ps"], r_c=R_C, c=C_MOL, grid=w["grid"], support=w["support"], max_atoms=N)
+    ws = plan.new_workspace(dev)
+    out = {"energy": torch.empty(3 * C, dtype=torch.float64, device=dev),
+           "forces": torch.empty((N, 3), dtype=torch.float32, device=dev),
+           "virial": torch.empty(6, dtype=torch.float64, device=dev)}
+    L = _lib.lib()
+
+    def step():
+        plan.execute(pos, q, forces=True, virial=True, workspace=ws, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    _lib.check(L.pswflr_profile_enable(plan.handle, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (ctypes.c_double * len(STAGES))()
+    cnt = (ctypes.c_int64 * len(STAGES))()
+    _lib.check(L.pswflr_profile_read(plan.handle, ms, cnt))
+    _lib.check(L.pswflr_profile_enable(plan.handle, 0))
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    stage_ms = {STAGES[i]: ms[i] / args.steps for i in range(len(STAGES))}
+    avg_launch_ms = {STAGES[i]: (ms[i] / cnt[i] if cnt[i] else 0.0) for i in range(len(STAGES))}
+
+    info = plan.info
+    cg_spread = int(info["cg_spread"])
+    algo = algorithmic_bytes(info, N, C, cg_spread)
+    dom = max(algo.keys(), key=lambda k: stage_ms[k])
+    achieved = algo[dom] / (avg_launch_ms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": int(algo[dom]),
+                "avg_launch_ms": round(avg_launch_ms[dom], 4)}
+    per_stage = {k: {"ms_per_step": round(stage_ms[k], 4),
+                     "GB_s": (round(algo[k] / (avg_launch_ms[k] * 1e-3) / 1e9, 1)
+                              if k in algo and avg_launch_ms[k] > 0 else None)} for k in STAGES}
+
+    rec = {
+        "metric": METRIC,
+        "value": N / (ms_per_step * 1e-3),
+        "unit": "atoms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "n_atoms": N, "channels": C, "p": sorted(set(w["ps"])),
+                   "grid": list(info["grid"]), "support": info["support"], "c": info["c"], "r_c": info["r_c"],
+                   "c_spread": round(info["c_spread"], 4), "eta": round(info["eta"], 4),
+                   "box": [round(b, 4) for b in w["box"]], "outputs": "energy+forces+virial"},
+        "roofline": roofline,
+        "stages": per_stage,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -93,6 +93,9 @@ typedef struct {
   int32_t kz_keep;        /* half-spectrum z columns kept (|k_z| <= k_c)    */
   int32_t ny_keep;        /* y frequencies kept after the y transform        */
   int32_t tile[3];        /* spreading/gather tile edge (grid points)        */
+  int32_t cg_spread;      /* channels per spreading launch                   */
+  int32_t cg_gather;      /* channels per LDS pass of the gather             */
+  int64_t xcols;          /* (k_y, k_z) columns the fused x pass transforms  */
   int64_t max_atoms;
   size_t workspace_bytes; /* bytes needed by pswflr_execute                  */
   size_t grid_offset;     /* byte offset of the real grids [C][Mx][My][Mz]   */
@@ -166,6 +169,30 @@ pswflr_status pswflr_batch_workspace(int32_t n, const pswflr_plan *plans,
 pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans,
                                    const pswflr_io *io, pswflr_stream stream,
                                    void *workspace, size_t ws_bytes);
+
+/* Per-stage device timing, for measurement (the paper times whole
+ * forward+backward evaluations after warm-ups; Methods, "Performance
+ * comparison in differentiable long-range evaluations").  While enabled,
+ * every stage launch of the execute calls is bracketed by a pair of
+ * hipEvents on the caller's stream.  pswflr_profile_read waits for the
+ * recorded events, writes per-stage total milliseconds and launch counts
+ * ([PSWFLR_NUM_STAGES] each) and forgets them.  Not for concurrent use of
+ * one plan from several threads while enabled. */
+enum {
+  PSWFLR_STAGE_SORT = 0,       /* binning, cell order                      */
+  PSWFLR_STAGE_QSUM = 1,       /* per-channel sum q, sum q^2               */
+  PSWFLR_STAGE_SPREAD = 2,     /* step (i), one launch per channel group   */
+  PSWFLR_STAGE_FFT_Z = 3,      /* z real-to-complex                        */
+  PSWFLR_STAGE_FFT_Y = 4,      /* y forward                                */
+  PSWFLR_STAGE_FFT_X_SCALE = 5,/* x forward, scaling, reduction, x inverse */
+  PSWFLR_STAGE_REDUCE = 6,     /* FP64 energy and virial                   */
+  PSWFLR_STAGE_IFFT_Y = 7,
+  PSWFLR_STAGE_IFFT_Z = 8,
+  PSWFLR_STAGE_GATHER = 9,
+  PSWFLR_NUM_STAGES = 10
+};
+pswflr_status pswflr_profile_enable(pswflr_plan plan, int enable);
+pswflr_status pswflr_profile_read(pswflr_plan plan, double *ms_total, int64_t *launches);
 
 const char *pswflr_status_string(pswflr_status status);
 /* Copies the last error message of the calling thread (NUL-terminated). */

@@ -45,6 +45,9 @@ class Info(ctypes.Structure):
         ("kz_keep", ctypes.c_int32),
         ("ny_keep", ctypes.c_int32),
         ("tile", ctypes.c_int32 * 3),
+        ("cg_spread", ctypes.c_int32),
+        ("cg_gather", ctypes.c_int32),
+        ("xcols", ctypes.c_int64),
         ("max_atoms", ctypes.c_int64),
         ("workspace_bytes", ctypes.c_size_t),
         ("grid_offset", ctypes.c_size_t),
@@ -87,11 +90,14 @@ def lib():
     L.pswflr_batch_workspace.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                          ctypes.POINTER(sz)]
     L.pswflr_execute_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(IO), vp, vp, sz]
+    L.pswflr_profile_enable.argtypes = [vp, ctypes.c_int]
+    L.pswflr_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     L.pswflr_status_string.argtypes = [ctypes.c_int]
     L.pswflr_status_string.restype = ctypes.c_char_p
     L.pswflr_last_error.argtypes = [ctypes.c_char_p, sz]
     for name in ("pswflr_plan_create", "pswflr_plan_info", "pswflr_plan_destroy", "pswflr_execute",
-                 "pswflr_backward", "pswflr_batch_workspace", "pswflr_execute_batch"):
+                 "pswflr_backward", "pswflr_batch_workspace", "pswflr_execute_batch",
+                 "pswflr_profile_enable", "pswflr_profile_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

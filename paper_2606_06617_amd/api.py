@@ -41,6 +41,7 @@ class Plan:
             "c": inf.c, "r_c": inf.r_c, "k_c": inf.k_c, "c_spread": inf.c_spread, "eta": inf.eta,
             "h": tuple(inf.h), "volume": inf.volume, "grid": tuple(inf.grid), "support": inf.support,
             "n_channels": C, "kz_keep": inf.kz_keep, "ny_keep": inf.ny_keep, "tile": tuple(inf.tile),
+            "cg_spread": inf.cg_spread, "cg_gather": inf.cg_gather, "xcols": inf.xcols,
             "max_atoms": inf.max_atoms, "workspace_bytes": inf.workspace_bytes,
             "grid_offset": inf.grid_offset,
             "self_coef": [inf.self_coef[i] for i in range(C)],

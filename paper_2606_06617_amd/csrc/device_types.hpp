@@ -14,11 +14,30 @@ constexpr int kKerSeg = 16;    // kernel polynomials: segments on kappa in [0, 1
 constexpr int kKerDeg = 11;
 constexpr int kKerCoef = kKerSeg * (kKerDeg + 1);
 
+// Division by a loop-invariant divisor d < 2^31 with a multiply-high
+// (Granlund-Montgomery): q = (umulhi(n, m) + n) >> s for n < 2^31.
+struct FastDiv {
+  unsigned m = 0;
+  int s = 0;
+  int d = 1;
+};
+inline FastDiv make_fastdiv(int d) {
+  FastDiv f;
+  f.d = d;
+  if (d <= 1) return f;
+  int s = 0;
+  while ((1u << s) < unsigned(d)) ++s;
+  f.s = s;
+  f.m = unsigned(((1ull << 32) * ((1ull << s) - unsigned(d))) / unsigned(d) + 1);
+  return f;
+}
+
 // Stockham factorisation of one transform length.
 struct FftAxis {
   int n = 1;
   int nst = 0;
   int rad[kMaxRadixStages] = {0};
+  FastDiv nsdiv[kMaxRadixStages];   // divisor = product of the radices before stage s
 };
 
 // Per-channel constants of the Fourier kernel (see host_math.hpp):
@@ -59,6 +78,8 @@ struct Geo {
   int zlines;             // lines per z-pass block (power of two)
   int kb;                 // columns per y/x-pass block (power of two)
   int kb_log2;
+  FastDiv div_nz;         // by Nz
+  FastDiv div_kz;         // by KZ
 };
 
 // Device pointers into a plan's table allocation.

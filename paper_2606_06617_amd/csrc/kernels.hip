@@ -28,6 +28,9 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ int fdiv(int n, const FastDiv &f) {
+  return int((__umulhi(unsigned(n), f.m) + unsigned(n)) >> f.s);
+}
 // multiply by i*sigma (sigma = +-1)
 template <int S>
 __device__ __forceinline__ float2 mul_isig(float2 a) {
@@ -122,7 +125,7 @@ struct Dft<8, S> {
 // order.  Results are held in registers across a barrier, so the stage is
 // in place.  Each thread owns at most MAXE elements.
 template <int R, int S, int MAXE>
-__device__ __forceinline__ void fft_stage(float2 *buf, int n, int ns, int nl_log2, int ld,
+__device__ __forceinline__ void fft_stage(float2 *buf, int n, int ns, const FastDiv &nsd, int nl_log2, int ld,
                                           const float2 *tw, int tid) {
   constexpr int MAXB = (MAXE + R - 1) / R;
   const int nb = n / R;
@@ -137,7 +140,7 @@ __device__ __forceinline__ void fft_stage(float2 *buf, int n, int ns, int nl_log
     if (b < total) {
       const int line = b & ((1 << nl_log2) - 1);
       const int j = b >> nl_log2;
-      const int jq = j / ns;
+      const int jq = fdiv(j, nsd);
       const int k = j - jq * ns;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * nb) * ld + line];
@@ -172,12 +175,13 @@ __device__ void lds_fft(float2 *buf, const FftAxis &ax, int nl_log2, int ld, con
   int ns = 1;
   for (int s = 0; s < ax.nst; ++s) {
     const int R = ax.rad[s];
+    const FastDiv &nsd = ax.nsdiv[s];
     switch (R) {
-      case 2: fft_stage<2, S, MAXE>(buf, ax.n, ns, nl_log2, ld, tw, tid); break;
-      case 3: fft_stage<3, S, MAXE>(buf, ax.n, ns, nl_log2, ld, tw, tid); break;
-      case 4: fft_stage<4, S, MAXE>(buf, ax.n, ns, nl_log2, ld, tw, tid); break;
-      case 5: fft_stage<5, S, MAXE>(buf, ax.n, ns, nl_log2, ld, tw, tid); break;
-      default: fft_stage<8, S, MAXE>(buf, ax.n, ns, nl_log2, ld, tw, tid); break;
+      case 2: fft_stage<2, S, MAXE>(buf, ax.n, ns, nsd, nl_log2, ld, tw, tid); break;
+      case 3: fft_stage<3, S, MAXE>(buf, ax.n, ns, nsd, nl_log2, ld, tw, tid); break;
+      case 4: fft_stage<4, S, MAXE>(buf, ax.n, ns, nsd, nl_log2, ld, tw, tid); break;
+      case 5: fft_stage<5, S, MAXE>(buf, ax.n, ns, nsd, nl_log2, ld, tw, tid); break;
+      default: fft_stage<8, S, MAXE>(buf, ax.n, ns, nsd, nl_log2, ld, tw, tid); break;
     }
     ns *= R;
   }
@@ -366,47 +370,80 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nbl
 }
 
 // ---------------------------------------------------------------------------
-// Spread (step i): one workgroup per tile and channel group.  Candidate atoms
-// (windows touching the tile) are staged in LDS with their 3 P window
-// weights; wave w owns tile planes x = w, w + 4, ... so every grid value is
-// accumulated by exactly one wave, in candidate order: no atomics, and the
-// result is bitwise reproducible.
-constexpr int kSpreadChunk = PSWF_THREADS;
-constexpr int kSpreadCGMax = 4;
+// Spread (step i), output-stationary.  One workgroup of 8 waves per tile.
+// Candidate atoms (windows touching the tile) are staged in LDS with their
+// 3 P window weights and charges.  The tile is cut into 4 x 4 x 8 blocks;
+// each wave owns up to kSpreadNBW blocks and every lane owns two points of
+// a block (z and z + 4) with one accumulator per channel in registers.  All
+// waves walk the candidates in the same order, skip blocks the window does
+// not touch with a scalar test, and add w_x w_y w_z q to their own points:
+// no atomics and no read-modify-write of shared memory; the summation
+// order is fixed, so the result is bitwise reproducible.
+constexpr int kSpreadThreads = 512;
+constexpr int kSpreadChunk = 256;
+constexpr int kSpreadCGM = 12;   // channels per launch
+constexpr int kSpreadNBW = 2;    // blocks per wave
+
+// window [d, d + P) (mod M) meets block [o, o + S) ?
+__device__ __forceinline__ bool win_meets(int o, int S, int d, int P, int M) {
+  int a = o - d;
+  if (a < 0) a += M;
+  int b = d - o;
+  if (b < 0) b += M;
+  return a < P || b < S;
+}
 
 template <int P>
-__global__ __launch_bounds__(PSWF_THREADS) void k_spread(Geo g, Tables t, Work w, int cg0, int ncg) {
+__global__ __launch_bounds__(kSpreadThreads) void k_spread(Geo g, Tables t, Work w, int cg0, int ncg) {
   extern __shared__ float smem[];
-  const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
-  const int SZ = Bz + 1;                 // padded z stride
-  const int plane = By * SZ;
-  float *tile = smem;                                  // [ncg][Bx][By][SZ]
-  float *wcf = tile + ncg * Bx * plane;                // window coefficients
-  int *cd = reinterpret_cast<int *>(wcf + kWinSeg * (kWinDeg + 1));   // [3][chunk]
-  float *cw = reinterpret_cast<float *>(cd + 3 * kSpreadChunk);       // [chunk][3][P]
-  float *cq = cw + kSpreadChunk * 3 * P;                               // [chunk][CGMax]
-  __shared__ int wcount[PSWF_THREADS / 64];
+  float *cq = smem;                                                   // [chunk][CGM]
+  float *cw = cq + kSpreadChunk * kSpreadCGM;                         // [chunk][3][P]
+  float *wcf = cw + kSpreadChunk * 3 * P;                             // window coefficients
+  int *cd = reinterpret_cast<int *>(wcf + kWinSeg * (kWinDeg + 1));   // [chunk] packed offsets
+  __shared__ int wcount[kSpreadChunk / 64];
   __shared__ int ncand_s;
 
+  const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
+  const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cell = blockIdx.x;
   const int cz = cell % g.nc[2], cy = (cell / g.nc[2]) % g.nc[1], cx = cell / (g.nc[2] * g.nc[1]);
   const int t0[3] = {cx * Bx, cy * By, cz * Bz};
   const int ctile[3] = {cx, cy, cz};
 
-  for (int e = tid; e < ncg * Bx * plane; e += PSWF_THREADS) tile[e] = 0.0f;
-  for (int e = tid; e < kWinSeg * (kWinDeg + 1); e += PSWF_THREADS) wcf[e] = t.win[e];
+  for (int e = tid; e < kWinSeg * (kWinDeg + 1); e += kSpreadThreads) wcf[e] = t.win[e];
 
-  // candidate cells: this tile's cell and the previous one along each axis
-  int clist[3][2], ccount[3];
+  // blocks owned by this wave and this lane's two points in each
+  const int nbx = (Bx + 3) >> 2, nby = (By + 3) >> 2, nbz = (Bz + 7) >> 3;
+  const int nblk = nbx * nby * nbz;
+  const int lxo = lane >> 4, lyo = (lane >> 2) & 3, lzo = lane & 3;
+  int bo[kSpreadNBW][3];
+  bool bval[kSpreadNBW];
+#pragma unroll
+  for (int j = 0; j < kSpreadNBW; ++j) {
+    const int b = wave + j * (kSpreadThreads / 64);
+    bval[j] = b < nblk;
+    const int bb = bval[j] ? b : 0;
+    bo[j][0] = (bb / (nby * nbz)) * 4;
+    bo[j][1] = ((bb / nbz) % nby) * 4;
+    bo[j][2] = (bb % nbz) * 8;
+  }
+  float acc[kSpreadNBW][2][kSpreadCGM];
+#pragma unroll
+  for (int j = 0; j < kSpreadNBW; ++j)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < kSpreadCGM; ++c) acc[j][h][c] = 0.0f;
+
+  // candidate cells: this tile's cell and the ones before it along each
+  // axis that can hold a window start reaching into the tile
+  int clist[3][8], ccount[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    clist[a][0] = ctile[a];
-    ccount[a] = 1;
-    if (g.nc[a] > 1) {
-      clist[a][1] = (ctile[a] + g.nc[a] - 1) % g.nc[a];
-      ccount[a] = 2;
-    }
+    const int J = min(g.nc[a] - 1, (P - 2) / g.B[a] + 1);
+    ccount[a] = min(J + 1, 8);
+    for (int j = 0; j < ccount[a]; ++j) clist[a][j] = (ctile[a] - j + 8 * g.nc[a]) % g.nc[a];
   }
   __syncthreads();
 
@@ -416,11 +453,12 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_spread(Geo g, Tables t, Work w
         const int cc = (clist[0][ix] * g.nc[1] + clist[1][iy]) * g.nc[2] + clist[2][iz];
         const int s = w.cell_start[cc], e = w.cell_start[cc + 1];
         for (int base = s; base < e; base += kSpreadChunk) {
+          // stage candidates: threads 0..chunk-1 each test one atom
           const int i = base + tid;
           bool ok = false;
           float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
           int d[3] = {0, 0, 0};
-          if (i < e) {
+          if (tid < kSpreadChunk && i < e) {
             r = reinterpret_cast<const float4 *>(w.rec_a)[i];
             const unsigned pk = __float_as_uint(r.w);
             ok = true;
@@ -433,53 +471,65 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_spread(Geo g, Tables t, Work w
             }
           }
           const unsigned long long m = __ballot(ok);
-          if (lane == 0) wcount[wave] = __popcll(m);
+          if (lane == 0 && wave < kSpreadChunk / 64) wcount[wave] = __popcll(m);
           __syncthreads();
-          int off = 0;
-          for (int k = 0; k < wave; ++k) off += wcount[k];
-          if (tid == 0) {
-            int tot = 0;
-            for (int k = 0; k < PSWF_THREADS / 64; ++k) tot += wcount[k];
-            ncand_s = tot;
-          }
           if (ok) {
+            int off = 0;
+            for (int k = 0; k < wave; ++k) off += wcount[k];
             const int slot = off + __popcll(m & ((1ull << lane) - 1ull));
+            cd[slot] = d[0] | (d[1] << 10) | (d[2] << 20);
             const float dl[3] = {r.x, r.y, r.z};
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              cd[a * kSpreadChunk + slot] = d[a];
+            for (int a = 0; a < 3; ++a)
 #pragma unroll
               for (int l = 0; l < P; ++l)
                 cw[(slot * 3 + a) * P + l] = win_eval(wcf, (2.0f * (l + dl[a])) / P - 1.0f);
-            }
-            for (int c = 0; c < ncg; ++c) cq[slot * kSpreadCGMax + c] = w.q_a[int64_t(cg0 + c) * g.N + i];
+#pragma unroll
+            for (int c = 0; c < kSpreadCGM; ++c)
+              cq[slot * kSpreadCGM + c] = c < ncg ? w.q_a[int64_t(cg0 + c) * g.N + i] : 0.0f;
+          }
+          if (tid == 0) {
+            int tot = 0;
+            for (int k = 0; k < kSpreadChunk / 64; ++k) tot += wcount[k];
+            ncand_s = tot;
           }
           __syncthreads();
           const int ncand = ncand_s;
           for (int k = 0; k < ncand; ++k) {
-            const int dx = cd[k], dy = cd[kSpreadChunk + k], dz = cd[2 * kSpreadChunk + k];
+            const int pk = __builtin_amdgcn_readfirstlane(cd[k]);
+            const int dx = pk & 1023, dy = (pk >> 10) & 1023, dz = (pk >> 20) & 1023;
             const float *wk = cw + k * 3 * P;
-            float qk[kSpreadCGMax];
+            float q[kSpreadCGM];
 #pragma unroll
-            for (int c = 0; c < kSpreadCGMax; ++c) qk[c] = c < ncg ? cq[k * kSpreadCGMax + c] : 0.0f;
-            for (int xt = wave; xt < Bx; xt += PSWF_THREADS / 64) {
-              int lx = xt - dx;
-              if (lx < 0) lx += g.M[0];
-              if (lx >= P) continue;
-              const float wxv = wk[lx];
-              for (int l = lane; l < P * P; l += 64) {
-                const int ly = l / P, lz = l - ly * P;
-                int y = dy + ly;
-                if (y >= g.M[1]) y -= g.M[1];
-                int z = dz + lz;
-                if (z >= g.M[2]) z -= g.M[2];
-                if (y < By && z < Bz) {
-                  const float wv = wxv * wk[P + ly] * wk[2 * P + lz];
-                  float *dst = tile + xt * plane + y * SZ + z;
+            for (int c = 0; c < kSpreadCGM; c += 4) {
+              const float4 q4 = *reinterpret_cast<const float4 *>(cq + k * kSpreadCGM + c);
+              q[c] = q4.x;
+              q[c + 1] = q4.y;
+              q[c + 2] = q4.z;
+              q[c + 3] = q4.w;
+            }
 #pragma unroll
-                  for (int c = 0; c < kSpreadCGMax; ++c)
-                    if (c < ncg) dst[c * Bx * plane] += wv * qk[c];
-                }
+            for (int j = 0; j < kSpreadNBW; ++j) {
+              if (!bval[j]) continue;
+              if (!win_meets(bo[j][0], 4, dx, P, Mx) || !win_meets(bo[j][1], 4, dy, P, My) ||
+                  !win_meets(bo[j][2], 8, dz, P, Mz))
+                continue;
+              const int x = bo[j][0] + lxo, y = bo[j][1] + lyo, z0 = bo[j][2] + lzo, z1 = z0 + 4;
+              int lx = x - dx, ly = y - dy, lz0 = z0 - dz, lz1 = z1 - dz;
+              if (lx < 0) lx += Mx;
+              if (ly < 0) ly += My;
+              if (lz0 < 0) lz0 += Mz;
+              if (lz1 < 0) lz1 += Mz;
+              const bool vxy = x < Bx && y < By && lx < P && ly < P;
+              const bool v0 = vxy && z0 < Bz && lz0 < P;
+              const bool v1 = vxy && z1 < Bz && lz1 < P;
+              const float wxy = wk[min(lx, P - 1)] * wk[P + min(ly, P - 1)];
+              const float w0 = v0 ? wxy * wk[2 * P + min(lz0, P - 1)] : 0.0f;
+              const float w1 = v1 ? wxy * wk[2 * P + min(lz1, P - 1)] : 0.0f;
+#pragma unroll
+              for (int c = 0; c < kSpreadCGM; ++c) {
+                acc[j][0][c] = fmaf(w0, q[c], acc[j][0][c]);
+                acc[j][1][c] = fmaf(w1, q[c], acc[j][1][c]);
               }
             }
           }
@@ -487,14 +537,36 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_spread(Geo g, Tables t, Work w
         }
       }
 
-  // write the tile (every grid value belongs to exactly one tile)
+  // write the tile one channel at a time through LDS (coalesced rows);
+  // every grid value belongs to exactly one tile
+  float *stage = smem;  // reuses the candidate area (Bx * By * Bz floats)
   const int nt = Bx * By * Bz;
-  for (int e = tid; e < ncg * nt; e += PSWF_THREADS) {
-    const int c = e / nt, r0 = e - c * nt;
-    const int x = r0 / (By * Bz), r1 = r0 - x * By * Bz, y = r1 / Bz, z = r1 - y * Bz;
-    w.grid[((int64_t(cg0 + c) * g.M[0] + t0[0] + x) * g.M[1] + t0[1] + y) * g.M[2] + t0[2] + z] =
-        tile[c * Bx * plane + x * plane + y * SZ + z];
+  for (int c = 0; c < ncg; ++c) {
+#pragma unroll
+    for (int j = 0; j < kSpreadNBW; ++j) {
+      if (!bval[j]) continue;
+      const int x = bo[j][0] + lxo, y = bo[j][1] + lyo, z0 = bo[j][2] + lzo;
+      float v0 = 0.f, v1 = 0.f;
+#pragma unroll
+      for (int cc = 0; cc < kSpreadCGM; ++cc)
+        if (cc == c) {
+          v0 = acc[j][0][cc];
+          v1 = acc[j][1][cc];
+        }
+      if (x < Bx && y < By) {
+        if (z0 < Bz) stage[(x * By + y) * Bz + z0] = v0;
+        if (z0 + 4 < Bz) stage[(x * By + y) * Bz + z0 + 4] = v1;
+      }
+    }
+    __syncthreads();
+    for (int row = wave; row < Bx * By; row += kSpreadThreads / 64) {
+      const int x = row / By, y = row - (row / By) * By;
+      float *dst = w.grid + ((int64_t(cg0 + c) * Mx + t0[0] + x) * My + t0[1] + y) * Mz + t0[2];
+      for (int z = lane; z < Bz; z += 64) dst[z] = stage[row * Bz + z];
+    }
+    __syncthreads();
   }
+  (void)nt;
 }
 
 // ---------------------------------------------------------------------------
@@ -517,14 +589,14 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zfwd(Geo g, Tables t, FftAxis 
   for (int e = tid; e <= Nz; e += PSWF_THREADS) twr[e] = reinterpret_cast<const float2 *>(t.tw_zr)[e];
   const float2 *src = reinterpret_cast<const float2 *>(w.grid) + line0 * Nz;
   for (int e = tid; e < L * Nz; e += PSWF_THREADS) {
-    const int line = e / Nz, n = e - line * Nz;
+    const int line = fdiv(e, g.div_nz), n = e - line * Nz;
     buf[n * ld + line] = line < nl ? src[e] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   lds_fft<-1, 16>(buf, ax, llog, ld, tw, tid);
   float2 *dst = reinterpret_cast<float2 *>(w.s1) + line0 * g.KZ;
   for (int e = tid; e < nl * g.KZ; e += PSWF_THREADS) {
-    const int line = e / g.KZ, k = e - line * g.KZ;
+    const int line = fdiv(e, g.div_kz), k = e - line * g.KZ;
     const float2 zk = buf[(k == Nz ? 0 : k) * ld + line];
     const int km = (Nz - k) % Nz;
     const float2 zc = buf[(km < 0 ? km + Nz : km) * ld + line];
@@ -730,7 +802,7 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis 
   __syncthreads();
   const float2 *src = reinterpret_cast<const float2 *>(w.s1) + line0 * g.KZ;
   for (int e = tid; e < L * Nz; e += PSWF_THREADS) {
-    const int line = e / Nz, k = e - line * Nz;
+    const int line = fdiv(e, g.div_nz), k = e - line * Nz;
     float2 z = make_float2(0.f, 0.f);
     if (line < nl) {
       const float2 xk = k < g.KZ ? src[int64_t(line) * g.KZ + k] : make_float2(0.f, 0.f);
@@ -749,7 +821,7 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis 
   lds_fft<1, 16>(buf, ax, llog, ld, tw, tid);
   float2 *dst = reinterpret_cast<float2 *>(w.grid) + line0 * Nz;
   for (int e = tid; e < nl * Nz; e += PSWF_THREADS) {
-    const int line = e / Nz, n = e - line * Nz;
+    const int line = fdiv(e, g.div_nz), n = e - line * Nz;
     dst[e] = buf[n * ld + line];
   }
 }
@@ -757,15 +829,19 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis 
 // ---------------------------------------------------------------------------
 // Gather (adjoint of step i): one workgroup per tile; the tile's grid region
 // plus a P-1 halo is staged in LDS per channel group.  Eight lanes serve one
-// atom (lane = window z offset), summing the (x, y) plane with the
-// separable weights and their derivatives, then reducing over z.
+// atom (lane = window offset l): each lane evaluates the window and its
+// derivative at its own offset on the three axes and the group exchanges
+// them by shuffles; then lane l sums the (x, y) plane of z-offset l with the
+// separable weights and the group reduces over z.
 //   phi_i   = sum_n pg(n) W(n h - r_i)
 //   F_i     = q_i sum_n pg(n) grad W(n h - r_i)
 // mode 1: forces/potentials; mode 2: adjoint (grad_q = g phi, grad_r = -g F).
+constexpr int kGatherThreads = 512;
+
 template <int P>
-__global__ __launch_bounds__(PSWF_THREADS) void k_gather(Geo g, Tables t, Work w, float *__restrict__ fout,
-                                                          float *__restrict__ pout, int mode,
-                                                          const double *__restrict__ grad) {
+__global__ __launch_bounds__(kGatherThreads) void k_gather(Geo g, Tables t, Work w, float *__restrict__ fout,
+                                                            float *__restrict__ pout, int mode,
+                                                            const double *__restrict__ grad) {
   extern __shared__ float smem[];
   const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
   const int EX = Bx + P - 1, EY = By + P - 1, EZ = Bz + P - 1;
@@ -779,58 +855,62 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_gather(Geo g, Tables t, Work w
   if (s == e) return;
   const int cz = cell % g.nc[2], cy = (cell / g.nc[2]) % g.nc[1], cx = cell / (g.nc[2] * g.nc[1]);
   const int t0[3] = {cx * Bx, cy * By, cz * Bz};
-  for (int k = tid; k < kWinSeg * (kWinDeg + 1); k += PSWF_THREADS) wcf[k] = t.win[k];
+  for (int k = tid; k < kWinSeg * (kWinDeg + 1); k += kGatherThreads) wcf[k] = t.win[k];
   const int lz = tid & 7;
-  const int nchunks = (e - s + 31) / 32;
+  constexpr int kAtomsPerBatch = kGatherThreads / 8;
+  const int nchunks = (e - s + kAtomsPerBatch - 1) / kAtomsPerBatch;
 
   for (int cg0 = 0; cg0 < g.C; cg0 += g.CG_gather) {
     const int ncg = min(g.CG_gather, g.C - cg0);
     __syncthreads();
-    for (int k = tid; k < ncg * EX * EY * EZ; k += PSWF_THREADS) {
-      const int c = k / (EX * EY * EZ);
-      int r = k - c * EX * EY * EZ;
-      const int x = r / (EY * EZ);
-      r -= x * EY * EZ;
-      const int y = r / EZ, z = r - y * EZ;
-      int gx = t0[0] + x, gy = t0[1] + y, gz = t0[2] + z;
-      if (gx >= g.M[0]) gx -= g.M[0];
-      if (gy >= g.M[1]) gy -= g.M[1];
-      if (gz >= g.M[2]) gz -= g.M[2];
-      tile[c * chan + x * plane + y * SZ + z] =
-          w.grid[((int64_t(cg0 + c) * g.M[0] + gx) * g.M[1] + gy) * g.M[2] + gz];
+    // rows of EZ contiguous floats; one row per half-wave step, no divisions
+    {
+      const int hw = tid >> 5, hl = tid & 31, nhw = kGatherThreads / 32;
+      for (int c = 0; c < ncg; ++c)
+        for (int x = 0; x < EX; ++x) {
+          int gx = t0[0] + x;
+          if (gx >= g.M[0]) gx -= g.M[0];
+          for (int y = hw; y < EY; y += nhw) {
+            int gy = t0[1] + y;
+            if (gy >= g.M[1]) gy -= g.M[1];
+            const float *src = w.grid + ((int64_t(cg0 + c) * g.M[0] + gx) * g.M[1] + gy) * g.M[2];
+            float *dst = tile + c * chan + x * plane + y * SZ;
+            for (int z = hl; z < EZ; z += 32) {
+              int gz = t0[2] + z;
+              if (gz >= g.M[2]) gz -= g.M[2];
+              dst[z] = src[gz];
+            }
+          }
+        }
     }
     __syncthreads();
     const bool last = cg0 + ncg >= g.C;
     for (int ch = 0; ch < nchunks; ++ch) {
-      const int a = s + ch * 32 + (tid >> 3);
+      const int a = s + ch * kAtomsPerBatch + (tid >> 3);
       const bool active = a < e;
-      float wx[P], dwx[P], wy[P], dwy[P];
-      float wz = 0.f, dwz = 0.f;
       int ox = 0, oy = 0, oz = 0;
+      float2 vx = make_float2(0.f, 0.f), vy = vx, vz = vx;
       if (active) {
         const float4 r = reinterpret_cast<const float4 *>(w.rec_a)[a];
         const unsigned pk = __float_as_uint(r.w);
         ox = unpack_n0(pk, 0) - t0[0];
         oy = unpack_n0(pk, 1) - t0[1];
         oz = unpack_n0(pk, 2) - t0[2];
-#pragma unroll
-        for (int l = 0; l < P; ++l) {
-          float2 vx = win_eval_d(wcf, (2.0f * (l + r.x)) / P - 1.0f);
-          float2 vy = win_eval_d(wcf, (2.0f * (l + r.y)) / P - 1.0f);
-          wx[l] = vx.x;
-          dwx[l] = vx.y * g.dwin[0];
-          wy[l] = vy.x;
-          dwy[l] = vy.y * g.dwin[1];
-        }
         if (lz < P) {
-          float2 vz = win_eval_d(wcf, (2.0f * (lz + r.z)) / P - 1.0f);
-          wz = vz.x;
-          dwz = vz.y * g.dwin[2];
+          vx = win_eval_d(wcf, (2.0f * (lz + r.x)) / P - 1.0f);
+          vy = win_eval_d(wcf, (2.0f * (lz + r.y)) / P - 1.0f);
+          vz = win_eval_d(wcf, (2.0f * (lz + r.z)) / P - 1.0f);
         }
-      } else {
-#pragma unroll
-        for (int l = 0; l < P; ++l) wx[l] = dwx[l] = wy[l] = dwy[l] = 0.f;
       }
+      float wx[P], dwx[P], wy[P], dwy[P];
+#pragma unroll
+      for (int l = 0; l < P; ++l) {
+        wx[l] = __shfl(vx.x, l, 8);
+        dwx[l] = __shfl(vx.y, l, 8) * g.dwin[0];
+        wy[l] = __shfl(vy.x, l, 8);
+        dwy[l] = __shfl(vy.y, l, 8) * g.dwin[1];
+      }
+      const float wz = vz.x, dwz = vz.y * g.dwin[2];
       float f[3] = {0.f, 0.f, 0.f};
       for (int c = 0; c < ncg; ++c) {
         float sp = 0.f, sx = 0.f, sy = 0.f;
@@ -945,10 +1025,13 @@ static inline unsigned nblocks(int64_t n, int per) { return unsigned((n + per - 
   } while (0)
 
 size_t spread_lds_bytes(const Geo &g, int ncg) {
-  const size_t plane = size_t(g.B[1]) * (g.B[2] + 1);
-  return (size_t(ncg) * g.B[0] * plane + kWinSeg * (kWinDeg + 1)) * 4 + 3 * kSpreadChunk * 4 +
-         size_t(kSpreadChunk) * 3 * g.P * 4 + size_t(kSpreadChunk) * kSpreadCGMax * 4;
+  (void)ncg;
+  const size_t staging = size_t(kSpreadChunk) * (kSpreadCGM + 3 * g.P + 1) + kWinSeg * (kWinDeg + 1);
+  const size_t outtile = size_t(g.B[0]) * g.B[1] * g.B[2];
+  return std::max(staging, outtile) * 4;
 }
+int spread_max_channels() { return kSpreadCGM; }
+int spread_max_blocks() { return kSpreadNBW * kSpreadThreads / 64; }
 size_t gather_lds_bytes(const Geo &g, int ncg) {
   const size_t EX = g.B[0] + g.P - 1, EY = g.B[1] + g.P - 1, EZ = g.B[2] + g.P - 1;
   return (size_t(ncg) * EX * EY * (EZ + 1) + kWinSeg * (kWinDeg + 1)) * 4;
@@ -1014,47 +1097,45 @@ hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t
 }
 
 template <int P>
-static hipError_t spread_p(const Geo &g, const Tables &t, const Work &w, hipStream_t st) {
-  for (int cg0 = 0; cg0 < g.C; cg0 += g.CG_spread) {
-    const int ncg = std::min(g.CG_spread, g.C - cg0);
-    hipError_t e = lds_request(reinterpret_cast<const void *>(&k_spread<P>), spread_lds_bytes(g, ncg));
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_spread<P>, dim3(g.ncell), dim3(PSWF_THREADS), spread_lds_bytes(g, ncg), st, g, t,
-                       w, cg0, ncg);
-    LAUNCH_CHECK();
-  }
+static hipError_t spread_p(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
+  hipError_t e = lds_request(reinterpret_cast<const void *>(&k_spread<P>), spread_lds_bytes(g, ncg));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_spread<P>, dim3(g.ncell), dim3(kSpreadThreads), spread_lds_bytes(g, ncg), st, g, t, w,
+                     cg0, ncg);
+  LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t enqueue_spread(const Geo &g, const Tables &t, const Work &w, hipStream_t st) {
+hipError_t launch_spread(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
   switch (g.P) {
-    case 2: return spread_p<2>(g, t, w, st);
-    case 3: return spread_p<3>(g, t, w, st);
-    case 4: return spread_p<4>(g, t, w, st);
-    case 5: return spread_p<5>(g, t, w, st);
-    case 6: return spread_p<6>(g, t, w, st);
-    case 7: return spread_p<7>(g, t, w, st);
-    case 8: return spread_p<8>(g, t, w, st);
-    case 9: return spread_p<9>(g, t, w, st);
-    case 10: return spread_p<10>(g, t, w, st);
+    case 2: return spread_p<2>(g, t, w, cg0, ncg, st);
+    case 3: return spread_p<3>(g, t, w, cg0, ncg, st);
+    case 4: return spread_p<4>(g, t, w, cg0, ncg, st);
+    case 5: return spread_p<5>(g, t, w, cg0, ncg, st);
+    case 6: return spread_p<6>(g, t, w, cg0, ncg, st);
+    case 7: return spread_p<7>(g, t, w, cg0, ncg, st);
+    case 8: return spread_p<8>(g, t, w, cg0, ncg, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t enqueue_forward_fft(const Geo &g, const Tables &t, const FftAxis &az, const FftAxis &ay,
-                               const Work &w, hipStream_t st) {
+hipError_t launch_zfwd(const Geo &g, const Tables &t, const FftAxis &az, const Work &w, hipStream_t st) {
   const int64_t lines = int64_t(g.C) * g.M[0] * g.M[1];
   hipLaunchKernelGGL(k_zfwd, dim3(nblocks(lines, g.zlines)), dim3(PSWF_THREADS), zpass_lds_bytes(g), st, g, t,
                      az, w, lines);
   LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_yfwd(const Geo &g, const Tables &t, const FftAxis &ay, const Work &w, hipStream_t st) {
   hipLaunchKernelGGL(k_yfwd, dim3(nblocks(g.KZ, g.kb), g.C * g.M[0]), dim3(PSWF_THREADS), ypass_lds_bytes(g),
                      st, g, t, ay, w);
   LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t enqueue_xmul(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int mode,
-                        const double *grad, hipStream_t st) {
+hipError_t launch_xmul(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int mode,
+                       const double *grad, hipStream_t st) {
   if (g.nxblk == 0) return hipSuccess;
   hipLaunchKernelGGL(k_xmul, dim3(g.nxblk, g.C), dim3(PSWF_THREADS), xpass_lds_bytes(g), st, g, t, ax, w, mode,
                      grad);
@@ -1062,11 +1143,14 @@ hipError_t enqueue_xmul(const Geo &g, const Tables &t, const FftAxis &ax, const 
   return hipSuccess;
 }
 
-hipError_t enqueue_inverse_fft(const Geo &g, const Tables &t, const FftAxis &az, const FftAxis &ay,
-                               const Work &w, hipStream_t st) {
+hipError_t launch_yinv(const Geo &g, const Tables &t, const FftAxis &ay, const Work &w, hipStream_t st) {
   hipLaunchKernelGGL(k_yinv, dim3(nblocks(g.KZ, g.kb), g.C * g.M[0]), dim3(PSWF_THREADS), ypass_lds_bytes(g),
                      st, g, t, ay, w);
   LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_zinv(const Geo &g, const Tables &t, const FftAxis &az, const Work &w, hipStream_t st) {
   const int64_t lines = int64_t(g.C) * g.M[0] * g.M[1];
   hipLaunchKernelGGL(k_zinv, dim3(nblocks(lines, g.zlines)), dim3(PSWF_THREADS), zpass_lds_bytes(g), st, g, t,
                      az, w, lines);
@@ -1079,14 +1163,14 @@ static hipError_t gather_p(const Geo &g, const Tables &t, const Work &w, float *
                            const double *grad, hipStream_t st) {
   hipError_t e = lds_request(reinterpret_cast<const void *>(&k_gather<P>), gather_lds_bytes(g, g.CG_gather));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gather<P>, dim3(g.ncell), dim3(PSWF_THREADS), gather_lds_bytes(g, g.CG_gather), st, g, t,
-                     w, f, pot, mode, grad);
+  hipLaunchKernelGGL(k_gather<P>, dim3(g.ncell), dim3(kGatherThreads), gather_lds_bytes(g, g.CG_gather), st, g,
+                     t, w, f, pot, mode, grad);
   LAUNCH_CHECK();
   return hipSuccess;
 }
 
-hipError_t enqueue_gather(const Geo &g, const Tables &t, const Work &w, float *forces, float *pot, int mode,
-                          const double *grad, hipStream_t st) {
+hipError_t launch_gather(const Geo &g, const Tables &t, const Work &w, float *forces, float *pot, int mode,
+                         const double *grad, hipStream_t st) {
   if (g.N == 0) return hipSuccess;
   switch (g.P) {
     case 2: return gather_p<2>(g, t, w, forces, pot, mode, grad, st);
@@ -1100,8 +1184,8 @@ hipError_t enqueue_gather(const Geo &g, const Tables &t, const Work &w, float *f
   return hipErrorInvalidValue;
 }
 
-hipError_t enqueue_finalize(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial,
-                            hipStream_t st) {
+hipError_t launch_finalize(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial,
+                           hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(PSWF_THREADS), 0, st, g, t, w, energy, virial);
   LAUNCH_CHECK();
   return hipSuccess;

@@ -17,20 +17,22 @@ size_t zpass_lds_bytes(const Geo &g);
 size_t ypass_lds_bytes(const Geo &g);
 size_t xpass_lds_bytes(const Geo &g);
 int qsum_blocks(const Geo &g);
+int spread_max_channels();   // channels per spreading launch
+int spread_max_blocks();     // 4x4x8 blocks a spreading tile may hold
 
 hipError_t enqueue_sort(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st);
 hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t st);
-hipError_t enqueue_spread(const Geo &g, const Tables &t, const Work &w, hipStream_t st);
-hipError_t enqueue_forward_fft(const Geo &g, const Tables &t, const FftAxis &az, const FftAxis &ay,
-                               const Work &w, hipStream_t st);
+hipError_t launch_spread(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st);
+hipError_t launch_zfwd(const Geo &g, const Tables &t, const FftAxis &az, const Work &w, hipStream_t st);
+hipError_t launch_yfwd(const Geo &g, const Tables &t, const FftAxis &ay, const Work &w, hipStream_t st);
 // mode 0: energy only, 1: energy + potential grid, 2: adjoint scaled by grad[c]
-hipError_t enqueue_xmul(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int mode,
-                        const double *grad, hipStream_t st);
-hipError_t enqueue_inverse_fft(const Geo &g, const Tables &t, const FftAxis &az, const FftAxis &ay,
-                               const Work &w, hipStream_t st);
-hipError_t enqueue_gather(const Geo &g, const Tables &t, const Work &w, float *forces, float *pot, int mode,
-                          const double *grad, hipStream_t st);
-hipError_t enqueue_finalize(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial,
-                            hipStream_t st);
+hipError_t launch_xmul(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int mode,
+                       const double *grad, hipStream_t st);
+hipError_t launch_yinv(const Geo &g, const Tables &t, const FftAxis &ay, const Work &w, hipStream_t st);
+hipError_t launch_zinv(const Geo &g, const Tables &t, const FftAxis &az, const Work &w, hipStream_t st);
+hipError_t launch_gather(const Geo &g, const Tables &t, const Work &w, float *forces, float *pot, int mode,
+                         const double *grad, hipStream_t st);
+hipError_t launch_finalize(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial,
+                           hipStream_t st);
 
 }  // namespace pswf

@@ -12,7 +12,9 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "device_types.hpp"
@@ -47,7 +49,12 @@ FftAxis factorise(int n, bool *ok) {
   while (m % 5 == 0) { r.push_back(5); m /= 5; }
   *ok = (m == 1) && int(r.size()) <= kMaxRadixStages;
   ax.nst = int(r.size());
-  for (size_t i = 0; i < r.size() && i < size_t(kMaxRadixStages); ++i) ax.rad[i] = r[i];
+  int ns = 1;
+  for (size_t i = 0; i < r.size() && i < size_t(kMaxRadixStages); ++i) {
+    ax.rad[i] = r[i];
+    ax.nsdiv[i] = make_fastdiv(ns);
+    ns *= r[i];
+  }
   return ax;
 }
 
@@ -79,6 +86,10 @@ struct pswflr_plan_s {
   size_t off_grid = 0, off_s1 = 0, off_s2 = 0, off_rec_a = 0, off_rec_b = 0, off_q_a = 0, off_q_b = 0,
          off_perm_a = 0, off_perm_b = 0, off_cell_of = 0, off_slot = 0, off_count = 0, off_start = 0,
          off_facc = 0, off_epart = 0, off_qpart = 0, off_qsum = 0, ws_bytes = 0;
+  // optional per-stage event timing (measurement only)
+  bool prof = false;
+  std::mutex prof_mu;
+  std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> prof_ev;
 };
 
 namespace {
@@ -165,31 +176,64 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   g.FY = std::min(int(std::floor(kc * p.box[1] / (2 * kPi))), (M[1] - 1) / 2);
   g.NY = 2 * g.FY + 1;
 
-  // tiles: B_x ~ 8, B_y, B_z ~ 16, each >= P - 1 unless the axis is one tile
-  const int target[3] = {8, 16, 16};
-  for (int a = 0; a < 3; ++a) {
-    const int lo = std::max(P - 1, 1);
-    int b = divisor_in(M[a], lo, std::max(target[a], lo));
-    if (b == 0) b = divisor_in(M[a], lo, 32);
-    if (b == 0) b = M[a];  // one tile spans the axis
-    g.B[a] = b;
-    g.nc[a] = M[a] / b;
+  // tiles (binning cells): over all divisor triples, maximise the fraction
+  // of useful window work prod B / (B + P - 1) subject to the spreading
+  // kernel's register blocks and the gather's LDS halo tile; ties go to the
+  // larger tile
+  {
+    auto divisors = [](int m) {
+      std::vector<int> d;
+      for (int k = 1; k <= m; ++k)
+        if (m % k == 0) d.push_back(k);
+      return d;
+    };
+    double best_eff = -1.0;
+    long best_vol = 0;
+    int best[3] = {0, 0, 0};
+    for (int bx : divisors(M[0]))
+      for (int by : divisors(M[1]))
+        for (int bz : divisors(M[2])) {
+          const int nblk = ((bx + 3) / 4) * ((by + 3) / 4) * ((bz + 7) / 8);
+          if (nblk > spread_max_blocks()) continue;
+          const size_t glds = (size_t(bx + P - 1) * (by + P - 1) * (bz + P) + 96) * 4;
+          if (glds > 160 * 1024) continue;
+          const double eff = double(bx) / (bx + P - 1) * double(by) / (by + P - 1) * double(bz) / (bz + P - 1);
+          const long vol = long(bx) * by * bz;
+          if (eff > best_eff + 1e-12 || (std::fabs(eff - best_eff) <= 1e-12 && vol > best_vol)) {
+            best_eff = eff;
+            best_vol = vol;
+            best[0] = bx; best[1] = by; best[2] = bz;
+          }
+        }
+    if (best_eff < 0) return fail(PSWFLR_ERR_UNSUPPORTED, "no tile shape fits this grid");
+    for (int a = 0; a < 3; ++a) {
+      g.B[a] = best[a];
+      g.nc[a] = M[a] / best[a];
+    }
   }
   g.ncell = g.nc[0] * g.nc[1] * g.nc[2];
-  // channel groups sized to LDS (64 KiB preferred, 160 KiB hard limit)
-  g.CG_spread = 1;
-  for (int k = std::min(C, 4); k >= 1; --k)
-    if (spread_lds_bytes(g, k) <= 64 * 1024) { g.CG_spread = k; break; }
-  if (spread_lds_bytes(g, g.CG_spread) > 160 * 1024) return fail(PSWFLR_ERR_UNSUPPORTED, "spread tile too large");
-  g.CG_gather = 1;
-  for (int k = C; k >= 1; --k)
-    if (gather_lds_bytes(g, k) <= 64 * 1024) { g.CG_gather = k; break; }
-  if (gather_lds_bytes(g, g.CG_gather) > 160 * 1024) return fail(PSWFLR_ERR_UNSUPPORTED, "gather tile too large");
-
+  // channel groups: the spreading kernel keeps kSpreadCGM channels in
+  // registers; the gather stages as many halo tiles as fit the 160 KiB of
+  // LDS a gfx950 workgroup may use.  Groups are balanced.
+  const size_t kLds = 160 * 1024;
+  g.CG_spread = std::min(C, spread_max_channels());
+  g.CG_gather = 0;
+  for (int k = std::min(C, 16); k >= 1; --k)
+    if (gather_lds_bytes(g, k) <= kLds) { g.CG_gather = k; break; }
+  if (g.CG_gather == 0) return fail(PSWFLR_ERR_UNSUPPORTED, "gather tile too large for LDS");
+  {
+    int ng = (C + g.CG_spread - 1) / g.CG_spread;
+    g.CG_spread = (C + ng - 1) / ng;
+    ng = (C + g.CG_gather - 1) / g.CG_gather;
+    g.CG_gather = (C + ng - 1) / ng;
+  }
+  if (spread_lds_bytes(g, g.CG_spread) > kLds) return fail(PSWFLR_ERR_UNSUPPORTED, "spread staging exceeds LDS");
   g.kb = std::max(1, std::min(16, floor_pow2(4096 / std::max(M[0], M[1]))));
   g.kb_log2 = 0;
   while ((1 << g.kb_log2) < g.kb) ++g.kb_log2;
   g.zlines = std::max(1, floor_pow2(4096 / g.Nz));
+  g.div_nz = make_fastdiv(g.Nz);
+  g.div_kz = make_fastdiv(g.KZ);
   bool ok1, ok2, ok3;
   pl.az = factorise(g.Nz, &ok1);
   pl.ay = factorise(M[1], &ok2);
@@ -340,6 +384,10 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   inf.n_channels = C;
   inf.kz_keep = g.KZ;
   inf.ny_keep = g.NY;
+  inf.cg_spread = g.CG_spread;
+  inf.cg_gather = g.CG_gather;
+  inf.xcols = 0;
+  for (size_t i = 2; i < xblk.size(); i += 4) inf.xcols += xblk[i];
   inf.max_atoms = max_atoms;
   inf.workspace_bytes = pl.ws_bytes;
   inf.grid_offset = pl.off_grid;
@@ -434,6 +482,68 @@ pswflr_status pswflr_plan_destroy(pswflr_plan plan) {
   return PSWFLR_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Runs one stage (one kernel launch, or the small sort/charge-sum groups)
+// and, while profiling is on, brackets it with events on the same stream.
+struct StageRunner {
+  pswflr_plan_s *pl;
+  hipStream_t st;
+  template <class F>
+  hipError_t operator()(int stage, F &&f) {
+    if (!pl->prof) return f();
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return hipErrorOutOfMemory;
+    (void)hipEventRecord(a, st);
+    hipError_t e = f();
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lock(pl->prof_mu);
+    pl->prof_ev.emplace_back(stage, a, b);
+    return e;
+  }
+};
+
+hipError_t run_forward(pswflr_plan_s *pl, hipStream_t st, const Geo &g, const Work &w, const float *pos,
+                       const float *q, int xmode, double *energy, double *virial) {
+  StageRunner run{pl, st};
+  const Tables &t = pl->tab;
+  hipError_t e;
+  if ((e = run(PSWFLR_STAGE_SORT, [&] { return enqueue_sort(g, w, pos, q, st); })) != hipSuccess) return e;
+  if ((e = run(PSWFLR_STAGE_QSUM, [&] { return enqueue_qsum(g, w, q, st); })) != hipSuccess) return e;
+  for (int cg0 = 0; cg0 < g.C; cg0 += g.CG_spread) {
+    const int ncg = std::min(g.CG_spread, g.C - cg0);
+    if ((e = run(PSWFLR_STAGE_SPREAD, [&] { return launch_spread(g, t, w, cg0, ncg, st); })) != hipSuccess)
+      return e;
+  }
+  if ((e = run(PSWFLR_STAGE_FFT_Z, [&] { return launch_zfwd(g, t, pl->az, w, st); })) != hipSuccess) return e;
+  if ((e = run(PSWFLR_STAGE_FFT_Y, [&] { return launch_yfwd(g, t, pl->ay, w, st); })) != hipSuccess) return e;
+  if ((e = run(PSWFLR_STAGE_FFT_X_SCALE, [&] { return launch_xmul(g, t, pl->ax, w, xmode, nullptr, st); })) !=
+      hipSuccess)
+    return e;
+  return run(PSWFLR_STAGE_REDUCE, [&] { return launch_finalize(g, t, w, energy, virial, st); });
+}
+
+hipError_t run_adjoint(pswflr_plan_s *pl, hipStream_t st, const Geo &g, const Work &w, float *forces,
+                       float *pot, int mode, const double *grad) {
+  StageRunner run{pl, st};
+  const Tables &t = pl->tab;
+  hipError_t e;
+  if (mode == 2) {
+    if ((e = run(PSWFLR_STAGE_FFT_X_SCALE, [&] { return launch_xmul(g, t, pl->ax, w, 2, grad, st); })) !=
+        hipSuccess)
+      return e;
+  }
+  if ((e = run(PSWFLR_STAGE_IFFT_Y, [&] { return launch_yinv(g, t, pl->ay, w, st); })) != hipSuccess) return e;
+  if ((e = run(PSWFLR_STAGE_IFFT_Z, [&] { return launch_zinv(g, t, pl->az, w, st); })) != hipSuccess) return e;
+  return run(PSWFLR_STAGE_GATHER, [&] { return launch_gather(g, t, w, forces, pot, mode, grad, st); });
+}
+
+}  // namespace
+
+extern "C" {
+
 pswflr_status pswflr_execute(pswflr_plan plan, pswflr_stream stream, void *workspace, size_t ws_bytes,
                              int64_t n_atoms, const float *pos, const float *q, double *energy, float *forces,
                              double *virial, float *potential) {
@@ -444,18 +554,10 @@ pswflr_status pswflr_execute(pswflr_plan plan, pswflr_stream stream, void *works
   Geo g = plan->geo;
   g.N = n_atoms;
   Work w = carve(*plan, workspace, n_atoms);
-  const Tables &t = plan->tab;
   const bool adjoint = forces || potential;
-  HIPCHK(enqueue_sort(g, w, pos, q, st));
-  HIPCHK(enqueue_qsum(g, w, q, st));
-  HIPCHK(enqueue_spread(g, t, w, st));
-  HIPCHK(enqueue_forward_fft(g, t, plan->az, plan->ay, w, st));
-  HIPCHK(enqueue_xmul(g, t, plan->ax, w, adjoint ? 1 : 0, nullptr, st));
-  HIPCHK(enqueue_finalize(g, t, w, energy, virial, st));
-  if (adjoint) {
-    HIPCHK(enqueue_inverse_fft(g, t, plan->az, plan->ay, w, st));
-    HIPCHK(enqueue_gather(g, t, w, forces, potential, 1, nullptr, st));
-  }
+  hipError_t e = run_forward(plan, st, g, w, pos, q, adjoint ? 1 : 0, energy, virial);
+  if (e == hipSuccess && adjoint) e = run_adjoint(plan, st, g, w, forces, potential, 1, nullptr);
+  if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return PSWFLR_OK;
 }
 
@@ -470,11 +572,37 @@ pswflr_status pswflr_backward(pswflr_plan plan, pswflr_stream stream, void *work
   Geo g = plan->geo;
   g.N = n_atoms;
   Work w = carve(*plan, workspace, n_atoms);
-  const Tables &t = plan->tab;
-  HIPCHK(enqueue_xmul(g, t, plan->ax, w, 2, grad_energy, st));
-  HIPCHK(enqueue_inverse_fft(g, t, plan->az, plan->ay, w, st));
-  HIPCHK(enqueue_gather(g, t, w, grad_pos, grad_q, 2, grad_energy, st));
+  hipError_t e = run_adjoint(plan, st, g, w, grad_pos, grad_q, 2, grad_energy);
+  if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return PSWFLR_OK;
+}
+
+pswflr_status pswflr_profile_enable(pswflr_plan plan, int enable) {
+  if (!plan) return fail(PSWFLR_ERR_INVALID_ARG, "plan is NULL");
+  plan->prof = enable != 0;
+  return PSWFLR_OK;
+}
+
+pswflr_status pswflr_profile_read(pswflr_plan plan, double *ms_total, int64_t *launches) {
+  if (!plan || !ms_total || !launches) return fail(PSWFLR_ERR_INVALID_ARG, "NULL argument");
+  for (int i = 0; i < PSWFLR_NUM_STAGES; ++i) {
+    ms_total[i] = 0.0;
+    launches[i] = 0;
+  }
+  std::lock_guard<std::mutex> lock(plan->prof_mu);
+  pswflr_status s = PSWFLR_OK;
+  for (auto &ev : plan->prof_ev) {
+    hipEvent_t a = std::get<1>(ev), b = std::get<2>(ev);
+    float ms = 0.f;
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+      s = fail(PSWFLR_ERR_DEVICE, "event timing failed");
+    ms_total[std::get<0>(ev)] += ms;
+    launches[std::get<0>(ev)] += 1;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  plan->prof_ev.clear();
+  return s;
 }
 
 pswflr_status pswflr_batch_workspace(int32_t n, const pswflr_plan *plans, const int64_t *n_atoms, size_t *bytes) {
