@@ -78,6 +78,9 @@ typedef struct {
   int32_t support;                   /* P points per axis, 2..8; 0: from tol  */
   double c_spread;                   /* window bandwidth; <= 0: minimiser of a
                                         force-weighted aliasing estimate     */
+  int32_t tile[3];                   /* binning/spreading tile edges; 0: the
+                                        planner's choice.  Each must divide
+                                        the grid edge (autotuner knob)       */
   uint32_t flags;                    /* reserved, 0                           */
 } pswflr_params;
 

@@ -29,6 +29,7 @@ class Params(ctypes.Structure):
         ("grid", ctypes.c_int32 * 3),
         ("support", ctypes.c_int32),
         ("c_spread", ctypes.c_double),
+        ("tile", ctypes.c_int32 * 3),
         ("flags", ctypes.c_uint32),
     ]
 
@@ -116,7 +117,7 @@ def check(status):
         raise PswflrError(status, buf.value.decode(errors="replace"))
 
 
-def make_params(box, ps, r_c, c=0.0, tol=1e-5, grid=None, support=0, c_spread=0.0):
+def make_params(box, ps, r_c, c=0.0, tol=1e-5, grid=None, support=0, c_spread=0.0, tile=None):
     prm = Params()
     ps = list(ps)
     if not 1 <= len(ps) <= MAX_CHANNELS:
@@ -132,5 +133,7 @@ def make_params(box, ps, r_c, c=0.0, tol=1e-5, grid=None, support=0, c_spread=0.
     prm.tol = float(tol or 0.0)
     prm.support = int(support or 0)
     prm.c_spread = float(c_spread or 0.0)
+    for a in range(3):
+        prm.tile[a] = int(tile[a]) if tile is not None else 0
     prm.flags = 0
     return prm

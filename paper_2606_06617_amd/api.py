@@ -27,9 +27,9 @@ class Plan:
     """
 
     def __init__(self, box, ps, r_c=5.0, c=12.024, tol=1e-5, grid=None, support=0, c_spread=0.0,
-                 max_atoms=1):
+                 max_atoms=1, tile=None):
         L = _lib.lib()
-        self.params = _lib.make_params(box, ps, r_c, c, tol, grid, support, c_spread)
+        self.params = _lib.make_params(box, ps, r_c, c, tol, grid, support, c_spread, tile)
         h = ctypes.c_void_p()
         _lib.check(L.pswflr_plan_create(ctypes.byref(self.params), int(max_atoms), ctypes.byref(h)))
         self.handle = h
@@ -108,6 +108,41 @@ class Plan:
                                         _ptr(pos), _ptr(q), _ptr(g), _ptr(gq), _ptr(gp))
         _lib.check(st)
         return gq, gp
+
+
+def execute_batch(plans, inputs, forces=True, virial=True, potential=False, workspace=None, stream=None):
+    """Evaluate many structures in one batched call (one launch per stage
+    over all structures).  inputs: list of (pos [N,3], q [C,N]) CUDA tensors,
+    one per plan.  Returns a list of output dicts as Plan.execute does."""
+    L = _lib.lib()
+    n = len(plans)
+    if n != len(inputs):
+        raise ValueError("one (pos, q) per plan")
+    handles = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    natoms = (ctypes.c_int64 * n)(*[int(x[0].shape[0]) for x in inputs])
+    need = ctypes.c_size_t()
+    _lib.check(L.pswflr_batch_workspace(n, handles, natoms, ctypes.byref(need)))
+    dev = inputs[0][0].device if n else torch.device("cuda")
+    ws = workspace if workspace is not None else torch.empty(max(1, need.value), dtype=torch.uint8, device=dev)
+    ios = (_lib.IO * n)()
+    outs = []
+    for i, (plan, (pos, q)) in enumerate(zip(plans, inputs)):
+        _check_inputs(pos, q, plan.C, plan.max_atoms)
+        N = pos.shape[0]
+        o = {"energy": torch.empty(3 * plan.C, dtype=torch.float64, device=dev),
+             "forces": torch.empty((N, 3), dtype=torch.float32, device=dev) if forces else None,
+             "virial": torch.empty(6, dtype=torch.float64, device=dev) if virial else None,
+             "potential": torch.empty((plan.C, N), dtype=torch.float32, device=dev) if potential else None}
+        ios[i].n_atoms = N
+        ios[i].pos = pos.data_ptr()
+        ios[i].q = q.data_ptr()
+        ios[i].energy = o["energy"].data_ptr()
+        ios[i].forces = o["forces"].data_ptr() if forces else None
+        ios[i].virial = o["virial"].data_ptr() if virial else None
+        ios[i].potential = o["potential"].data_ptr() if potential else None
+        outs.append(o)
+    _lib.check(L.pswflr_execute_batch(n, handles, ios, _stream(stream), _ptr(ws), ws.numel()))
+    return outs, ws
 
 
 def _check_inputs(pos, q, C, max_atoms):

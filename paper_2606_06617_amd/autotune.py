@@ -1,0 +1,122 @@
+"""Autotuner for the tile schedule of the spreading / gather / binning cells.
+
+For a (grid, support P, channels C, atom count) the planner's default tile
+maximises the fraction of useful window work prod B / (B + P - 1).  That
+ignores parallelism (few large tiles leave CUs idle on small grids) and the
+cost balance between spreading and gathering, so the autotuner times a short
+list of candidate tiles on the device with the caller's stream and keeps
+the fastest.  Results are cached in a JSON file (path from
+PSWFLR_AUTOTUNE_CACHE, default ~/.cache/pswflr/autotune.json) keyed by the
+device architecture, grid, P, C and the atom count rounded to a power of two.
+"""
+import json
+import math
+import os
+import threading
+import time
+
+KERNEL_VERSION = 3
+_LOCK = threading.Lock()
+
+
+def cache_path():
+    return os.environ.get("PSWFLR_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "pswflr", "autotune.json"))
+
+
+def _load():
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(db):
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _divisors(m):
+    return [d for d in range(1, m + 1) if m % d == 0]
+
+
+def candidate_tiles(grid, P, max_blocks=16, lds=160 * 1024, limit=6):
+    """Feasible tiles ranked by useful-work fraction, plus the most parallel
+    feasible ones (small grids)."""
+    feas = []
+    for bx in _divisors(grid[0]):
+        for by in _divisors(grid[1]):
+            for bz in _divisors(grid[2]):
+                nblk = ((bx + 3) // 4) * ((by + 3) // 4) * ((bz + 7) // 8)
+                if nblk > max_blocks:
+                    continue
+                if ((bx + P - 1) * (by + P - 1) * (bz + P) + 96) * 4 > lds:
+                    continue
+                eff = bx / (bx + P - 1) * by / (by + P - 1) * bz / (bz + P - 1)
+                ncell = (grid[0] // bx) * (grid[1] // by) * (grid[2] // bz)
+                feas.append((eff, bx * by * bz, ncell, (bx, by, bz)))
+    by_eff = sorted(feas, key=lambda t: (-t[0], -t[1]))
+    out = [t[3] for t in by_eff[:limit]]
+    # for small grids also try shapes that give at least one tile per CU
+    par = sorted([t for t in feas if t[2] >= 256], key=lambda t: (-t[0], -t[1]))
+    for t in par[:2]:
+        if t[3] not in out:
+            out.append(t[3])
+    return out
+
+
+def key_for(arch, grid, P, C, n_atoms):
+    nb = 1 << max(0, int(math.ceil(math.log2(max(1, n_atoms)))))
+    return "%s|%dx%dx%d|P%d|C%d|N%d|v%d" % (arch, grid[0], grid[1], grid[2], P, C, nb, KERNEL_VERSION)
+
+
+def lookup(arch, grid, P, C, n_atoms):
+    with _LOCK:
+        return _load().get(key_for(arch, grid, P, C, n_atoms))
+
+
+def tune(pos, q, box, ps, r_c=5.0, c=12.024, grid=None, support=0, c_spread=0.0, reps=5, verbose=False):
+    """Time candidate tiles for this structure shape; cache and return the best
+    tile (a 3-tuple).  pos, q: CUDA tensors as for Plan.execute."""
+    import torch
+
+    from .api import Plan
+    base = Plan(box, ps, r_c=r_c, c=c, grid=grid, support=support, c_spread=c_spread,
+                max_atoms=max(1, pos.shape[0]))
+    g, P, C = base.info["grid"], base.info["support"], base.info["n_channels"]
+    arch = torch.cuda.get_device_properties(pos.device).gcnArchName.split(":")[0]
+    key = key_for(arch, g, P, C, pos.shape[0])
+    results = {}
+    for tile in candidate_tiles(g, P):
+        try:
+            plan = Plan(box, ps, r_c=r_c, c=c, grid=g, support=P, c_spread=base.info["c_spread"],
+                        max_atoms=max(1, pos.shape[0]), tile=tile)
+        except RuntimeError:
+            continue
+        ws = plan.new_workspace(pos.device)
+        out = None
+        for _ in range(2):
+            out = plan.execute(pos, q, forces=True, virial=True, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = plan.execute(pos, q, forces=True, virial=True, workspace=ws)
+        torch.cuda.synchronize()
+        results[tile] = (time.perf_counter() - t0) / reps
+        del out, ws
+        if verbose:
+            print("tile", tile, "%.3f ms" % (results[tile] * 1e3), flush=True)
+    best = min(results, key=results.get)
+    with _LOCK:
+        db = _load()
+        db[key] = {"tile": list(best), "ms": results[best] * 1e3,
+                   "default_ms": results.get(tuple(base.info["tile"]), None) and
+                   results[tuple(base.info["tile"])] * 1e3,
+                   "tried": {"%dx%dx%d" % t: round(v * 1e3, 4) for t, v in results.items()}}
+        _store(db)
+    return best

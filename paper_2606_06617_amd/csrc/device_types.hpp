@@ -118,4 +118,27 @@ struct Work {
   double *qsum;           // [C][2]: Q_net, Q_self
 };
 
+// One structure of a batched call: everything a stage body needs.
+struct BatchItem {
+  Geo g;
+  Tables t;
+  Work w;
+  FftAxis az, ay, ax;
+  const float *pos;
+  const float *q;
+  double *energy;
+  float *forces;
+  double *virial;
+  float *pot;
+  int qblocks;
+  int pad_;
+  int64_t nlines;
+};
+
+// Stages of one evaluation, in launch order.
+enum BatchStage {
+  kBsZero = 0, kBsBin, kBsScan, kBsScatter, kBsOrder, kBsQsum, kBsQreduce, kBsSpread, kBsZfwd, kBsYfwd,
+  kBsXmul, kBsFinalize, kBsYinv, kBsZinv, kBsGather, kNumBatchStages
+};
+
 }  // namespace pswf

@@ -50,68 +50,141 @@ void gauss_legendre(int n, double a, double b, std::vector<double> &x, std::vect
   }
 }
 
-// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (row-major).
-// On return a holds the eigenvalues on its diagonal, v the eigenvectors in
-// its columns.
-static void jacobi_eigen(int n, std::vector<double> &a, std::vector<double> &v) {
-  v.assign(size_t(n) * n, 0.0);
-  for (int i = 0; i < n; ++i) v[size_t(i) * n + i] = 1.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        double e = a[size_t(i) * n + j] * a[size_t(i) * n + j];
-        tot += e;
-        if (i != j) off += e;
-      }
-    if (off <= 1e-30 * tot) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        double apq = a[size_t(p) * n + q];
-        if (std::fabs(apq) < 1e-300) continue;
-        double app = a[size_t(p) * n + p], aqq = a[size_t(q) * n + q];
-        double theta = (aqq - app) / (2.0 * apq);
-        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
-        for (int k = 0; k < n; ++k) {
-          double akp = a[size_t(k) * n + p], akq = a[size_t(k) * n + q];
-          a[size_t(k) * n + p] = cs * akp - sn * akq;
-          a[size_t(k) * n + q] = sn * akp + cs * akq;
-        }
-        for (int k = 0; k < n; ++k) {
-          double apk = a[size_t(p) * n + k], aqk = a[size_t(q) * n + k];
-          a[size_t(p) * n + k] = cs * apk - sn * aqk;
-          a[size_t(q) * n + k] = sn * apk + cs * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          double vkp = v[size_t(k) * n + p], vkq = v[size_t(k) * n + q];
-          v[size_t(k) * n + p] = cs * vkp - sn * vkq;
-          v[size_t(k) * n + q] = sn * vkp + cs * vkq;
-        }
-      }
+// LU factorisation with partial pivoting (row-major n x n), in place.
+static bool lu_factor(int n, std::vector<double> &a, std::vector<int> &piv) {
+  piv.resize(n);
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(a[size_t(i) * n + k]) > std::fabs(a[size_t(p) * n + k])) p = i;
+    piv[k] = p;
+    if (a[size_t(p) * n + k] == 0.0) return false;
+    if (p != k)
+      for (int j = 0; j < n; ++j) std::swap(a[size_t(k) * n + j], a[size_t(p) * n + j]);
+    const double inv = 1.0 / a[size_t(k) * n + k];
+    for (int i = k + 1; i < n; ++i) {
+      const double f = a[size_t(i) * n + k] * inv;
+      a[size_t(i) * n + k] = f;
+      if (f != 0.0)
+        for (int j = k + 1; j < n; ++j) a[size_t(i) * n + j] -= f * a[size_t(k) * n + j];
+    }
+  }
+  return true;
+}
+
+static void lu_solve(int n, const std::vector<double> &lu, const std::vector<int> &piv, std::vector<double> &b) {
+  // the factorisation swapped whole rows (multipliers included): apply all
+  // interchanges to b first, then the unit-lower solve
+  for (int k = 0; k < n; ++k) std::swap(b[k], b[piv[k]]);
+  for (int k = 0; k < n; ++k)
+    for (int i = k + 1; i < n; ++i) b[i] -= lu[size_t(i) * n + k] * b[k];
+  for (int i = n - 1; i >= 0; --i) {
+    double s = b[i];
+    for (int j = i + 1; j < n; ++j) s -= lu[size_t(i) * n + j] * b[j];
+    b[i] = s / lu[size_t(i) * n + i];
   }
 }
 
-Prolate::Prolate(double c, int nodes) : c_(c) {
+// Chebyshev-Gauss-Lobatto nodes x_j = cos(pi j / N) and the collocation
+// differentiation matrix (the classical closed form with the negative-sum
+// diagonal).
+static void cheb_matrix(int N, std::vector<double> &x, std::vector<double> &D) {
+  const int n = N + 1;
+  x.resize(n);
+  for (int j = 0; j < n; ++j) x[j] = std::cos(kPi * j / N);
+  x[N / 2] = (N % 2 == 0) ? 0.0 : x[N / 2];
+  std::vector<double> cw(n, 1.0);
+  cw[0] = cw[N] = 2.0;
+  D.assign(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double rowsum = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (i == j) continue;
+      const double sgn = ((i + j) % 2 == 0) ? 1.0 : -1.0;
+      const double v = (cw[i] / cw[j]) * sgn / (x[i] - x[j]);
+      D[size_t(i) * n + j] = v;
+      rowsum += v;
+    }
+    D[size_t(i) * n + i] = -rowsum;
+  }
+}
+
+// psi_0^c from the prolate differential operator (it commutes with F_c and
+// has well-separated eigenvalues chi_0 < chi_2 < ..., unlike the eigenvalues
+// of F_c itself, which cluster near sqrt(2 pi / c) for large c):
+//   L psi = -(1 - x^2) psi'' + 2 x psi' + c^2 x^2 psi = chi psi,
+// collocated at Chebyshev-Gauss-Lobatto points (the endpoint rows enforce
+// regularity), smallest eigenvalue by inverse iteration from an even start.
+Prolate::Prolate(double c, int N) : c_(c) {
   if (!(c > 0.0)) throw std::invalid_argument("prolate bandwidth must be positive");
-  gauss_legendre(nodes, 0.0, 1.0, t_, w_);
-  const int n = nodes;
-  std::vector<double> a(size_t(n) * n), v;
+  if (N % 2) ++N;
+  const int n = N + 1;
+  std::vector<double> D;
+  cheb_matrix(N, x_, D);
+  std::vector<double> D2(size_t(n) * n, 0.0);
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j)
-      a[size_t(i) * n + j] = 2.0 * std::sqrt(w_[i] * w_[j]) * std::cos(c * t_[i] * t_[j]);
-  jacobi_eigen(n, a, v);
-  int best = 0;
-  for (int i = 1; i < n; ++i)
-    if (a[size_t(i) * n + i] > a[size_t(best) * n + best]) best = i;
-  lam_ = a[size_t(best) * n + best];
-  std::vector<double> psi(n);
-  for (int j = 0; j < n; ++j) psi[j] = v[size_t(j) * n + best] / std::sqrt(w_[j]);
-  double psi0 = 0.0;
-  for (int j = 0; j < n; ++j) psi0 += 2.0 / lam_ * w_[j] * psi[j];
-  wpsi_.resize(n);
-  for (int j = 0; j < n; ++j) wpsi_[j] = 2.0 / lam_ * w_[j] * psi[j] / psi0;
+    for (int k = 0; k < n; ++k) {
+      const double dik = D[size_t(i) * n + k];
+      if (dik == 0.0) continue;
+      for (int j = 0; j < n; ++j) D2[size_t(i) * n + j] += dik * D[size_t(k) * n + j];
+    }
+  std::vector<double> A(size_t(n) * n), Ash;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double v = -(1.0 - x_[i] * x_[i]) * D2[size_t(i) * n + j] + 2.0 * x_[i] * D[size_t(i) * n + j];
+      if (i == j) v += c * c * x_[i] * x_[i];
+      A[size_t(i) * n + j] = v;
+    }
+  // shift near chi_0 (about c^2/3 for small c and c - 3/4 for large c; the
+  // next even eigenvalue is ~4c higher, the odd one ~2c), iterate in the
+  // even subspace (the nodes are symmetric: x_{N-j} = -x_j)
+  const double sigma = std::min(c * c / 3.0, c - 0.75);
+  Ash = A;
+  for (int i = 0; i < n; ++i) Ash[size_t(i) * n + i] -= sigma;
+  std::vector<int> piv;
+  if (!lu_factor(n, Ash, piv)) throw std::runtime_error("prolate collocation matrix is singular");
+  std::vector<double> v(n, 1.0);
+  for (int it = 0; it < 60; ++it) {
+    lu_solve(n, Ash, piv, v);
+    for (int i = 0; i < n / 2; ++i) {
+      const double e = 0.5 * (v[i] + v[N - i]);
+      v[i] = v[N - i] = e;
+    }
+    double nrm = 0.0;
+    for (double e : v) nrm = std::max(nrm, std::fabs(e));
+    for (double &e : v) e /= nrm;
+  }
+  // Rayleigh-like estimate of chi at x = 0 row is ill-posed; use the
+  // residual-minimising quotient over all nodes
+  std::vector<double> Av(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Av[i] += A[size_t(i) * n + j] * v[j];
+  double num = 0.0, den = 0.0;
+  for (int i = 0; i < n; ++i) {
+    num += Av[i] * v[i];
+    den += v[i] * v[i];
+  }
+  chi_ = num / den;
+  const double v0 = v[N / 2];
+  psi_.resize(n);
+  for (int i = 0; i < n; ++i) psi_[i] = v[i] / v0;
+  // derivatives at the nodes
+  dpsi_.assign(n, 0.0);
+  d2psi_.assign(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      dpsi_[i] += D[size_t(i) * n + j] * psi_[j];
+      d2psi_[i] += D2[size_t(i) * n + j] * psi_[j];
+    }
+  // barycentric weights
+  bw_.resize(n);
+  for (int j = 0; j < n; ++j) bw_[j] = ((j % 2) ? -1.0 : 1.0) * ((j == 0 || j == N) ? 0.5 : 1.0);
+  // lambda_0 = int_{-1}^{1} psi (eq. psidefinit at x = 0), Gauss quadrature
   gauss_legendre(64, 0.0, 1.0, qx_, qw_);
+  std::vector<double> gx, gw;
+  gauss_legendre(96, -1.0, 1.0, gx, gw);
+  lam_ = 0.0;
+  for (size_t i = 0; i < gx.size(); ++i) lam_ += gw[i] * (*this)(gx[i]);
   // quadrature for the window transform at frequencies up to ~200
   std::vector<double> fw;
   gauss_legendre(320, 0.0, 1.0, fx_, fw);
@@ -119,33 +192,40 @@ Prolate::Prolate(double c, int nodes) : c_(c) {
   for (size_t i = 0; i < fx_.size(); ++i) fwpsi_[i] = 2.0 * fw[i] * (*this)(fx_[i]);
 }
 
-double Prolate::operator()(double x) const {
-  double s = 0.0;
-  for (size_t j = 0; j < t_.size(); ++j) s += wpsi_[j] * std::cos(c_ * x * t_[j]);
-  return s;
-}
-double Prolate::d1(double x) const {
-  double s = 0.0;
-  for (size_t j = 0; j < t_.size(); ++j) s -= wpsi_[j] * c_ * t_[j] * std::sin(c_ * x * t_[j]);
-  return s;
-}
-double Prolate::d2(double x) const {
-  double s = 0.0;
-  for (size_t j = 0; j < t_.size(); ++j) {
-    double a = c_ * t_[j];
-    s -= wpsi_[j] * a * a * std::cos(a * x);
+double Prolate::bary(const std::vector<double> &f, double x) const {
+  double num = 0.0, den = 0.0;
+  for (size_t j = 0; j < x_.size(); ++j) {
+    const double dx = x - x_[j];
+    if (dx == 0.0) return f[j];
+    const double t = bw_[j] / dx;
+    num += t * f[j];
+    den += t;
   }
-  return s;
+  return num / den;
 }
+
+double Prolate::operator()(double x) const { return bary(psi_, x); }
+double Prolate::d1(double x) const { return bary(dpsi_, x); }
+double Prolate::d2(double x) const { return bary(d2psi_, x); }
+
+// psi^(n)(0) for even n: psi''(0) = -chi from the ODE at x = 0, and the
+// n-times differentiated ODE at 0:
+//   psi^(n+2)(0) = (n (n + 1) - chi) psi^(n)(0) + c^2 n (n - 1) psi^(n-2)(0).
 double Prolate::deriv0(int n) const {
-  double s = 0.0;
-  double sign = ((n / 2) % 2 == 0) ? 1.0 : -1.0;
-  for (size_t j = 0; j < t_.size(); ++j) s += wpsi_[j] * std::pow(c_ * t_[j], n);
-  return sign * s;
+  if (n == 0) return 1.0;
+  if (n % 2) return 0.0;
+  double prev = 1.0, cur = -chi_;  // psi(0), psi''(0)
+  for (int m = 2; m < n; m += 2) {
+    const double next = (m * (m + 1) - chi_) * cur + c_ * c_ * m * (m - 1) * prev;
+    prev = cur;
+    cur = next;
+  }
+  return cur;
 }
+
 double Prolate::I0(double k) const {
   double s = 0.0;
-  for (size_t j = 0; j < t_.size(); ++j) s += wpsi_[j] * std::sin(c_ * k * t_[j]) / (c_ * t_[j]);
+  for (size_t i = 0; i < qx_.size(); ++i) s += k * qw_[i] * (*this)(k * qx_[i]);
   return s;
 }
 double Prolate::J1(double k) const {
@@ -435,6 +515,9 @@ double estimate_spread_error(int P, double eta, double c_s, double c_moll) {
 double choose_c_spread(int P, double eta, double c_moll) {
   static std::mutex mu;
   static std::map<std::tuple<int, long, long>, double> cache;
+  // eta is rounded up to a multiple of 0.005 (a slightly coarser grid is the
+  // conservative side) so that boxes of nearby shapes share one search
+  eta = std::ceil(eta * 200.0 - 1e-9) / 200.0;
   auto key = std::make_tuple(P, std::lround(eta * 1e4), std::lround(c_moll * 1e4));
   {
     std::lock_guard<std::mutex> lock(mu);

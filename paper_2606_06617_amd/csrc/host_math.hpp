@@ -15,15 +15,13 @@ void gauss_legendre(int n, double a, double b, std::vector<double> &x, std::vect
 
 // Order-zero prolate spheroidal wave function psi_0^c with psi(0) = 1
 // (Methods, "Prolate spheroidal wave functions", eqs. formula and
-// psidefinit).  Represented by the Nystrom discretisation of the integral
-// eigen-relation itself: on Gauss nodes t_j of [0, 1], the even part of
-// F_c acts as 2 int_0^1 phi(t) cos(c x t) dt, whose symmetric matrix
-// 2 sqrt(w_i w_j) cos(c t_i t_j) has lambda_0 as its largest eigenvalue.
-// The eigenvector gives psi at the nodes and the relation itself extends
-// psi to every x:  psi(x) = (2 / lambda_0) sum_j w_j psi_j cos(c x t_j).
+// psidefinit).  Computed from the prolate differential operator, which
+// commutes with F_c, by Chebyshev collocation and inverse iteration;
+// evaluated anywhere by barycentric interpolation; lambda_0 = int psi
+// (eq. psidefinit at x = 0).
 class Prolate {
  public:
-  explicit Prolate(double c, int nodes = 72);
+  explicit Prolate(double c, int N = 96);
   double c() const { return c_; }
   double lambda() const { return lam_; }
   double C0() const { return 0.5 * lam_; }          // int_0^1 psi
@@ -31,7 +29,7 @@ class Prolate {
   double d1(double x) const;                        // psi'(x)
   double d2(double x) const;                        // psi''(x)
   double deriv0(int n) const;                       // psi^(n)(0), n even
-  double chi() const { return -deriv0(2); }         // prolate ODE eigenvalue
+  double chi() const { return chi_; }               // prolate ODE eigenvalue
   double I0(double k) const;                        // int_0^k psi
   double J1(double k) const;                        // int_k^1 u psi(u) du
   double J3(double k) const;                        // int_k^1 u^3 psi(u) du
@@ -41,10 +39,11 @@ class Prolate {
   double window_ft(double s) const;
 
  private:
-  double c_ = 0, lam_ = 0;
-  std::vector<double> t_, w_, wpsi_;  // nodes, weights, (2/lambda) w_j psi_j
-  std::vector<double> qx_, qw_;       // quadrature on [0,1] for integrals
-  std::vector<double> fx_, fwpsi_;    // window-transform nodes, 2 w psi
+  double bary(const std::vector<double> &f, double x) const;
+  double c_ = 0, lam_ = 0, chi_ = 0;
+  std::vector<double> x_, bw_, psi_, dpsi_, d2psi_;  // collocation nodes, values
+  std::vector<double> qx_, qw_;                      // quadrature on [0,1] for integrals
+  std::vector<double> fx_, fwpsi_;                   // window-transform nodes, 2 w psi
 };
 
 // Shared, cached instances (plan creation is cheap after the first call).

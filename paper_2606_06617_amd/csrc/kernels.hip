@@ -118,28 +118,36 @@ struct Dft<8, S> {
   }
 };
 
-// One Stockham stage over `nlines` independent lines of length n stored in
+// One Stockham stage over the lines owned by one wave (LW = 2^lw_log2
+// lines, wave w owns lines [w LW, (w + 1) LW)), each of length n stored in
 // LDS as buf[idx * ld + line].  Butterfly j of a line reads x[j + r n/R],
 // twiddles by exp(S 2 pi i r k / (ns R)) with k = j mod ns, and writes
 // y[(j / ns) ns R + k + u ns]: the output of the last stage is in natural
-// order.  Results are held in registers across a barrier, so the stage is
-// in place.  Each thread owns at most MAXE elements.
+// order.  Results are held in registers across a wave-scope fence, so the
+// stage is in place and waves never wait for each other.  Each lane owns at
+// most MAXE elements.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <int R, int S, int MAXE>
-__device__ __forceinline__ void fft_stage(float2 *buf, int n, int ns, const FastDiv &nsd, int nl_log2, int ld,
-                                          const float2 *tw, int tid) {
+__device__ __forceinline__ void fft_stage(float2 *buf, int n, int ns, const FastDiv &nsd, int lw_log2, int ld,
+                                          const float2 *tw, int lane, int wave) {
   constexpr int MAXB = (MAXE + R - 1) / R;
   const int nb = n / R;
-  const int total = nb << nl_log2;
+  const int total = nb << lw_log2;
   const int twstep = n / (ns * R);
+  const int line0 = wave << lw_log2;
   float2 v[MAXB][R];
   int oidx[MAXB];
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int b = tid + i * PSWF_THREADS;
+    const int b = lane + i * 64;
     oidx[i] = -1;
     if (b < total) {
-      const int line = b & ((1 << nl_log2) - 1);
-      const int j = b >> nl_log2;
+      const int line = line0 + (b & ((1 << lw_log2) - 1));
+      const int j = b >> lw_log2;
       const int jq = fdiv(j, nsd);
       const int k = j - jq * ns;
 #pragma unroll
@@ -156,7 +164,7 @@ __device__ __forceinline__ void fft_stage(float2 *buf, int n, int ns, const Fast
       oidx[i] = (jq * ns * R + k) * ld + line;
     }
   }
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
     if (oidx[i] >= 0) {
@@ -164,24 +172,25 @@ __device__ __forceinline__ void fft_stage(float2 *buf, int n, int ns, const Fast
       for (int r = 0; r < R; ++r) buf[oidx[i] + r * ns * ld] = v[i][r];
     }
   }
-  __syncthreads();
+  wave_sync();
 }
 
-// Full transform of all lines in LDS.  S = -1 forward, +1 inverse
-// (unnormalised in both directions).  tw[m] = exp(-2 pi i m / n).
+// Full transform of the wave's lines.  S = -1 forward, +1 inverse
+// (unnormalised in both directions).  tw[m] = exp(-2 pi i m / n).  The
+// caller synchronises the workgroup before (data loaded) and after.
 template <int S, int MAXE>
-__device__ void lds_fft(float2 *buf, const FftAxis &ax, int nl_log2, int ld, const float2 *tw,
-                        int tid) {
+__device__ void lds_fft(float2 *buf, const FftAxis &ax, int lw_log2, int ld, const float2 *tw, int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
   int ns = 1;
   for (int s = 0; s < ax.nst; ++s) {
     const int R = ax.rad[s];
     const FastDiv &nsd = ax.nsdiv[s];
     switch (R) {
-      case 2: fft_stage<2, S, MAXE>(buf, ax.n, ns, nsd, nl_log2, ld, tw, tid); break;
-      case 3: fft_stage<3, S, MAXE>(buf, ax.n, ns, nsd, nl_log2, ld, tw, tid); break;
-      case 4: fft_stage<4, S, MAXE>(buf, ax.n, ns, nsd, nl_log2, ld, tw, tid); break;
-      case 5: fft_stage<5, S, MAXE>(buf, ax.n, ns, nsd, nl_log2, ld, tw, tid); break;
-      default: fft_stage<8, S, MAXE>(buf, ax.n, ns, nsd, nl_log2, ld, tw, tid); break;
+      case 2: fft_stage<2, S, MAXE>(buf, ax.n, ns, nsd, lw_log2, ld, tw, lane, wave); break;
+      case 3: fft_stage<3, S, MAXE>(buf, ax.n, ns, nsd, lw_log2, ld, tw, lane, wave); break;
+      case 4: fft_stage<4, S, MAXE>(buf, ax.n, ns, nsd, lw_log2, ld, tw, lane, wave); break;
+      case 5: fft_stage<5, S, MAXE>(buf, ax.n, ns, nsd, lw_log2, ld, tw, lane, wave); break;
+      default: fft_stage<8, S, MAXE>(buf, ax.n, ns, nsd, lw_log2, ld, tw, lane, wave); break;
     }
     ns *= R;
   }
@@ -222,13 +231,15 @@ __device__ __forceinline__ int unpack_n0(unsigned v, int a) { return int((v >> (
 // ---------------------------------------------------------------------------
 // Binning: each atom is assigned to the tile holding the first node of its
 // window, n0 = ceil(x/h - P/2) (mod M); delta = n0 - (x/h - P/2) in [0, 1).
-__global__ __launch_bounds__(PSWF_THREADS) void k_zero_int(int *p, int n) {
-  int i = blockIdx.x * PSWF_THREADS + threadIdx.x;
+__device__ __forceinline__ void zero_int_body(int *p, int n, int bx) {
+  int i = bx * PSWF_THREADS + threadIdx.x;
   if (i < n) p[i] = 0;
 }
 
-__global__ __launch_bounds__(PSWF_THREADS) void k_bin(Geo g, Work w, const float *__restrict__ pos) {
-  const int64_t i = int64_t(blockIdx.x) * PSWF_THREADS + threadIdx.x;
+__global__ __launch_bounds__(PSWF_THREADS) void k_zero_int(int *p, int n) { zero_int_body(p, n, blockIdx.x); }
+
+__device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const float *__restrict__ pos, int bx) {
+  const int64_t i = int64_t(bx) * PSWF_THREADS + threadIdx.x;
   if (i >= g.N) return;
   unsigned packed = 0;
   float dl[3];
@@ -257,8 +268,12 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_bin(Geo g, Work w, const float
   reinterpret_cast<float4 *>(w.rec_a)[i] = r;  // staged in caller order
 }
 
+__global__ __launch_bounds__(PSWF_THREADS) void k_bin(Geo g, Work w, const float *__restrict__ pos) {
+  bin_body(g, w, pos, blockIdx.x);
+}
+
 // exclusive scan of cell counts (single block)
-__global__ __launch_bounds__(1024) void k_scan(Work w, int ncell, int64_t N) {
+__device__ __forceinline__ void scan_body(const Work &w, int ncell, int64_t N) {
   __shared__ int part[1024];
   __shared__ int carry;
   if (threadIdx.x == 0) carry = 0;
@@ -282,9 +297,11 @@ __global__ __launch_bounds__(1024) void k_scan(Work w, int ncell, int64_t N) {
   if (threadIdx.x == 0) w.cell_start[ncell] = int(N);
 }
 
+__global__ __launch_bounds__(1024) void k_scan(Work w, int ncell, int64_t N) { scan_body(w, ncell, N); }
+
 // scatter into cell order (arbitrary order inside a cell)
-__global__ __launch_bounds__(PSWF_THREADS) void k_scatter(Geo g, Work w, const float *__restrict__ q) {
-  const int64_t i = int64_t(blockIdx.x) * PSWF_THREADS + threadIdx.x;
+__device__ __forceinline__ void scatter_body(const Geo &g, const Work &w, const float *__restrict__ q, int bx) {
+  const int64_t i = int64_t(bx) * PSWF_THREADS + threadIdx.x;
   if (i >= g.N) return;
   const int dst = w.cell_start[w.cell_of[i]] + w.slot[i];
   reinterpret_cast<float4 *>(w.rec_b)[dst] = reinterpret_cast<const float4 *>(w.rec_a)[i];
@@ -292,10 +309,14 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_scatter(Geo g, Work w, const f
   for (int c = 0; c < g.C; ++c) w.q_b[int64_t(c) * g.N + dst] = q[int64_t(c) * g.N + i];
 }
 
+__global__ __launch_bounds__(PSWF_THREADS) void k_scatter(Geo g, Work w, const float *__restrict__ q) {
+  scatter_body(g, w, q, blockIdx.x);
+}
+
 // deterministic order inside each cell: ascending caller index
-__global__ __launch_bounds__(PSWF_THREADS) void k_order(Geo g, Work w) {
+__device__ __forceinline__ void order_body(const Geo &g, const Work &w, int bx) {
   __shared__ int keys[2048];
-  const int cell = blockIdx.x;
+  const int cell = bx;
   const int s = w.cell_start[cell], e = w.cell_start[cell + 1];
   const int n = e - s;
   if (n <= 0) return;
@@ -315,12 +336,13 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_order(Geo g, Work w) {
   }
 }
 
+__global__ __launch_bounds__(PSWF_THREADS) void k_order(Geo g, Work w) { order_body(g, w, blockIdx.x); }
+
 // per-channel sum q and sum q^2 (FP64 block partials, fixed order)
-__global__ __launch_bounds__(PSWF_THREADS) void k_qsum(Geo g, Work w, const float *__restrict__ q,
-                                                        int chunk) {
+__device__ __forceinline__ void qsum_body(const Geo &g, const Work &w, const float *__restrict__ q, int chunk, int bx, int by) {
   __shared__ double s0[PSWF_THREADS], s1[PSWF_THREADS];
-  const int c = blockIdx.y;
-  const int64_t b0 = int64_t(blockIdx.x) * chunk;
+  const int c = by;
+  const int64_t b0 = int64_t(bx) * chunk;
   double a = 0.0, b = 0.0;
   for (int64_t i = b0 + threadIdx.x; i < min(b0 + chunk, g.N); i += PSWF_THREADS) {
     double v = double(q[int64_t(c) * g.N + i]);
@@ -338,12 +360,16 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_qsum(Geo g, Work w, const floa
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    w.qpart[(int64_t(blockIdx.x) * g.C + c) * 2 + 0] = s0[0];
-    w.qpart[(int64_t(blockIdx.x) * g.C + c) * 2 + 1] = s1[0];
+    w.qpart[(int64_t(bx) * g.C + c) * 2 + 0] = s0[0];
+    w.qpart[(int64_t(bx) * g.C + c) * 2 + 1] = s1[0];
   }
 }
 
-__global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nblk) {
+__global__ __launch_bounds__(PSWF_THREADS) void k_qsum(Geo g, Work w, const float *__restrict__ q, int chunk) {
+  qsum_body(g, w, q, chunk, blockIdx.x, blockIdx.y);
+}
+
+__device__ __forceinline__ void qreduce_body(const Geo &g, const Work &w, int nblk) {
   __shared__ double s0[PSWF_THREADS], s1[PSWF_THREADS];
   for (int c = 0; c < g.C; ++c) {
     double a = 0.0, b = 0.0;
@@ -368,6 +394,8 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nbl
     __syncthreads();
   }
 }
+
+__global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nblk) { qreduce_body(g, w, nblk); }
 
 // ---------------------------------------------------------------------------
 // Spread (step i), output-stationary.  One workgroup of 8 waves per tile.
@@ -394,7 +422,7 @@ __device__ __forceinline__ bool win_meets(int o, int S, int d, int P, int M) {
 }
 
 template <int P>
-__global__ __launch_bounds__(kSpreadThreads) void k_spread(Geo g, Tables t, Work w, int cg0, int ncg) {
+__device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, int bx) {
   extern __shared__ float smem[];
   float *cq = smem;                                                   // [chunk][CGM]
   float *cw = cq + kSpreadChunk * kSpreadCGM;                         // [chunk][3][P]
@@ -406,7 +434,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(Geo g, Tables t, Work
   const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
   const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int cell = blockIdx.x;
+  const int cell = bx;
   const int cz = cell % g.nc[2], cy = (cell / g.nc[2]) % g.nc[1], cx = cell / (g.nc[2] * g.nc[1]);
   const int t0[3] = {cx * Bx, cy * By, cz * Bz};
   const int ctile[3] = {cx, cy, cz};
@@ -569,12 +597,16 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(Geo g, Tables t, Work
   (void)nt;
 }
 
+template <int P>
+__global__ __launch_bounds__(kSpreadThreads) void k_spread(Geo g, Tables t, Work w, int cg0, int ncg) {
+  spread_body<P>(g, t, w, cg0, ncg, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // z R2C (step ii, first axis): lines of M_z reals -> KZ complex columns.
 // The real line is packed as z_n = x_2n + i x_2n+1, transformed with length
 // Nz = M_z / 2 and split: X_k = E_k + exp(-2 pi i k / M_z) O_k.
-__global__ __launch_bounds__(PSWF_THREADS) void k_zfwd(Geo g, Tables t, FftAxis ax, Work w,
-                                                        int64_t nlines_total) {
+__device__ __forceinline__ void zfwd_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int64_t nlines_total, int bx) {
   extern __shared__ float smem[];
   const int L = g.zlines, ld = L + 1, Nz = g.Nz;
   int llog = 0;
@@ -583,7 +615,7 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zfwd(Geo g, Tables t, FftAxis 
   float2 *tw = buf + Nz * ld;
   float2 *twr = tw + Nz;
   const int tid = threadIdx.x;
-  const int64_t line0 = int64_t(blockIdx.x) * L;
+  const int64_t line0 = int64_t(bx) * L;
   const int nl = int(min(int64_t(L), nlines_total - line0));
   for (int e = tid; e < Nz; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_z)[e];
   for (int e = tid; e <= Nz; e += PSWF_THREADS) twr[e] = reinterpret_cast<const float2 *>(t.tw_zr)[e];
@@ -593,7 +625,8 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zfwd(Geo g, Tables t, FftAxis 
     buf[n * ld + line] = line < nl ? src[e] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  lds_fft<-1, 16>(buf, ax, llog, ld, tw, tid);
+  lds_fft<-1, 16>(buf, ax, llog - 2, ld, tw, tid);
+  __syncthreads();
   float2 *dst = reinterpret_cast<float2 *>(w.s1) + line0 * g.KZ;
   for (int e = tid; e < nl * g.KZ; e += PSWF_THREADS) {
     const int line = fdiv(e, g.div_kz), k = e - line * g.KZ;
@@ -607,16 +640,20 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zfwd(Geo g, Tables t, FftAxis 
   }
 }
 
+__global__ __launch_bounds__(PSWF_THREADS) void k_zfwd(Geo g, Tables t, FftAxis ax, Work w, int64_t nlines_total) {
+  zfwd_body(g, t, ax, w, nlines_total, blockIdx.x);
+}
+
 // y forward (step ii, second axis): plane (c, x), a block of kb z columns;
 // keeps only |f_y| <= FY.
-__global__ __launch_bounds__(PSWF_THREADS) void k_yfwd(Geo g, Tables t, FftAxis ax, Work w) {
+__device__ __forceinline__ void yfwd_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int bx, int by) {
   extern __shared__ float smem[];
   const int kb = g.kb, ld = kb + 1, My = g.M[1];
   float2 *buf = reinterpret_cast<float2 *>(smem);
   float2 *tw = buf + My * ld;
   const int tid = threadIdx.x;
-  const int kz0 = blockIdx.x * kb;
-  const int64_t plane = blockIdx.y;  // c * Mx + x
+  const int kz0 = bx * kb;
+  const int64_t plane = by;  // c * Mx + x
   const int ncol = min(kb, g.KZ - kz0);
   for (int e = tid; e < My; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_y)[e];
   const float2 *src = reinterpret_cast<const float2 *>(w.s1) + plane * My * g.KZ;
@@ -625,7 +662,8 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_yfwd(Geo g, Tables t, FftAxis 
     buf[y * ld + col] = col < ncol ? src[int64_t(y) * g.KZ + kz0 + col] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  lds_fft<-1, 16>(buf, ax, g.kb_log2, ld, tw, tid);
+  lds_fft<-1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
+  __syncthreads();
   float2 *dst = reinterpret_cast<float2 *>(w.s2) + plane * g.NY * g.KZ;
   for (int e = tid; e < g.NY * kb; e += PSWF_THREADS) {
     const int iy = e >> g.kb_log2, col = e & (kb - 1);
@@ -633,6 +671,10 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_yfwd(Geo g, Tables t, FftAxis 
     const int my = iy <= g.FY ? iy : My - g.NY + iy;
     dst[int64_t(iy) * g.KZ + kz0 + col] = buf[my * ld + col];
   }
+}
+
+__global__ __launch_bounds__(PSWF_THREADS) void k_yfwd(Geo g, Tables t, FftAxis ax, Work w) {
+  yfwd_body(g, t, ax, w, blockIdx.x, blockIdx.y);
 }
 
 // Fourier kernel at kappa: (Phi, Phi'/k) from the per-channel polynomials.
@@ -673,8 +715,7 @@ __device__ __forceinline__ float2 kernel_eval(const float *fc, const float *gc, 
 // FP64 block partials of the energy and virial, inverse x transform.
 // mode 0: energy only (no write-back), 1: full, 2: adjoint with the scale
 // grad[c] folded into the kernel.
-__global__ __launch_bounds__(PSWF_THREADS) void k_xmul(Geo g, Tables t, FftAxis ax, Work w, int mode,
-                                                        const double *__restrict__ grad) {
+__device__ __forceinline__ void xmul_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int mode, const double *__restrict__ grad, int bx, int by) {
   extern __shared__ float smem[];
   const int kb = g.kb, ld = kb + 1, Mx = g.M[0];
   float2 *buf = reinterpret_cast<float2 *>(smem);
@@ -683,7 +724,7 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_xmul(Geo g, Tables t, FftAxis 
   float *gc = fc + kKerCoef;
   __shared__ double red[7][PSWF_THREADS / 64];
   const int tid = threadIdx.x;
-  const int blk = blockIdx.x, c = blockIdx.y;
+  const int blk = bx, c = by;
   const int iy = t.xblk[4 * blk], kz0 = t.xblk[4 * blk + 1], ncol = t.xblk[4 * blk + 2];
   const KChan kc = t.kch[c];
   for (int e = tid; e < Mx; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_x)[e];
@@ -698,7 +739,8 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_xmul(Geo g, Tables t, FftAxis 
     buf[x * ld + col] = col < ncol ? col0[x * xstride + col] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  lds_fft<-1, 16>(buf, ax, g.kb_log2, ld, tw, tid);
+  lds_fft<-1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
+  __syncthreads();
 
   const int fy = iy <= g.FY ? iy : iy - g.NY;
   const float ky = fy * g.kunit[1];
@@ -746,22 +788,28 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_xmul(Geo g, Tables t, FftAxis 
     w.epart[(int64_t(c) * g.nxblk + blk) * 8 + tid] = s;
   }
   if (mode == 0) return;
-  lds_fft<1, 16>(buf, ax, g.kb_log2, ld, tw, tid);
+  lds_fft<1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
+  __syncthreads();
   for (int e = tid; e < Mx * kb; e += PSWF_THREADS) {
     const int x = e >> g.kb_log2, col = e & (kb - 1);
     if (col < ncol) col0[x * xstride + col] = buf[x * ld + col];
   }
 }
 
+__global__ __launch_bounds__(PSWF_THREADS) void k_xmul(Geo g, Tables t, FftAxis ax, Work w, int mode,
+                                                        const double *__restrict__ grad) {
+  xmul_body(g, t, ax, w, mode, grad, blockIdx.x, blockIdx.y);
+}
+
 // inverse y: kept rows (zero elsewhere and for columns the x pass skipped)
-__global__ __launch_bounds__(PSWF_THREADS) void k_yinv(Geo g, Tables t, FftAxis ax, Work w) {
+__device__ __forceinline__ void yinv_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int bx, int by) {
   extern __shared__ float smem[];
   const int kb = g.kb, ld = kb + 1, My = g.M[1];
   float2 *buf = reinterpret_cast<float2 *>(smem);
   float2 *tw = buf + My * ld;
   const int tid = threadIdx.x;
-  const int kz0 = blockIdx.x * kb;
-  const int64_t plane = blockIdx.y;
+  const int kz0 = bx * kb;
+  const int64_t plane = by;
   const int ncol = min(kb, g.KZ - kz0);
   for (int e = tid; e < My; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_y)[e];
   for (int e = tid; e < My * ld; e += PSWF_THREADS) buf[e] = make_float2(0.f, 0.f);
@@ -775,7 +823,8 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_yinv(Geo g, Tables t, FftAxis 
     buf[my * ld + col] = src[int64_t(iy) * g.KZ + kz];
   }
   __syncthreads();
-  lds_fft<1, 16>(buf, ax, g.kb_log2, ld, tw, tid);
+  lds_fft<1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
+  __syncthreads();
   float2 *dst = reinterpret_cast<float2 *>(w.s1) + plane * My * g.KZ;
   for (int e = tid; e < My * kb; e += PSWF_THREADS) {
     const int y = e >> g.kb_log2, col = e & (kb - 1);
@@ -783,10 +832,13 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_yinv(Geo g, Tables t, FftAxis 
   }
 }
 
+__global__ __launch_bounds__(PSWF_THREADS) void k_yinv(Geo g, Tables t, FftAxis ax, Work w) {
+  yinv_body(g, t, ax, w, blockIdx.x, blockIdx.y);
+}
+
 // z C2R: Z'_k = (X_k + conj X_{N-k}) + i exp(+2 pi i k / M_z)(X_k - conj X_{N-k}),
 // inverse transform of length Nz gives x_2m + i x_2m+1.
-__global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis ax, Work w,
-                                                        int64_t nlines_total) {
+__device__ __forceinline__ void zinv_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int64_t nlines_total, int bx) {
   extern __shared__ float smem[];
   const int L = g.zlines, ld = L + 1, Nz = g.Nz;
   int llog = 0;
@@ -795,7 +847,7 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis 
   float2 *tw = buf + Nz * ld;
   float2 *twr = tw + Nz;
   const int tid = threadIdx.x;
-  const int64_t line0 = int64_t(blockIdx.x) * L;
+  const int64_t line0 = int64_t(bx) * L;
   const int nl = int(min(int64_t(L), nlines_total - line0));
   for (int e = tid; e < Nz; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_z)[e];
   for (int e = tid; e <= Nz; e += PSWF_THREADS) twr[e] = reinterpret_cast<const float2 *>(t.tw_zr)[e];
@@ -818,12 +870,17 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis 
     buf[k * ld + line] = z;
   }
   __syncthreads();
-  lds_fft<1, 16>(buf, ax, llog, ld, tw, tid);
+  lds_fft<1, 16>(buf, ax, llog - 2, ld, tw, tid);
+  __syncthreads();
   float2 *dst = reinterpret_cast<float2 *>(w.grid) + line0 * Nz;
   for (int e = tid; e < nl * Nz; e += PSWF_THREADS) {
     const int line = fdiv(e, g.div_nz), n = e - line * Nz;
     dst[e] = buf[n * ld + line];
   }
+}
+
+__global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis ax, Work w, int64_t nlines_total) {
+  zinv_body(g, t, ax, w, nlines_total, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -839,9 +896,8 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis 
 constexpr int kGatherThreads = 512;
 
 template <int P>
-__global__ __launch_bounds__(kGatherThreads) void k_gather(Geo g, Tables t, Work w, float *__restrict__ fout,
-                                                            float *__restrict__ pout, int mode,
-                                                            const double *__restrict__ grad) {
+__device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const Work &w, float *__restrict__ fout,
+                                            float *__restrict__ pout, int mode, const double *__restrict__ grad, int bx) {
   extern __shared__ float smem[];
   const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
   const int EX = Bx + P - 1, EY = By + P - 1, EZ = Bz + P - 1;
@@ -850,7 +906,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(Geo g, Tables t, Work
   float *tile = smem;
   float *wcf = tile + g.CG_gather * chan;
   const int tid = threadIdx.x;
-  const int cell = blockIdx.x;
+  const int cell = bx;
   const int s = w.cell_start[cell], e = w.cell_start[cell + 1];
   if (s == e) return;
   const int cz = cell % g.nc[2], cy = (cell / g.nc[2]) % g.nc[1], cx = cell / (g.nc[2] * g.nc[1]);
@@ -974,9 +1030,15 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(Geo g, Tables t, Work
   }
 }
 
+template <int P>
+__global__ __launch_bounds__(kGatherThreads) void k_gather(Geo g, Tables t, Work w, float *__restrict__ fout,
+                                                            float *__restrict__ pout, int mode,
+                                                            const double *__restrict__ grad) {
+  gather_body<P>(g, t, w, fout, pout, mode, grad, blockIdx.x);
+}
+
 // Final FP64 reduction: energy [3C] (E_k, E_0, E_self) and virial [6].
-__global__ __launch_bounds__(PSWF_THREADS) void k_finalize(Geo g, Tables t, Work w, double *energy,
-                                                            double *virial) {
+__device__ __forceinline__ void finalize_body(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial) {
   __shared__ double red[8][PSWF_THREADS];
   __shared__ double vir[6];
   const int tid = threadIdx.x;
@@ -1012,6 +1074,10 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_finalize(Geo g, Tables t, Work
     __syncthreads();
   }
   if (virial && tid < 6) virial[tid] = vir[tid];
+}
+
+__global__ __launch_bounds__(PSWF_THREADS) void k_finalize(Geo g, Tables t, Work w, double *energy, double *virial) {
+  finalize_body(g, t, w, energy, virial);
 }
 
 // ---------------------------------------------------------------------------
@@ -1189,6 +1255,152 @@ hipError_t launch_finalize(const Geo &g, const Tables &t, const Work &w, double 
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(PSWF_THREADS), 0, st, g, t, w, energy, virial);
   LAUNCH_CHECK();
   return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: one launch per stage covers every structure of a batch.
+// prefix[s] is the first virtual block of structure s in this stage
+// (prefix[n] = total); a workgroup finds its structure by binary search.
+__device__ __forceinline__ int find_item(const int *__restrict__ prefix, int n, int b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int STAGE, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_batch(const BatchItem *__restrict__ items,
+                                                    const int *__restrict__ prefix, int n, int mode) {
+  const int b = blockIdx.x;
+  const int s = find_item(prefix, n, b);
+  const BatchItem &it = items[s];
+  const int vb = b - prefix[s];
+  const Geo &g = it.g;
+  switch (STAGE) {
+    case kBsZero: zero_int_body(it.w.cell_count, g.ncell, vb); break;
+    case kBsBin: bin_body(g, it.w, it.pos, vb); break;
+    case kBsScan: scan_body(it.w, g.ncell, g.N); break;
+    case kBsScatter: scatter_body(g, it.w, it.q, vb); break;
+    case kBsOrder: order_body(g, it.w, vb); break;
+    case kBsQsum: qsum_body(g, it.w, it.q, kQChunk, vb % it.qblocks, vb / it.qblocks); break;
+    case kBsQreduce: qreduce_body(g, it.w, it.qblocks); break;
+    case kBsSpread:
+      switch (g.P) {
+        case 2: spread_body<2>(g, it.t, it.w, 0, g.C, vb); break;
+        case 3: spread_body<3>(g, it.t, it.w, 0, g.C, vb); break;
+        case 4: spread_body<4>(g, it.t, it.w, 0, g.C, vb); break;
+        case 5: spread_body<5>(g, it.t, it.w, 0, g.C, vb); break;
+        case 6: spread_body<6>(g, it.t, it.w, 0, g.C, vb); break;
+        case 7: spread_body<7>(g, it.t, it.w, 0, g.C, vb); break;
+        default: spread_body<8>(g, it.t, it.w, 0, g.C, vb); break;
+      }
+      break;
+    case kBsZfwd: zfwd_body(g, it.t, it.az, it.w, it.nlines, vb); break;
+    case kBsYfwd: {
+      const int gx = (g.KZ + g.kb - 1) / g.kb;
+      yfwd_body(g, it.t, it.ay, it.w, vb % gx, vb / gx);
+      break;
+    }
+    case kBsXmul: xmul_body(g, it.t, it.ax, it.w, mode, nullptr, vb % g.nxblk, vb / g.nxblk); break;
+    case kBsFinalize: finalize_body(g, it.t, it.w, it.energy, it.virial); break;
+    case kBsYinv: {
+      const int gx = (g.KZ + g.kb - 1) / g.kb;
+      yinv_body(g, it.t, it.ay, it.w, vb % gx, vb / gx);
+      break;
+    }
+    case kBsZinv: zinv_body(g, it.t, it.az, it.w, it.nlines, vb); break;
+    case kBsGather:
+      switch (g.P) {
+        case 2: gather_body<2>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
+        case 3: gather_body<3>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
+        case 4: gather_body<4>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
+        case 5: gather_body<5>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
+        case 6: gather_body<6>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
+        case 7: gather_body<7>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
+        default: gather_body<8>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
+      }
+      break;
+  }
+}
+
+int batch_stage_threads(int stage) {
+  switch (stage) {
+    case kBsScan: return 1024;
+    case kBsSpread: return kSpreadThreads;
+    case kBsGather: return kGatherThreads;
+    default: return PSWF_THREADS;
+  }
+}
+
+// virtual blocks of one structure in one stage (0 when the stage is skipped)
+int batch_stage_blocks(const BatchItem &it, int stage, bool adjoint) {
+  const Geo &g = it.g;
+  const int64_t N = g.N;
+  switch (stage) {
+    case kBsZero: return int(nblocks(g.ncell, PSWF_THREADS));
+    case kBsBin: case kBsScatter: return N > 0 ? int(nblocks(N, PSWF_THREADS)) : 0;
+    case kBsScan: case kBsQreduce: case kBsFinalize: return 1;
+    case kBsOrder: return N > 0 ? g.ncell : 0;
+    case kBsQsum: return it.qblocks * g.C;
+    case kBsSpread: return g.ncell;
+    case kBsZfwd: return int(nblocks(it.nlines, g.zlines));
+    case kBsYfwd: return int(nblocks(g.KZ, g.kb)) * g.C * g.M[0];
+    case kBsXmul: return g.nxblk * g.C;
+    case kBsYinv: return adjoint ? int(nblocks(g.KZ, g.kb)) * g.C * g.M[0] : 0;
+    case kBsZinv: return adjoint ? int(nblocks(it.nlines, g.zlines)) : 0;
+    case kBsGather: return (adjoint && N > 0) ? g.ncell : 0;
+  }
+  return 0;
+}
+
+size_t batch_stage_lds(const BatchItem &it, int stage) {
+  switch (stage) {
+    case kBsSpread: return spread_lds_bytes(it.g, it.g.C);
+    case kBsZfwd: case kBsZinv: return zpass_lds_bytes(it.g);
+    case kBsYfwd: case kBsYinv: return ypass_lds_bytes(it.g);
+    case kBsXmul: return xpass_lds_bytes(it.g);
+    case kBsGather: return gather_lds_bytes(it.g, it.g.CG_gather);
+  }
+  return 0;
+}
+
+template <int STAGE>
+static hipError_t launch_stage_t(const BatchItem *d_items, const int *d_prefix, int n, int total_blocks, size_t lds,
+                                 int mode, hipStream_t st) {
+  constexpr int T = (STAGE == kBsScan) ? 1024 : (STAGE == kBsSpread ? kSpreadThreads
+                                                                    : (STAGE == kBsGather ? kGatherThreads
+                                                                                          : PSWF_THREADS));
+  hipError_t e = lds_request(reinterpret_cast<const void *>(&k_batch<STAGE, T>), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_batch<STAGE, T>), dim3(total_blocks), dim3(T), lds, st, d_items, d_prefix, n, mode);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_batch_stage(const BatchItem *d_items, const int *d_prefix, int n, int stage, int total_blocks,
+                              size_t lds, int mode, hipStream_t st) {
+  if (total_blocks <= 0) return hipSuccess;
+  switch (stage) {
+    case kBsZero: return launch_stage_t<kBsZero>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsBin: return launch_stage_t<kBsBin>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsScan: return launch_stage_t<kBsScan>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsScatter: return launch_stage_t<kBsScatter>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsOrder: return launch_stage_t<kBsOrder>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsQsum: return launch_stage_t<kBsQsum>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsQreduce: return launch_stage_t<kBsQreduce>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsSpread: return launch_stage_t<kBsSpread>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsZfwd: return launch_stage_t<kBsZfwd>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsYfwd: return launch_stage_t<kBsYfwd>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsXmul: return launch_stage_t<kBsXmul>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsFinalize: return launch_stage_t<kBsFinalize>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsYinv: return launch_stage_t<kBsYinv>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsZinv: return launch_stage_t<kBsZinv>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsGather: return launch_stage_t<kBsGather>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace pswf

@@ -35,4 +35,11 @@ hipError_t launch_gather(const Geo &g, const Tables &t, const Work &w, float *fo
 hipError_t launch_finalize(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial,
                            hipStream_t st);
 
+// batched execution (one launch per stage over every structure)
+int batch_stage_threads(int stage);
+int batch_stage_blocks(const BatchItem &it, int stage, bool adjoint);
+size_t batch_stage_lds(const BatchItem &it, int stage);
+hipError_t launch_batch_stage(const BatchItem *d_items, const int *d_prefix, int n, int stage, int total_blocks,
+                              size_t lds, int mode, hipStream_t st);
+
 }  // namespace pswf

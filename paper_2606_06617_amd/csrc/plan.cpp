@@ -42,9 +42,14 @@ FftAxis factorise(int n, bool *ok) {
   int m = n, a = 0;
   while (m % 2 == 0) { m /= 2; ++a; }
   std::vector<int> r;
-  while (a >= 3) { r.push_back(8); a -= 3; }
-  if (a == 2) r.push_back(4);
-  if (a == 1) r.push_back(2);
+  // powers of two as radix 8 and 4 stages (a lone radix-2 stage only for n = 2)
+  if (a == 1) {
+    r.push_back(2);
+    a = 0;
+  }
+  if (a % 3 == 1) { r.push_back(4); r.push_back(4); a -= 4; }
+  if (a % 3 == 2) { r.push_back(4); a -= 2; }
+  while (a >= 3) { r.insert(r.begin(), 8); a -= 3; }
   while (m % 3 == 0) { r.push_back(3); m /= 3; }
   while (m % 5 == 0) { r.push_back(5); m /= 5; }
   *ok = (m == 1) && int(r.size()) <= kMaxRadixStages;
@@ -205,6 +210,18 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
             best[0] = bx; best[1] = by; best[2] = bz;
           }
         }
+    if (p.tile[0] > 0 || p.tile[1] > 0 || p.tile[2] > 0) {
+      for (int a = 0; a < 3; ++a) {
+        const int b = p.tile[a] > 0 ? p.tile[a] : best[a];
+        if (b <= 0 || M[a] % b != 0) return fail(PSWFLR_ERR_INVALID_ARG, "tile edges must divide the grid");
+        best[a] = b;
+      }
+      if (((best[0] + 3) / 4) * ((best[1] + 3) / 4) * ((best[2] + 7) / 8) > spread_max_blocks())
+        return fail(PSWFLR_ERR_UNSUPPORTED, "tile holds too many 4x4x8 spreading blocks");
+      if ((size_t(best[0] + P - 1) * (best[1] + P - 1) * (best[2] + P) + 96) * 4 > 160 * 1024)
+        return fail(PSWFLR_ERR_UNSUPPORTED, "tile halo exceeds LDS");
+      best_eff = 0.0;
+    }
     if (best_eff < 0) return fail(PSWFLR_ERR_UNSUPPORTED, "no tile shape fits this grid");
     for (int a = 0; a < 3; ++a) {
       g.B[a] = best[a];
@@ -605,11 +622,42 @@ pswflr_status pswflr_profile_read(pswflr_plan plan, double *ms_total, int64_t *l
   return s;
 }
 
+}  // extern "C"
+
+namespace {
+
+size_t batch_header_bytes(int n) {
+  return align256(size_t(n) * sizeof(BatchItem)) + align256(size_t(kNumBatchStages) * (n + 1) * sizeof(int));
+}
+
+int stage_profile_id(int bs) {
+  switch (bs) {
+    case kBsZero: case kBsBin: case kBsScan: case kBsScatter: case kBsOrder: return PSWFLR_STAGE_SORT;
+    case kBsQsum: case kBsQreduce: return PSWFLR_STAGE_QSUM;
+    case kBsSpread: return PSWFLR_STAGE_SPREAD;
+    case kBsZfwd: return PSWFLR_STAGE_FFT_Z;
+    case kBsYfwd: return PSWFLR_STAGE_FFT_Y;
+    case kBsXmul: return PSWFLR_STAGE_FFT_X_SCALE;
+    case kBsFinalize: return PSWFLR_STAGE_REDUCE;
+    case kBsYinv: return PSWFLR_STAGE_IFFT_Y;
+    case kBsZinv: return PSWFLR_STAGE_IFFT_Z;
+    default: return PSWFLR_STAGE_GATHER;
+  }
+}
+
+void free_host_blob(void *p) { delete[] static_cast<char *>(p); }
+
+}  // namespace
+
+extern "C" {
+
 pswflr_status pswflr_batch_workspace(int32_t n, const pswflr_plan *plans, const int64_t *n_atoms, size_t *bytes) {
   if (n < 0 || (n > 0 && (!plans || !n_atoms)) || !bytes) return fail(PSWFLR_ERR_INVALID_ARG, "bad batch arguments");
-  size_t tot = 0;
+  size_t tot = batch_header_bytes(n);
   for (int i = 0; i < n; ++i) {
     if (!plans[i]) return fail(PSWFLR_ERR_INVALID_ARG, "NULL plan in batch");
+    if (n_atoms[i] < 0 || n_atoms[i] > plans[i]->max_atoms)
+      return fail(PSWFLR_ERR_INVALID_ARG, "batch entry exceeds its plan's max_atoms");
     tot += align256(plans[i]->ws_bytes);
   }
   *bytes = tot;
@@ -618,19 +666,89 @@ pswflr_status pswflr_batch_workspace(int32_t n, const pswflr_plan *plans, const 
 
 pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const pswflr_io *io,
                                    pswflr_stream stream, void *workspace, size_t ws_bytes) {
+  if (n == 0) return PSWFLR_OK;
+  if (n < 0 || !plans || !io) return fail(PSWFLR_ERR_INVALID_ARG, "bad batch arguments");
+  std::vector<int64_t> na(n);
+  for (int i = 0; i < n; ++i) na[i] = io[i].n_atoms;
   size_t need = 0;
-  std::vector<int64_t> na(std::max(0, n));
-  for (int i = 0; i < n; ++i) na[i] = io ? io[i].n_atoms : 0;
   pswflr_status s = pswflr_batch_workspace(n, plans, na.data(), &need);
   if (s != PSWFLR_OK) return s;
-  if (!io && n > 0) return fail(PSWFLR_ERR_INVALID_ARG, "io is NULL");
-  if (ws_bytes < need || (n > 0 && !workspace)) return fail(PSWFLR_ERR_WORKSPACE, "batch workspace too small");
-  size_t off = 0;
+  if (!workspace || ws_bytes < need) return fail(PSWFLR_ERR_WORKSPACE, "batch workspace missing or too small");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return fail(PSWFLR_ERR_WORKSPACE, "workspace not 256-byte aligned");
   for (int i = 0; i < n; ++i) {
-    s = pswflr_execute(plans[i], stream, static_cast<char *>(workspace) + off, plans[i]->ws_bytes, io[i].n_atoms,
-                       io[i].pos, io[i].q, io[i].energy, io[i].forces, io[i].virial, io[i].potential);
-    if (s != PSWFLR_OK) return s;
-    off += align256(plans[i]->ws_bytes);
+    if (!io[i].energy) return fail(PSWFLR_ERR_INVALID_ARG, "energy output is required");
+    if (io[i].n_atoms > 0 && (!io[i].pos || !io[i].q)) return fail(PSWFLR_ERR_INVALID_ARG, "pos and q required");
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char *ws = static_cast<char *>(workspace);
+  const size_t hdr = batch_header_bytes(n);
+  bool fused = true;
+  for (int i = 0; i < n; ++i) fused = fused && plans[i]->geo.C <= spread_max_channels();
+  if (!fused) {  // channel groups beyond one spreading launch: one call per structure
+    size_t off = hdr;
+    for (int i = 0; i < n; ++i) {
+      s = pswflr_execute(plans[i], stream, ws + off, plans[i]->ws_bytes, io[i].n_atoms, io[i].pos, io[i].q,
+                         io[i].energy, io[i].forces, io[i].virial, io[i].potential);
+      if (s != PSWFLR_OK) return s;
+      off += align256(plans[i]->ws_bytes);
+    }
+    return PSWFLR_OK;
+  }
+  // host image of the header: items, then per-stage prefixes
+  char *blob = new char[hdr]();
+  BatchItem *items = reinterpret_cast<BatchItem *>(blob);
+  int *prefix = reinterpret_cast<int *>(blob + align256(size_t(n) * sizeof(BatchItem)));
+  std::vector<bool> adj(n);
+  size_t off = hdr;
+  for (int i = 0; i < n; ++i) {
+    const pswflr_plan_s &pl = *plans[i];
+    BatchItem &it = items[i];
+    it.g = pl.geo;
+    it.g.N = io[i].n_atoms;
+    it.t = pl.tab;
+    it.w = carve(pl, ws + off, io[i].n_atoms);
+    it.az = pl.az;
+    it.ay = pl.ay;
+    it.ax = pl.ax;
+    it.pos = io[i].pos;
+    it.q = io[i].q;
+    it.energy = io[i].energy;
+    it.forces = io[i].forces;
+    it.virial = io[i].virial;
+    it.pot = io[i].potential;
+    it.qblocks = qsum_blocks(it.g);
+    it.nlines = int64_t(it.g.C) * it.g.M[0] * it.g.M[1];
+    adj[i] = io[i].forces || io[i].potential;
+    off += align256(pl.ws_bytes);
+  }
+  std::vector<int> total(kNumBatchStages);
+  std::vector<size_t> lds(kNumBatchStages, 0);
+  for (int stg = 0; stg < kNumBatchStages; ++stg) {
+    int acc = 0;
+    for (int i = 0; i < n; ++i) {
+      prefix[stg * (n + 1) + i] = acc;
+      acc += batch_stage_blocks(items[i], stg, adj[i]);
+      lds[stg] = std::max(lds[stg], batch_stage_lds(items[i], stg));
+    }
+    prefix[stg * (n + 1) + n] = acc;
+    total[stg] = acc;
+  }
+  hipError_t e = hipMemcpyAsync(ws, blob, hdr, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipLaunchHostFunc(st, free_host_blob, blob);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    delete[] blob;
+    return fail(PSWFLR_ERR_DEVICE, std::string("batch header upload failed: ") + hipGetErrorString(e));
+  }
+  const BatchItem *d_items = reinterpret_cast<const BatchItem *>(ws);
+  const int *d_prefix = reinterpret_cast<const int *>(ws + align256(size_t(n) * sizeof(BatchItem)));
+  StageRunner run{plans[0], st};
+  for (int stg = 0; stg < kNumBatchStages; ++stg) {
+    e = run(stage_profile_id(stg), [&] {
+      return launch_batch_stage(d_items, d_prefix + stg * (n + 1), n, stg, total[stg], lds[stg], 1, st);
+    });
+    if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
   }
   return PSWFLR_OK;
 }

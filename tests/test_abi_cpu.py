@@ -41,10 +41,10 @@ def test_status_strings():
 def _create(**kw):
     L = _lib.lib()
     base = dict(box=(20.0, 20.0, 20.0), ps=[1], r_c=5.0, c=12.024, tol=1e-5, grid=(32, 32, 32),
-                support=6, c_spread=16.4)
+                support=6, c_spread=16.4, tile=None)
     base.update(kw)
     prm = _lib.make_params(base["box"], base["ps"], base["r_c"], base["c"], base["tol"], base["grid"],
-                           base["support"], base["c_spread"])
+                           base["support"], base["c_spread"], base["tile"])
     h = ctypes.c_void_p()
     return L.pswflr_plan_create(ctypes.byref(prm), 100, ctypes.byref(h))
 
@@ -58,6 +58,8 @@ def _create(**kw):
     (dict(grid=(32, 32, 31)), 2),      # odd M_z
     (dict(grid=(32, 14, 32)), 2),      # 7 is not a supported radix
     (dict(grid=(8, 8, 8)), 1),         # Nyquist: k_c h / pi >= 1
+    (dict(tile=(5, 16, 16)), 1),       # tile does not divide the grid
+    (dict(tile=(32, 32, 32)), 2),      # too many spreading blocks
 ])
 def test_argument_errors_before_device(kw, status):
     assert _create(**kw) == status
