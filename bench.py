@@ -24,6 +24,7 @@ if ROOT not in sys.path:
 
 METRIC = "LR energy+force atoms/s at ≤1e-4 rel force err; served p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32, published
 STAGES = ["sort", "qsum", "spread", "fft_z", "fft_y", "fft_x_scale", "reduce", "ifft_y", "ifft_z", "gather"]
 C_MOL, R_C = 12.024, 5.0
 
@@ -56,6 +57,31 @@ def algorithmic_bytes(info, N, C, cg_spread):
         "ifft_z": s1 + 4 * C * M,
         "gather": 4 * C * M + N * (16 + 4 * C) + 12 * N,
     }
+
+
+def algorithmic_flops(info, N, C):
+    """FP32 operations the method needs per launch where they, not bytes,
+    bound a kernel: spreading 2 P^3 N C (one FMA per window point and
+    channel), gathering 8 P^3 N C (potential and gradient sums)."""
+    P = info["support"]
+    return {"spread": 2 * P ** 3 * N * C, "gather": 8 * P ** 3 * N * C}
+
+
+def stage_kernel(stage, P):
+    """Name (as in rocprofv3 summaries) of the kernel a timed stage launches."""
+    return {"spread": "k_spread<%d>" % P, "fft_z": "k_zfwd", "fft_y": "k_yfwd", "fft_x_scale": "k_xmul",
+            "ifft_y": "k_yinv", "ifft_z": "k_zinv", "gather": "k_gather<%d>" % P}.get(stage)
+
+
+def measured_traffic(workload_name, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary
+    of this workload, or None when there is none or the kernel source has
+    changed since the counters were taken."""
+    from paper_2606_06617_amd import profiling
+    rows, sha = profiling.read_traffic(os.path.join(ROOT, "profiles", "traffic_%s.txt" % workload_name))
+    if not rows or sha != profiling.source_hash() or kernel not in rows:
+        return None
+    return rows[kernel]
 
 
 def cpu_baseline(w, n_sample=48):
@@ -102,6 +128,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="ionic_1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also launch one plain device-to-device copy of this many MiB (a known-size "
+                         "kernel that calibrates FETCH_SIZE / WRITE_SIZE counter readings)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -153,12 +182,22 @@ def main():
     info = plan.info
     cg_spread = int(info["cg_spread"])
     algo = algorithmic_bytes(info, N, C, cg_spread)
+    flops = algorithmic_flops(info, N, C)
     dom = max(algo.keys(), key=lambda k: stage_ms[k])
-    achieved = algo[dom] / (avg_launch_ms[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "algorithmic_bytes_per_launch": int(algo[dom]),
-                "avg_launch_ms": round(avg_launch_ms[dom], 4)}
+    t_dom = avg_launch_ms[dom] * 1e-3
+    traffic = measured_traffic(args.workload, stage_kernel(dom, info["support"]))
+    if flops.get(dom, 0) / (FP32_PEAK_TFLOPS * 1e12) > algo[dom] / (HBM_PEAK_GBS * 1e9):
+        achieved = flops[dom] / t_dom / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                    "traffic": None if traffic is None else int(traffic),
+                    "algorithmic_flops_per_launch": int(flops[dom]), "avg_launch_ms": round(avg_launch_ms[dom], 4)}
+    else:
+        achieved = algo[dom] / t_dom / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None if traffic is None else int(traffic),
+                    "algorithmic_bytes_per_launch": int(algo[dom]), "avg_launch_ms": round(avg_launch_ms[dom], 4)}
     per_stage = {k: {"ms_per_step": round(stage_ms[k], 4),
                      "GB_s": (round(algo[k] / (avg_launch_ms[k] * 1e-3) / 1e9, 1)
                               if k in algo and avg_launch_ms[k] > 0 else None)} for k in STAGES}
@@ -183,6 +222,13 @@ def main():
         "roofline": roofline,
         "stages": per_stage,
     }
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["calib_copy_bytes"] = 2 * src.numel() * 4
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)

@@ -15,7 +15,7 @@ import os
 import threading
 import time
 
-KERNEL_VERSION = 3
+KERNEL_VERSION = 4
 _LOCK = threading.Lock()
 
 
@@ -45,17 +45,29 @@ def _divisors(m):
     return [d for d in range(1, m + 1) if m % d == 0]
 
 
-def candidate_tiles(grid, P, max_blocks=16, lds=160 * 1024, limit=6):
+def _tile_fits(bx, by, bz, P, lds=160 * 1024):
+    """The kernels' own limits: at most 32 4x4x4 spreading blocks with padded
+    edges summing to <= 64, and a gather halo of one channel that fits LDS
+    with at most 128 (y, 16-wide z run) staging items."""
+    pad = lambda b: (b + 3) // 4 * 4
+    nblk = (pad(bx) // 4) * (pad(by) // 4) * (pad(bz) // 4)
+    S = pad(bx) + pad(by) + pad(bz)
+    if nblk > 32 or S > 64 or bx * by * bz > 256 * (12 + S + 1 + 5):
+        return False
+    ey, ez = by + P - 1, bz + P - 1
+    if ey * ((ez + 15) // 16) > 128:
+        return False
+    return ((bx + P - 1) * ey * (ez | 1) + 96) * 4 <= lds
+
+
+def candidate_tiles(grid, P, limit=6):
     """Feasible tiles ranked by useful-work fraction, plus the most parallel
     feasible ones (small grids)."""
     feas = []
     for bx in _divisors(grid[0]):
         for by in _divisors(grid[1]):
             for bz in _divisors(grid[2]):
-                nblk = ((bx + 3) // 4) * ((by + 3) // 4) * ((bz + 7) // 8)
-                if nblk > max_blocks:
-                    continue
-                if ((bx + P - 1) * (by + P - 1) * (bz + P) + 96) * 4 > lds:
+                if not _tile_fits(bx, by, bz, P):
                     continue
                 eff = bx / (bx + P - 1) * by / (by + P - 1) * bz / (bz + P - 1)
                 ncell = (grid[0] // bx) * (grid[1] // by) * (grid[2] // bz)

@@ -73,7 +73,7 @@ struct Geo {
   float invV;
   double V;
   int CG_spread;          // channels per spread pass
-  int CG_gather;          // channels per gather pass
+  int CG_gather;          // channels per gather halo staging (1)
   int nxblk;              // blocks of the fused x pass
   int zlines;             // lines per z-pass block (power of two)
   int kb;                 // columns per y/x-pass block (power of two)
@@ -112,7 +112,6 @@ struct Work {
   int *cell_of, *slot;    // [N]
   int *cell_count;        // [ncell]
   int *cell_start;        // [ncell + 1]
-  float *facc;            // [N][3] force accumulator in cell order
   double *epart;          // [C][nxblk][8]
   double *qpart;          // [nqblk][C][2]
   double *qsum;           // [C][2]: Q_net, Q_self

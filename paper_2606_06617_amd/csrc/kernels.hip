@@ -399,20 +399,36 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nbl
 
 // ---------------------------------------------------------------------------
 // Spread (step i), output-stationary.  One workgroup of 8 waves per tile.
-// Candidate atoms (windows touching the tile) are staged in LDS with their
-// 3 P window weights and charges.  The tile is cut into 4 x 4 x 8 blocks;
-// each wave owns up to kSpreadNBW blocks and every lane owns two points of
-// a block (z and z + 4) with one accumulator per channel in registers.  All
-// waves walk the candidates in the same order, skip blocks the window does
-// not touch with a scalar test, and add w_x w_y w_z q to their own points:
-// no atomics and no read-modify-write of shared memory; the summation
+// The tile is cut into 4 x 4 x 4 blocks; each wave owns up to kSpreadNBW
+// blocks and every lane owns one point of each, with one accumulator per
+// channel in registers.  Atoms of the candidate cells are screened in
+// chunks; the ones whose window reaches into the tile are staged in LDS with
+// their charges and, per axis, the window weights laid out over the tile's
+// coordinates (zero outside the window), so a lane reads its weight with no
+// index arithmetic.  A wave then tests 64 staged candidates at a time
+// against each of its blocks, and walks only the candidates that meet a
+// block (a scalar loop over the ballot mask), adding w_x w_y w_z q to its
+// points.  No atomics, no read-modify-write of shared memory; the summation
 // order is fixed, so the result is bitwise reproducible.
 constexpr int kSpreadThreads = 512;
-constexpr int kSpreadChunk = 256;
-constexpr int kSpreadCGM = 12;   // channels per launch
-constexpr int kSpreadNBW = 2;    // blocks per wave
+constexpr int kSpreadCap = 256;     // candidates staged per flush
+constexpr int kSpreadScreen = 128;  // atoms screened per chunk (two waves)
+constexpr int kSpreadCGM = 12;      // channels per launch
+constexpr int kSpreadNBW = 4;       // 4x4x4 blocks per wave
+constexpr int kSpreadMaxS = 64;     // padded tile edges Sx + Sy + Sz
+constexpr int kSpreadBias = 8;      // packed window offsets are stored + bias
+constexpr int kSpreadMaxPts = kSpreadNBW * (kSpreadThreads / 64) * 64;  // tile points
+constexpr int kSpreadOutMax = (kSpreadMaxPts + kSpreadThreads - 1) / kSpreadThreads;  // scalar elements/thread
 
-// window [d, d + P) (mod M) meets block [o, o + S) ?
+// LDS floats of the candidate staging area (tile edges padded to 4, summed: S)
+__host__ __device__ __forceinline__ int spread_stride(int S) { return S + 1; }
+__host__ __device__ __forceinline__ int spread_stage_floats(int stride) {
+  return kSpreadCap * (kSpreadCGM + stride + 5);
+}
+
+__device__ __forceinline__ int spread_pad4(int b) { return (b + 3) & ~3; }
+
+// window [d, d + P) (mod M) meets block [o, o + S) ?  (0 <= d, o < M)
 __device__ __forceinline__ bool win_meets(int o, int S, int d, int P, int M) {
   int a = o - d;
   if (a < 0) a += M;
@@ -422,18 +438,119 @@ __device__ __forceinline__ bool win_meets(int o, int S, int d, int P, int M) {
 }
 
 template <int P>
+__device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg0, int ncg, int ncand,
+                                             const int *sz, float *cq, float *cw, const int *cd, const float *cf,
+                                             const int *ci, const float *wcf, const int (&bo)[kSpreadNBW][3],
+                                             const bool (&bval)[kSpreadNBW], const bool (&newcol)[kSpreadNBW],
+                                             float (&acc)[kSpreadNBW][kSpreadCGM]) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int S = spread_stride(sz[0] + sz[1] + sz[2]);
+  const int soff[3] = {0, sz[0], sz[0] + sz[1]};
+  // (1) per candidate and axis, the window weights over the padded tile edge
+  for (int t = tid; t < 3 * kSpreadCap; t += kSpreadThreads) {
+    const int a = t / kSpreadCap, k = t - a * kSpreadCap;
+    if (k >= ncand) continue;
+    const int d = ((cd[k] >> (10 * a)) & 1023) - kSpreadBias;  // tile-relative window start
+    const float r = cf[3 * k + a];
+    float *dst = cw + k * S + soff[a];
+    for (int x = 0; x < sz[a]; ++x) dst[x] = 0.0f;
+    const int Ma = g.M[a], Ba = g.B[a];
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+      int x = d + l;
+      if (x < 0) x += Ma;
+      if (x >= Ma) x -= Ma;
+      if (x < Ba) dst[x] += win_eval(wcf, (2.0f * (l + r)) / P - 1.0f);
+    }
+    if (a == 0) {
+      const int i = ci[k];
+#pragma unroll
+      for (int c = 0; c < kSpreadCGM; ++c) cq[k * kSpreadCGM + c] = c < ncg ? w.q_a[int64_t(cg0 + c) * g.N + i] : 0.0f;
+    }
+  }
+  __syncthreads();
+  // (2) accumulate: 64 candidates per ballot, scalar walk over the hits.
+  // A wave's blocks run along z within a column, so the x and y weights
+  // are shared by consecutive blocks of one column.
+  const int lx = lane >> 4, ly = (lane >> 2) & 3, lz = lane & 3;
+  int xa[kSpreadNBW], ya[kSpreadNBW], za[kSpreadNBW];
+#pragma unroll
+  for (int j = 0; j < kSpreadNBW; ++j) {
+    xa[j] = (bo[j][0] + lx) * 4;
+    ya[j] = (soff[1] + bo[j][1] + ly) * 4;
+    za[j] = (soff[2] + bo[j][2] + lz) * 4;
+  }
+  for (int k0 = 0; k0 < ncand; k0 += 64) {
+    const int k = k0 + lane;
+    const bool valid = k < ncand;
+    const int pk = valid ? cd[k] : 0;
+    int dd[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      dd[a] = ((pk >> (10 * a)) & 1023) - kSpreadBias;
+      if (dd[a] < 0) dd[a] += g.M[a];
+    }
+    unsigned long long m[kSpreadNBW];
+    unsigned long long u = 0ull;
+#pragma unroll
+    for (int j = 0; j < kSpreadNBW; ++j) {
+      const bool hit = valid && bval[j] && win_meets(bo[j][0], 4, dd[0], P, g.M[0]) &&
+                       win_meets(bo[j][1], 4, dd[1], P, g.M[1]) && win_meets(bo[j][2], 4, dd[2], P, g.M[2]);
+      m[j] = __ballot(hit);
+      u |= m[j];
+    }
+    while (u) {
+      const int b = __builtin_ctzll(u);
+      u &= u - 1ull;
+      const int kk = k0 + b;
+      float q[kSpreadCGM];
+#pragma unroll
+      for (int c = 0; c < kSpreadCGM; c += 4) {
+        const float4 q4 = *reinterpret_cast<const float4 *>(cq + kk * kSpreadCGM + c);
+        q[c] = q4.x;
+        q[c + 1] = q4.y;
+        q[c + 2] = q4.z;
+        q[c + 3] = q4.w;
+      }
+      const char *wk = reinterpret_cast<const char *>(cw + kk * S);
+      float wxy[kSpreadNBW], wv[kSpreadNBW];
+#pragma unroll
+      for (int j = 0; j < kSpreadNBW; ++j) {
+        if (j == 0 || newcol[j])
+          wxy[j] = *reinterpret_cast<const float *>(wk + xa[j]) * *reinterpret_cast<const float *>(wk + ya[j]);
+        else
+          wxy[j] = wxy[j - 1];
+      }
+#pragma unroll
+      for (int j = 0; j < kSpreadNBW; ++j) wv[j] = wxy[j] * *reinterpret_cast<const float *>(wk + za[j]);
+#pragma unroll
+      for (int j = 0; j < kSpreadNBW; ++j) {
+        if (!((m[j] >> b) & 1ull)) continue;
+#pragma unroll
+        for (int c = 0; c < kSpreadCGM; ++c) acc[j][c] = fmaf(wv[j], q[c], acc[j][c]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int P>
 __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, int bx) {
   extern __shared__ float smem[];
-  float *cq = smem;                                                   // [chunk][CGM]
-  float *cw = cq + kSpreadChunk * kSpreadCGM;                         // [chunk][3][P]
-  float *wcf = cw + kSpreadChunk * 3 * P;                             // window coefficients
-  int *cd = reinterpret_cast<int *>(wcf + kWinSeg * (kWinDeg + 1));   // [chunk] packed offsets
-  __shared__ int wcount[kSpreadChunk / 64];
-  __shared__ int ncand_s;
-
   const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
-  const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int sz[3] = {spread_pad4(Bx), spread_pad4(By), spread_pad4(Bz)};
+  const int S = spread_stride(sz[0] + sz[1] + sz[2]);
+  float *cq = smem;                                                 // [cap][CGM]
+  float *cw = cq + kSpreadCap * kSpreadCGM;                         // [cap][S]
+  float *cf = cw + kSpreadCap * S;                                  // [cap][3] window offsets delta
+  int *cd = reinterpret_cast<int *>(cf + 3 * kSpreadCap);           // [cap] packed window starts
+  int *ci = cd + kSpreadCap;                                        // [cap] atom index
+  float *wcf = reinterpret_cast<float *>(ci + kSpreadCap);          // window coefficients
+  // (the write-out stage below reuses everything up to wcf)
+  __shared__ int wcount[kSpreadScreen / 64];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps block bookkeeping scalar
   const int cell = bx;
   const int cz = cell % g.nc[2], cy = (cell / g.nc[2]) % g.nc[1], cx = cell / (g.nc[2] * g.nc[1]);
   const int t0[3] = {cx * Bx, cy * By, cz * Bz};
@@ -441,28 +558,29 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
 
   for (int e = tid; e < kWinSeg * (kWinDeg + 1); e += kSpreadThreads) wcf[e] = t.win[e];
 
-  // blocks owned by this wave and this lane's two points in each
-  const int nbx = (Bx + 3) >> 2, nby = (By + 3) >> 2, nbz = (Bz + 7) >> 3;
+  // 4x4x4 blocks, z fastest; wave w owns the per consecutive blocks
+  // [w per, w per + per), which run along z within a column
+  const int nbx = sz[0] >> 2, nby = sz[1] >> 2, nbz = sz[2] >> 2;
   const int nblk = nbx * nby * nbz;
-  const int lxo = lane >> 4, lyo = (lane >> 2) & 3, lzo = lane & 3;
+  const int per = (nblk + kSpreadThreads / 64 - 1) / (kSpreadThreads / 64);
   int bo[kSpreadNBW][3];
-  bool bval[kSpreadNBW];
+  bool bval[kSpreadNBW], newcol[kSpreadNBW];
 #pragma unroll
   for (int j = 0; j < kSpreadNBW; ++j) {
-    const int b = wave + j * (kSpreadThreads / 64);
-    bval[j] = b < nblk;
+    const int b = wave * per + j;
+    bval[j] = j < per && b < nblk;
     const int bb = bval[j] ? b : 0;
-    bo[j][0] = (bb / (nby * nbz)) * 4;
-    bo[j][1] = ((bb / nbz) % nby) * 4;
-    bo[j][2] = (bb % nbz) * 8;
+    const int col = bb / nbz, zb = bb - col * nbz;
+    bo[j][0] = (col / nby) * 4;
+    bo[j][1] = (col - (col / nby) * nby) * 4;
+    bo[j][2] = zb * 4;
+    newcol[j] = bval[j] && zb == 0;
   }
-  float acc[kSpreadNBW][2][kSpreadCGM];
+  float acc[kSpreadNBW][kSpreadCGM];
 #pragma unroll
   for (int j = 0; j < kSpreadNBW; ++j)
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int c = 0; c < kSpreadCGM; ++c) acc[j][h][c] = 0.0f;
+    for (int c = 0; c < kSpreadCGM; ++c) acc[j][c] = 0.0f;
 
   // candidate cells: this tile's cell and the ones before it along each
   // axis that can hold a window start reaching into the tile
@@ -475,130 +593,115 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   }
   __syncthreads();
 
-  for (int ix = 0; ix < ccount[0]; ++ix)
-    for (int iy = 0; iy < ccount[1]; ++iy)
-      for (int iz = 0; iz < ccount[2]; ++iz) {
-        const int cc = (clist[0][ix] * g.nc[1] + clist[1][iy]) * g.nc[2] + clist[2][iz];
-        const int s = w.cell_start[cc], e = w.cell_start[cc + 1];
-        for (int base = s; base < e; base += kSpreadChunk) {
-          // stage candidates: threads 0..chunk-1 each test one atom
-          const int i = base + tid;
-          bool ok = false;
-          float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
-          int d[3] = {0, 0, 0};
-          if (tid < kSpreadChunk && i < e) {
-            r = reinterpret_cast<const float4 *>(w.rec_a)[i];
-            const unsigned pk = __float_as_uint(r.w);
-            ok = true;
+  // walk the candidate cells chunk by chunk; flush the staged candidates
+  // whenever the next chunk might not fit, and at the end
+  const int ncells = ccount[0] * ccount[1] * ccount[2];
+  int ncand = 0, icell = -1, s = 0, e = 0, base = 0;
+  while (true) {
+    while (base >= e && icell < ncells) {
+      if (++icell >= ncells) break;
+      const int iz = icell % ccount[2], iy = (icell / ccount[2]) % ccount[1], ix = icell / (ccount[2] * ccount[1]);
+      const int cc = (clist[0][ix] * g.nc[1] + clist[1][iy]) * g.nc[2] + clist[2][iz];
+      s = w.cell_start[cc];
+      e = w.cell_start[cc + 1];
+      base = s;
+    }
+    const bool done = icell >= ncells;
+    if (!done) {
+      const int i = base + tid;
+      bool ok = false;
+      float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+      int d[3] = {0, 0, 0};
+      if (tid < kSpreadScreen && i < e) {
+        r = reinterpret_cast<const float4 *>(w.rec_a)[i];
+        const unsigned pk = __float_as_uint(r.w);
+        ok = true;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              int dd = unpack_n0(pk, a) - t0[a];
-              if (dd < 0) dd += g.M[a];
-              d[a] = dd;
-              ok = ok && (dd < g.B[a] || dd > g.M[a] - P);
-            }
-          }
-          const unsigned long long m = __ballot(ok);
-          if (lane == 0 && wave < kSpreadChunk / 64) wcount[wave] = __popcll(m);
-          __syncthreads();
-          if (ok) {
-            int off = 0;
-            for (int k = 0; k < wave; ++k) off += wcount[k];
-            const int slot = off + __popcll(m & ((1ull << lane) - 1ull));
-            cd[slot] = d[0] | (d[1] << 10) | (d[2] << 20);
-            const float dl[3] = {r.x, r.y, r.z};
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-              for (int l = 0; l < P; ++l)
-                cw[(slot * 3 + a) * P + l] = win_eval(wcf, (2.0f * (l + dl[a])) / P - 1.0f);
-#pragma unroll
-            for (int c = 0; c < kSpreadCGM; ++c)
-              cq[slot * kSpreadCGM + c] = c < ncg ? w.q_a[int64_t(cg0 + c) * g.N + i] : 0.0f;
-          }
-          if (tid == 0) {
-            int tot = 0;
-            for (int k = 0; k < kSpreadChunk / 64; ++k) tot += wcount[k];
-            ncand_s = tot;
-          }
-          __syncthreads();
-          const int ncand = ncand_s;
-          for (int k = 0; k < ncand; ++k) {
-            const int pk = __builtin_amdgcn_readfirstlane(cd[k]);
-            const int dx = pk & 1023, dy = (pk >> 10) & 1023, dz = (pk >> 20) & 1023;
-            const float *wk = cw + k * 3 * P;
-            float q[kSpreadCGM];
-#pragma unroll
-            for (int c = 0; c < kSpreadCGM; c += 4) {
-              const float4 q4 = *reinterpret_cast<const float4 *>(cq + k * kSpreadCGM + c);
-              q[c] = q4.x;
-              q[c + 1] = q4.y;
-              q[c + 2] = q4.z;
-              q[c + 3] = q4.w;
-            }
-#pragma unroll
-            for (int j = 0; j < kSpreadNBW; ++j) {
-              if (!bval[j]) continue;
-              if (!win_meets(bo[j][0], 4, dx, P, Mx) || !win_meets(bo[j][1], 4, dy, P, My) ||
-                  !win_meets(bo[j][2], 8, dz, P, Mz))
-                continue;
-              const int x = bo[j][0] + lxo, y = bo[j][1] + lyo, z0 = bo[j][2] + lzo, z1 = z0 + 4;
-              int lx = x - dx, ly = y - dy, lz0 = z0 - dz, lz1 = z1 - dz;
-              if (lx < 0) lx += Mx;
-              if (ly < 0) ly += My;
-              if (lz0 < 0) lz0 += Mz;
-              if (lz1 < 0) lz1 += Mz;
-              const bool vxy = x < Bx && y < By && lx < P && ly < P;
-              const bool v0 = vxy && z0 < Bz && lz0 < P;
-              const bool v1 = vxy && z1 < Bz && lz1 < P;
-              const float wxy = wk[min(lx, P - 1)] * wk[P + min(ly, P - 1)];
-              const float w0 = v0 ? wxy * wk[2 * P + min(lz0, P - 1)] : 0.0f;
-              const float w1 = v1 ? wxy * wk[2 * P + min(lz1, P - 1)] : 0.0f;
-#pragma unroll
-              for (int c = 0; c < kSpreadCGM; ++c) {
-                acc[j][0][c] = fmaf(w0, q[c], acc[j][0][c]);
-                acc[j][1][c] = fmaf(w1, q[c], acc[j][1][c]);
-              }
-            }
-          }
-          __syncthreads();
+        for (int a = 0; a < 3; ++a) {
+          int dd = unpack_n0(pk, a) - t0[a];
+          if (dd < 0) dd += g.M[a];
+          const bool in = dd < g.B[a];
+          ok = ok && (in || dd > g.M[a] - P);
+          d[a] = in ? dd : dd - g.M[a];
         }
       }
+      const unsigned long long m = __ballot(ok);
+      if (lane == 0 && wave < kSpreadScreen / 64) wcount[wave] = __popcll(m);
+      __syncthreads();
+      if (ok) {
+        int off = ncand;
+        for (int k = 0; k < wave; ++k) off += wcount[k];
+        const int slot = off + __popcll(m & ((1ull << lane) - 1ull));
+        cd[slot] = (d[0] + kSpreadBias) | ((d[1] + kSpreadBias) << 10) | ((d[2] + kSpreadBias) << 20);
+        cf[3 * slot] = r.x;
+        cf[3 * slot + 1] = r.y;
+        cf[3 * slot + 2] = r.z;
+        ci[slot] = i;
+      }
+#pragma unroll
+      for (int k = 0; k < kSpreadScreen / 64; ++k) ncand += wcount[k];
+      __syncthreads();
+      base += kSpreadScreen;
+    }
+    if (ncand > kSpreadCap - kSpreadScreen || (done && ncand > 0)) {
+      spread_flush<P>(g, w, cg0, ncg, ncand, sz, cq, cw, cd, cf, ci, wcf, bo, bval, newcol, acc);
+      ncand = 0;
+    }
+    if (done) break;
+  }
 
-  // write the tile one channel at a time through LDS (coalesced rows);
-  // every grid value belongs to exactly one tile
-  float *stage = smem;  // reuses the candidate area (Bx * By * Bz floats)
+  // write the tile through LDS, several channels per pass, as coalesced
+  // rows; every grid value belongs to exactly one tile.  A thread moves the
+  // same (x, y, z) element(s) of every channel.
+  float *stage = smem;  // reuses the candidate area
   const int nt = Bx * By * Bz;
-  for (int c = 0; c < ncg; ++c) {
+  const int cpp = max(1, min(ncg, spread_stage_floats(S) / nt));
+  const bool vec = (Bz & 3) == 0;
+  const int epr = vec ? 4 : 1;                       // floats per element
+  const int nel = nt / epr;                          // elements per channel
+  int goff[kSpreadOutMax], soffs[kSpreadOutMax];
+#pragma unroll
+  for (int r = 0; r < kSpreadOutMax; ++r) {
+    const int el = tid + r * kSpreadThreads;
+    const int f = min(el, nel - 1) * epr;            // first float of the element in the tile
+    const int x = f / (By * Bz), rem = f - x * (By * Bz), y = rem / Bz, z = rem - y * Bz;
+    goff[r] = el < nel ? ((t0[0] + x) * g.M[1] + t0[1] + y) * g.M[2] + t0[2] + z : -1;
+    soffs[r] = f;
+  }
+  const int64_t chan = int64_t(g.M[0]) * g.M[1] * g.M[2];
+  const int lx = lane >> 4, ly = (lane >> 2) & 3, lz = lane & 3;
+  for (int c0 = 0; c0 < ncg; c0 += cpp) {
+    const int nc = min(cpp, ncg - c0);
 #pragma unroll
     for (int j = 0; j < kSpreadNBW; ++j) {
       if (!bval[j]) continue;
-      const int x = bo[j][0] + lxo, y = bo[j][1] + lyo, z0 = bo[j][2] + lzo;
-      float v0 = 0.f, v1 = 0.f;
+      const int x = bo[j][0] + lx, y = bo[j][1] + ly, z = bo[j][2] + lz;
+      if (x < Bx && y < By && z < Bz) {
+        float *dst = stage + (x * By + y) * Bz + z;
 #pragma unroll
-      for (int cc = 0; cc < kSpreadCGM; ++cc)
-        if (cc == c) {
-          v0 = acc[j][0][cc];
-          v1 = acc[j][1][cc];
-        }
-      if (x < Bx && y < By) {
-        if (z0 < Bz) stage[(x * By + y) * Bz + z0] = v0;
-        if (z0 + 4 < Bz) stage[(x * By + y) * Bz + z0 + 4] = v1;
+        for (int cc = 0; cc < kSpreadCGM; ++cc)
+          if (cc >= c0 && cc < c0 + nc) dst[(cc - c0) * nt] = acc[j][cc];
       }
     }
     __syncthreads();
-    for (int row = wave; row < Bx * By; row += kSpreadThreads / 64) {
-      const int x = row / By, y = row - (row / By) * By;
-      float *dst = w.grid + ((int64_t(cg0 + c) * Mx + t0[0] + x) * My + t0[1] + y) * Mz + t0[2];
-      for (int z = lane; z < Bz; z += 64) dst[z] = stage[row * Bz + z];
+    for (int c = 0; c < nc; ++c) {
+      float *gch = w.grid + int64_t(cg0 + c0 + c) * chan;
+      const float *sch = stage + c * nt;
+#pragma unroll
+      for (int r = 0; r < kSpreadOutMax; ++r) {
+        if (goff[r] < 0) continue;
+        if (vec)
+          *reinterpret_cast<float4 *>(gch + goff[r]) = *reinterpret_cast<const float4 *>(sch + soffs[r]);
+        else
+          gch[goff[r]] = sch[soffs[r]];
+      }
     }
     __syncthreads();
   }
-  (void)nt;
 }
 
 template <int P>
-__global__ __launch_bounds__(kSpreadThreads) void k_spread(Geo g, Tables t, Work w, int cg0, int ncg) {
+__global__ __launch_bounds__(kSpreadThreads, 4) void k_spread(Geo g, Tables t, Work w, int cg0, int ncg) {
   spread_body<P>(g, t, w, cg0, ncg, blockIdx.x);
 }
 
@@ -884,27 +987,40 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis 
 }
 
 // ---------------------------------------------------------------------------
-// Gather (adjoint of step i): one workgroup per tile; the tile's grid region
-// plus a P-1 halo is staged in LDS per channel group.  Eight lanes serve one
-// atom (lane = window offset l): each lane evaluates the window and its
-// derivative at its own offset on the three axes and the group exchanges
-// them by shuffles; then lane l sums the (x, y) plane of z-offset l with the
-// separable weights and the group reduces over z.
+// Gather (adjoint of step i): one workgroup per tile.  The tile's atoms are
+// taken in passes of up to kGatherAtoms; four lanes serve one atom, lane l
+// owning the window rows at y-offsets l and l + 4.  Each lane evaluates the
+// window and its derivative at its own offsets and the four exchange them
+// once per pass, so every lane holds the atom's x and z weights in
+// registers across all channels.  Per channel the tile's grid region plus a
+// P-1 halo is staged in LDS (one channel at a time keeps the workgroup small
+// enough for several to share a CU); each lane contracts its rows -- z
+// first, then x -- and the lanes are reduced once per atom for the forces
+// (per channel only for the potential).
 //   phi_i   = sum_n pg(n) W(n h - r_i)
 //   F_i     = q_i sum_n pg(n) grad W(n h - r_i)
 // mode 1: forces/potentials; mode 2: adjoint (grad_q = g phi, grad_r = -g F).
 constexpr int kGatherThreads = 512;
+constexpr int kGatherLanes = 4;                                 // lanes per atom
+constexpr int kGatherAtoms = kGatherThreads / kGatherLanes;     // atoms per pass
+constexpr int kGatherItems = 4;                                 // halo (y, 16-wide z run) items per thread
+constexpr unsigned kGatherOOB = 0x7ffffff0u;                    // byte offset past any grid plane
+// gfx9 raw buffer descriptor word 3 (32-bit dwords, range-checked offsets)
+constexpr int kBufferWord3 = 0x00020000;
+
+__host__ __device__ __forceinline__ int gather_sz(int ez) { return ez | 1; }  // odd row stride
 
 template <int P>
 __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const Work &w, float *__restrict__ fout,
                                             float *__restrict__ pout, int mode, const double *__restrict__ grad, int bx) {
+  constexpr int R = (P + kGatherLanes - 1) / kGatherLanes;      // rows per lane
   extern __shared__ float smem[];
   const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
   const int EX = Bx + P - 1, EY = By + P - 1, EZ = Bz + P - 1;
-  const int SZ = EZ + 1;
-  const int plane = EY * SZ, chan = EX * plane;
-  float *tile = smem;
-  float *wcf = tile + g.CG_gather * chan;
+  const int SZ = gather_sz(EZ);
+  const int plane = EY * SZ;
+  float *tile = smem;                                           // [EX][EY][SZ]
+  float *wcf = smem + EX * plane;
   const int tid = threadIdx.x;
   const int cell = bx;
   const int s = w.cell_start[cell], e = w.cell_start[cell + 1];
@@ -912,126 +1028,158 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
   const int cz = cell % g.nc[2], cy = (cell / g.nc[2]) % g.nc[1], cx = cell / (g.nc[2] * g.nc[1]);
   const int t0[3] = {cx * Bx, cy * By, cz * Bz};
   for (int k = tid; k < kWinSeg * (kWinDeg + 1); k += kGatherThreads) wcf[k] = t.win[k];
-  const int lz = tid & 7;
-  constexpr int kAtomsPerBatch = kGatherThreads / 8;
-  const int nchunks = (e - s + kAtomsPerBatch - 1) / kAtomsPerBatch;
 
-  for (int cg0 = 0; cg0 < g.C; cg0 += g.CG_gather) {
-    const int ncg = min(g.CG_gather, g.C - cg0);
-    __syncthreads();
-    // rows of EZ contiguous floats; one row per half-wave step, no divisions
-    {
-      const int hw = tid >> 5, hl = tid & 31, nhw = kGatherThreads / 32;
-      for (int c = 0; c < ncg; ++c)
-        for (int x = 0; x < EX; ++x) {
-          int gx = t0[0] + x;
-          if (gx >= g.M[0]) gx -= g.M[0];
-          for (int y = hw; y < EY; y += nhw) {
-            int gy = t0[1] + y;
-            if (gy >= g.M[1]) gy -= g.M[1];
-            const float *src = w.grid + ((int64_t(cg0 + c) * g.M[0] + gx) * g.M[1] + gy) * g.M[2];
-            float *dst = tile + c * chan + x * plane + y * SZ;
-            for (int z = hl; z < EZ; z += 32) {
-              int gz = t0[2] + z;
-              if (gz >= g.M[2]) gz -= g.M[2];
-              dst[z] = src[gz];
-            }
-          }
-        }
+  // halo rows this thread stages: items (y, z run) at (tid / 16) + 32 r,
+  // lane tid % 16 of the run; the same for every channel.  Byte offsets
+  // within an x-plane of the grid; unused items get an offset past the
+  // buffer range, which a buffer load returns as 0.
+  const int nzc = (EZ + 15) >> 4, nitems = EY * nzc;
+  unsigned gyz[kGatherItems];
+  int lofs[kGatherItems];
+#pragma unroll
+  for (int r = 0; r < kGatherItems; ++r) {
+    const int it = (tid >> 4) + 32 * r;
+    const int y = it / nzc, z = (it - y * nzc) * 16 + (tid & 15);
+    int gy = t0[1] + y, gz = t0[2] + z;
+    if (gy >= g.M[1]) gy -= g.M[1];
+    if (gz >= g.M[2]) gz -= g.M[2];
+    const bool ok = it < nitems && z < EZ;
+    gyz[r] = ok ? unsigned(gy * g.M[2] + gz) * 4u : kGatherOOB;
+    lofs[r] = ok ? y * SZ + z : -1;
+  }
+  const int MyMz = g.M[1] * g.M[2];
+  const int64_t chan = int64_t(g.M[0]) * MyMz;
+  const int l = tid & (kGatherLanes - 1);
+  const float sg = mode == 2 ? -1.0f : 1.0f;
+  __syncthreads();  // window coefficients
+
+  for (int p0 = s; p0 < e; p0 += kGatherAtoms) {
+    const int na = min(kGatherAtoms, e - p0);
+    const int k = tid / kGatherLanes;
+    const bool act = k < na;
+    const int a = p0 + min(k, na - 1);
+    const float4 rr = reinterpret_cast<const float4 *>(w.rec_a)[a];
+    const unsigned pk = __float_as_uint(rr.w);
+    int o[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      o[ax] = unpack_n0(pk, ax) - t0[ax];
+      if (o[ax] < 0) o[ax] += g.M[ax];
     }
-    __syncthreads();
-    const bool last = cg0 + ncg >= g.C;
-    for (int ch = 0; ch < nchunks; ++ch) {
-      const int a = s + ch * kAtomsPerBatch + (tid >> 3);
-      const bool active = a < e;
-      int ox = 0, oy = 0, oz = 0;
-      float2 vx = make_float2(0.f, 0.f), vy = vx, vz = vx;
-      if (active) {
-        const float4 r = reinterpret_cast<const float4 *>(w.rec_a)[a];
-        const unsigned pk = __float_as_uint(r.w);
-        ox = unpack_n0(pk, 0) - t0[0];
-        oy = unpack_n0(pk, 1) - t0[1];
-        oz = unpack_n0(pk, 2) - t0[2];
-        if (lz < P) {
-          vx = win_eval_d(wcf, (2.0f * (lz + r.x)) / P - 1.0f);
-          vy = win_eval_d(wcf, (2.0f * (lz + r.y)) / P - 1.0f);
-          vz = win_eval_d(wcf, (2.0f * (lz + r.z)) / P - 1.0f);
-        }
-      }
-      float wx[P], dwx[P], wy[P], dwy[P];
+    // own offsets l + 4 j: window values and derivatives on the three axes
+    float2 vx[R], vy[R], vz[R];
 #pragma unroll
-      for (int l = 0; l < P; ++l) {
-        wx[l] = __shfl(vx.x, l, 8);
-        dwx[l] = __shfl(vx.y, l, 8) * g.dwin[0];
-        wy[l] = __shfl(vy.x, l, 8);
-        dwy[l] = __shfl(vy.y, l, 8) * g.dwin[1];
-      }
-      const float wz = vz.x, dwz = vz.y * g.dwin[2];
-      float f[3] = {0.f, 0.f, 0.f};
-      for (int c = 0; c < ncg; ++c) {
-        float sp = 0.f, sx = 0.f, sy = 0.f;
-        if (active && lz < P) {
-          const float *base = tile + c * chan + ox * plane + oy * SZ + oz + lz;
+    for (int j = 0; j < R; ++j) {
+      const int off = l + kGatherLanes * j;
+      const int oc = min(off, P - 1);
+      vx[j] = win_eval_d(wcf, (2.0f * (oc + rr.x)) / P - 1.0f);
+      vy[j] = win_eval_d(wcf, (2.0f * (oc + rr.y)) / P - 1.0f);
+      vz[j] = win_eval_d(wcf, (2.0f * (oc + rr.z)) / P - 1.0f);
+      if (off >= P) vy[j] = make_float2(0.0f, 0.0f);  // rows past the window add nothing
+    }
+    float wx[P], dwx[P], wz[P], dwz[P];
 #pragma unroll
-          for (int lx = 0; lx < P; ++lx) {
-            float a0 = 0.f, a1 = 0.f;
+    for (int i = 0; i < P; ++i) {
+      const int src = i % kGatherLanes, j = i / kGatherLanes;
+      wx[i] = __shfl(vx[j].x, src, kGatherLanes);
+      dwx[i] = __shfl(vx[j].y, src, kGatherLanes) * g.dwin[0];
+      wz[i] = __shfl(vz[j].x, src, kGatherLanes);
+      dwz[i] = __shfl(vz[j].y, src, kGatherLanes) * g.dwin[2];
+    }
+    float wy[R], dwy[R];
 #pragma unroll
-            for (int ly = 0; ly < P; ++ly) {
-              const float gv = base[lx * plane + ly * SZ];
-              a0 = fmaf(wy[ly], gv, a0);
-              a1 = fmaf(dwy[ly], gv, a1);
-            }
-            sp = fmaf(wx[lx], a0, sp);
-            sx = fmaf(dwx[lx], a0, sx);
-            sy = fmaf(wx[lx], a1, sy);
+    for (int j = 0; j < R; ++j) {
+      wy[j] = vy[j].x;
+      dwy[j] = vy[j].y * g.dwin[1];
+    }
+    const int base = o[0] * plane + o[1] * SZ + o[2];
+    float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+
+    for (int c = 0; c < g.C; ++c) {
+      const float qv = w.q_a[int64_t(c) * g.N + a];
+      __syncthreads();  // the tile buffer is free
+      {
+        const float *gch = w.grid + int64_t(c) * chan;
+        for (int x0 = 0; x0 < EX; x0 += 4) {
+          float v[4][kGatherItems];
+#pragma unroll
+          for (int xi = 0; xi < 4; ++xi) {
+            int gx = t0[0] + min(x0 + xi, EX - 1);
+            if (gx >= g.M[0]) gx -= g.M[0];
+            const __amdgpu_buffer_rsrc_t plane_rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float *>(gch + int64_t(gx) * MyMz), 0, MyMz * 4, kBufferWord3);
+#pragma unroll
+            for (int r = 0; r < kGatherItems; ++r) v[xi][r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(plane_rs, gyz[r], 0, 0));
           }
-        }
-        float vphi = wz * sp, vgx = wz * sx, vgy = wz * sy, vgz = dwz * sp;
 #pragma unroll
-        for (int off = 1; off < 8; off <<= 1) {
-          vphi += __shfl_xor(vphi, off, 8);
-          vgx += __shfl_xor(vgx, off, 8);
-          vgy += __shfl_xor(vgy, off, 8);
-          vgz += __shfl_xor(vgz, off, 8);
-        }
-        if (active && lz == 0) {
-          const int cc = cg0 + c;
-          const float qv = w.q_a[int64_t(cc) * g.N + a];
-          f[0] += qv * vgx;
-          f[1] += qv * vgy;
-          f[2] += qv * vgz;
-          if (pout) {
-            const double gsc = mode == 2 ? grad[cc] : 1.0;
-            // potential includes the zero-frequency term dE_0/dq = 2 a Q_net
-            const float zero = float(2.0 * t.zero_V[cc] / g.V * w.qsum[2 * cc] * gsc);
-            pout[int64_t(cc) * g.N + w.perm_a[a]] = vphi + zero;
+          for (int xi = 0; xi < 4; ++xi) {
+            if (x0 + xi >= EX) break;
+#pragma unroll
+            for (int r = 0; r < kGatherItems; ++r)
+              if (lofs[r] >= 0) tile[(x0 + xi) * plane + lofs[r]] = v[xi][r];
           }
         }
       }
-      if (active && lz == 0) {
-        if (cg0 > 0) {
-          f[0] += w.facc[3 * int64_t(a)];
-          f[1] += w.facc[3 * int64_t(a) + 1];
-          f[2] += w.facc[3 * int64_t(a) + 2];
+      __syncthreads();
+      float vphi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll 1
+      for (int j = 0; j < R; ++j) {
+        const int yo = min(l + kGatherLanes * j, P - 1);
+        const float *b = tile + base + yo * SZ;
+        float sp = 0.f, sx = 0.f, szz = 0.f;
+#pragma unroll
+        for (int lx = 0; lx < P; ++lx) {
+          const float *row = b + lx * plane;
+          float gv[P];
+#pragma unroll
+          for (int lz = 0; lz < P; ++lz) gv[lz] = row[lz];
+          float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+          for (int lz = 0; lz < P; ++lz) {
+            a0 = fmaf(wz[lz], gv[lz], a0);
+            a1 = fmaf(dwz[lz], gv[lz], a1);
+          }
+          sp = fmaf(wx[lx], a0, sp);
+          sx = fmaf(dwx[lx], a0, sx);
+          szz = fmaf(wx[lx], a1, szz);
         }
-        if (!last) {
-          w.facc[3 * int64_t(a)] = f[0];
-          w.facc[3 * int64_t(a) + 1] = f[1];
-          w.facc[3 * int64_t(a) + 2] = f[2];
-        } else if (fout) {
-          const float sg = mode == 2 ? -1.0f : 1.0f;
-          const int64_t o = 3 * int64_t(w.perm_a[a]);
-          fout[o] = sg * f[0];
-          fout[o + 1] = sg * f[1];
-          fout[o + 2] = sg * f[2];
+        const float wyj = j == 0 ? wy[0] : wy[R - 1], dwyj = j == 0 ? dwy[0] : dwy[R - 1];
+        vphi = fmaf(wyj, sp, vphi);
+        gx = fmaf(wyj, sx, gx);
+        gy = fmaf(dwyj, sp, gy);
+        gz = fmaf(wyj, szz, gz);
+      }
+      f0 = fmaf(qv, gx, f0);
+      f1 = fmaf(qv, gy, f1);
+      f2 = fmaf(qv, gz, f2);
+      if (pout) {
+#pragma unroll
+        for (int off = 1; off < kGatherLanes; off <<= 1) vphi += __shfl_xor(vphi, off, kGatherLanes);
+        if (act && l == 0) {
+          const double gsc = mode == 2 ? grad[c] : 1.0;
+          // potential includes the zero-frequency term dE_0/dq = 2 a Q_net
+          const float zero = float(2.0 * t.zero_V[c] / g.V * w.qsum[2 * c] * gsc);
+          pout[int64_t(c) * g.N + w.perm_a[a]] = vphi + zero;
         }
       }
+    }
+#pragma unroll
+    for (int off = 1; off < kGatherLanes; off <<= 1) {
+      f0 += __shfl_xor(f0, off, kGatherLanes);
+      f1 += __shfl_xor(f1, off, kGatherLanes);
+      f2 += __shfl_xor(f2, off, kGatherLanes);
+    }
+    if (act && l == 0 && fout) {
+      const int64_t oo = 3 * int64_t(w.perm_a[a]);
+      fout[oo] = sg * f0;
+      fout[oo + 1] = sg * f1;
+      fout[oo + 2] = sg * f2;
     }
   }
 }
 
 template <int P>
-__global__ __launch_bounds__(kGatherThreads) void k_gather(Geo g, Tables t, Work w, float *__restrict__ fout,
+__global__ __launch_bounds__(kGatherThreads, 4) void k_gather(Geo g, Tables t, Work w, float *__restrict__ fout,
                                                             float *__restrict__ pout, int mode,
                                                             const double *__restrict__ grad) {
   gather_body<P>(g, t, w, fout, pout, mode, grad, blockIdx.x);
@@ -1092,15 +1240,29 @@ static inline unsigned nblocks(int64_t n, int per) { return unsigned((n + per - 
 
 size_t spread_lds_bytes(const Geo &g, int ncg) {
   (void)ncg;
-  const size_t staging = size_t(kSpreadChunk) * (kSpreadCGM + 3 * g.P + 1) + kWinSeg * (kWinDeg + 1);
-  const size_t outtile = size_t(g.B[0]) * g.B[1] * g.B[2];
-  return std::max(staging, outtile) * 4;
+  const int S = (g.B[0] + 3) / 4 * 4 + (g.B[1] + 3) / 4 * 4 + (g.B[2] + 3) / 4 * 4;
+  return (size_t(spread_stage_floats(spread_stride(S))) + kWinSeg * (kWinDeg + 1)) * 4;
 }
 int spread_max_channels() { return kSpreadCGM; }
-int spread_max_blocks() { return kSpreadNBW * kSpreadThreads / 64; }
+bool spread_tile_ok(int bx, int by, int bz) {
+  const int nblk = ((bx + 3) / 4) * ((by + 3) / 4) * ((bz + 3) / 4);
+  const int S = (bx + 3) / 4 * 4 + (by + 3) / 4 * 4 + (bz + 3) / 4 * 4;
+  return nblk <= kSpreadNBW * kSpreadThreads / 64 && S <= kSpreadMaxS &&
+         bx * by * bz <= spread_stage_floats(spread_stride(S));
+}
 size_t gather_lds_bytes(const Geo &g, int ncg) {
+  (void)ncg;
   const size_t EX = g.B[0] + g.P - 1, EY = g.B[1] + g.P - 1, EZ = g.B[2] + g.P - 1;
-  return (size_t(ncg) * EX * EY * (EZ + 1) + kWinSeg * (kWinDeg + 1)) * 4;
+  return (EX * EY * gather_sz(int(EZ)) + kWinSeg * (kWinDeg + 1)) * 4;
+}
+bool gather_tile_ok(int bx, int by, int bz, int P) {
+  Geo g{};
+  g.B[0] = bx;
+  g.B[1] = by;
+  g.B[2] = bz;
+  g.P = P;
+  const int ey = by + P - 1, ez = bz + P - 1;
+  return ey * ((ez + 15) / 16) <= 32 * kGatherItems && gather_lds_bytes(g, 1) <= 160 * 1024;
 }
 size_t zpass_lds_bytes(const Geo &g) { return (size_t(g.Nz) * (g.zlines + 1) + 2 * g.Nz + 1) * 8; }
 size_t ypass_lds_bytes(const Geo &g) { return (size_t(g.M[1]) * (g.kb + 1) + g.M[1]) * 8; }
@@ -1272,7 +1434,7 @@ __device__ __forceinline__ int find_item(const int *__restrict__ prefix, int n, 
 }
 
 template <int STAGE, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_batch(const BatchItem *__restrict__ items,
+__global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather) ? 4 : 1)) void k_batch(const BatchItem *__restrict__ items,
                                                     const int *__restrict__ prefix, int n, int mode) {
   const int b = blockIdx.x;
   const int s = find_item(prefix, n, b);

@@ -13,12 +13,13 @@ constexpr int kQChunk = 8192;   // atoms per block of the charge sums
 
 size_t spread_lds_bytes(const Geo &g, int ncg);
 size_t gather_lds_bytes(const Geo &g, int ncg);
+bool gather_tile_ok(int bx, int by, int bz, int P);  // halo staging map and LDS fit
 size_t zpass_lds_bytes(const Geo &g);
 size_t ypass_lds_bytes(const Geo &g);
 size_t xpass_lds_bytes(const Geo &g);
 int qsum_blocks(const Geo &g);
 int spread_max_channels();   // channels per spreading launch
-int spread_max_blocks();     // 4x4x8 blocks a spreading tile may hold
+bool spread_tile_ok(int bx, int by, int bz);  // tile fits the spreading kernel's blocks and LDS
 
 hipError_t enqueue_sort(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st);
 hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t st);

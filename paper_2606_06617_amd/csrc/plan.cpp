@@ -90,7 +90,7 @@ struct pswflr_plan_s {
   int64_t max_atoms = 0;
   size_t off_grid = 0, off_s1 = 0, off_s2 = 0, off_rec_a = 0, off_rec_b = 0, off_q_a = 0, off_q_b = 0,
          off_perm_a = 0, off_perm_b = 0, off_cell_of = 0, off_slot = 0, off_count = 0, off_start = 0,
-         off_facc = 0, off_epart = 0, off_qpart = 0, off_qsum = 0, ws_bytes = 0;
+         off_epart = 0, off_qpart = 0, off_qsum = 0, ws_bytes = 0;
   // optional per-stage event timing (measurement only)
   bool prof = false;
   std::mutex prof_mu;
@@ -198,10 +198,7 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
     for (int bx : divisors(M[0]))
       for (int by : divisors(M[1]))
         for (int bz : divisors(M[2])) {
-          const int nblk = ((bx + 3) / 4) * ((by + 3) / 4) * ((bz + 7) / 8);
-          if (nblk > spread_max_blocks()) continue;
-          const size_t glds = (size_t(bx + P - 1) * (by + P - 1) * (bz + P) + 96) * 4;
-          if (glds > 160 * 1024) continue;
+          if (!spread_tile_ok(bx, by, bz) || !gather_tile_ok(bx, by, bz, P)) continue;
           const double eff = double(bx) / (bx + P - 1) * double(by) / (by + P - 1) * double(bz) / (bz + P - 1);
           const long vol = long(bx) * by * bz;
           if (eff > best_eff + 1e-12 || (std::fabs(eff - best_eff) <= 1e-12 && vol > best_vol)) {
@@ -216,10 +213,10 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
         if (b <= 0 || M[a] % b != 0) return fail(PSWFLR_ERR_INVALID_ARG, "tile edges must divide the grid");
         best[a] = b;
       }
-      if (((best[0] + 3) / 4) * ((best[1] + 3) / 4) * ((best[2] + 7) / 8) > spread_max_blocks())
-        return fail(PSWFLR_ERR_UNSUPPORTED, "tile holds too many 4x4x8 spreading blocks");
-      if ((size_t(best[0] + P - 1) * (best[1] + P - 1) * (best[2] + P) + 96) * 4 > 160 * 1024)
-        return fail(PSWFLR_ERR_UNSUPPORTED, "tile halo exceeds LDS");
+      if (!spread_tile_ok(best[0], best[1], best[2]))
+        return fail(PSWFLR_ERR_UNSUPPORTED, "tile exceeds the spreading kernel's 32 4x4x4 blocks");
+      if (!gather_tile_ok(best[0], best[1], best[2], P))
+        return fail(PSWFLR_ERR_UNSUPPORTED, "tile halo exceeds the gather kernel's LDS staging");
       best_eff = 0.0;
     }
     if (best_eff < 0) return fail(PSWFLR_ERR_UNSUPPORTED, "no tile shape fits this grid");
@@ -230,19 +227,15 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   }
   g.ncell = g.nc[0] * g.nc[1] * g.nc[2];
   // channel groups: the spreading kernel keeps kSpreadCGM channels in
-  // registers; the gather stages as many halo tiles as fit the 160 KiB of
-  // LDS a gfx950 workgroup may use.  Groups are balanced.
+  // registers (groups are balanced); the gather walks all channels, one
+  // staged halo tile at a time.
   const size_t kLds = 160 * 1024;
   g.CG_spread = std::min(C, spread_max_channels());
-  g.CG_gather = 0;
-  for (int k = std::min(C, 16); k >= 1; --k)
-    if (gather_lds_bytes(g, k) <= kLds) { g.CG_gather = k; break; }
-  if (g.CG_gather == 0) return fail(PSWFLR_ERR_UNSUPPORTED, "gather tile too large for LDS");
+  g.CG_gather = 1;  // the gather stages one channel's halo tile at a time
+  if (gather_lds_bytes(g, 1) > kLds) return fail(PSWFLR_ERR_UNSUPPORTED, "gather tile too large for LDS");
   {
-    int ng = (C + g.CG_spread - 1) / g.CG_spread;
+    const int ng = (C + g.CG_spread - 1) / g.CG_spread;
     g.CG_spread = (C + ng - 1) / ng;
-    ng = (C + g.CG_gather - 1) / g.CG_gather;
-    g.CG_gather = (C + ng - 1) / ng;
   }
   if (spread_lds_bytes(g, g.CG_spread) > kLds) return fail(PSWFLR_ERR_UNSUPPORTED, "spread staging exceeds LDS");
   g.kb = std::max(1, std::min(16, floor_pow2(4096 / std::max(M[0], M[1]))));
@@ -384,7 +377,6 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   pl.off_slot = take(size_t(Nm) * 4);
   pl.off_count = take(size_t(g.ncell) * 4);
   pl.off_start = take(size_t(g.ncell + 1) * 4);
-  pl.off_facc = take(size_t(Nm) * 12);
   pl.off_epart = take(size_t(C) * std::max(1, g.nxblk) * 8 * 8);
   pl.off_qpart = take(size_t((Nm + kQChunk - 1) / kQChunk + 1) * C * 2 * 8);
   pl.off_qsum = take(size_t(C) * 2 * 8);
@@ -436,7 +428,6 @@ Work carve(const pswflr_plan_s &pl, void *ws, int64_t N) {
   w.slot = reinterpret_cast<int *>(b + pl.off_slot);
   w.cell_count = reinterpret_cast<int *>(b + pl.off_count);
   w.cell_start = reinterpret_cast<int *>(b + pl.off_start);
-  w.facc = reinterpret_cast<float *>(b + pl.off_facc);
   w.epart = reinterpret_cast<double *>(b + pl.off_epart);
   w.qpart = reinterpret_cast<double *>(b + pl.off_qpart);
   w.qsum = reinterpret_cast<double *>(b + pl.off_qsum);
