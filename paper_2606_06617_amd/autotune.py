@@ -15,7 +15,7 @@ import os
 import threading
 import time
 
-KERNEL_VERSION = 4
+KERNEL_VERSION = 5
 _LOCK = threading.Lock()
 
 
@@ -46,13 +46,20 @@ def _divisors(m):
 
 
 def _tile_fits(bx, by, bz, P, lds=160 * 1024):
-    """The kernels' own limits: at most 32 4x4x4 spreading blocks with padded
-    edges summing to <= 64, and a gather halo of one channel that fits LDS
-    with at most 128 (y, 16-wide z run) staging items."""
+    """The kernels' own limits.  Spreading: 4x4x4 blocks, the tile's z edge
+    one, two or four blocks deep (NBZ), each wave owning NBZ blocks in each
+    of 4/NBZ neighbouring y columns (so the y block count is a multiple of
+    4/NBZ and there are at most 8 waves' worth of columns), padded edges
+    summing to <= 64.  Gather: a one-channel halo tile that fits LDS with at
+    most 128 (y, 16-wide z run) staging items."""
     pad = lambda b: (b + 3) // 4 * 4
-    nblk = (pad(bx) // 4) * (pad(by) // 4) * (pad(bz) // 4)
+    nbz = pad(bz) // 4
+    if nbz not in (1, 2, 4):
+        return False
+    cpw = 4 // nbz
+    nby = pad(by) // 4
     S = pad(bx) + pad(by) + pad(bz)
-    if nblk > 32 or S > 64 or bx * by * bz > 256 * (12 + S + 1 + 5):
+    if nby % cpw or (pad(bx) // 4) * nby > 8 * cpw or S > 64 or bx * by * bz > 256 * (12 + S + 5):
         return False
     ey, ez = by + P - 1, bz + P - 1
     if ey * ((ez + 15) // 16) > 128:

@@ -399,17 +399,20 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nbl
 
 // ---------------------------------------------------------------------------
 // Spread (step i), output-stationary.  One workgroup of 8 waves per tile.
-// The tile is cut into 4 x 4 x 4 blocks; each wave owns up to kSpreadNBW
-// blocks and every lane owns one point of each, with one accumulator per
-// channel in registers.  Atoms of the candidate cells are screened in
-// chunks; the ones whose window reaches into the tile are staged in LDS with
-// their charges and, per axis, the window weights laid out over the tile's
-// coordinates (zero outside the window), so a lane reads its weight with no
-// index arithmetic.  A wave then tests 64 staged candidates at a time
-// against each of its blocks, and walks only the candidates that meet a
-// block (a scalar loop over the ballot mask), adding w_x w_y w_z q to its
-// points.  No atomics, no read-modify-write of shared memory; the summation
-// order is fixed, so the result is bitwise reproducible.
+// The tile is cut into 4 x 4 x 4 blocks.  Each wave owns four of them: NBZ
+// consecutive blocks along z (the whole z extent of the tile) in each of
+// 4 / NBZ neighbouring columns along y, and every lane owns one point of
+// each block, with one accumulator per channel in registers.  Atoms of the
+// candidate cells are screened in chunks; the ones whose window reaches
+// into the tile are staged in LDS with their charges and, per axis, the
+// window weights laid out over the tile's coordinates (zero outside the
+// window; the z weights transposed so that a lane's NBZ values are
+// adjacent), so a lane reads its weights with one load per axis and no
+// index arithmetic.  A wave tests 64 staged candidates at a time against
+// each of its blocks (ballot) and walks only the candidates that meet a
+// block, with the LDS reads of the next one in flight while the current one
+// is accumulated.  No atomics, no read-modify-write of shared memory; the
+// summation order is fixed, so the result is bitwise reproducible.
 constexpr int kSpreadThreads = 512;
 constexpr int kSpreadCap = 256;     // candidates staged per flush
 constexpr int kSpreadScreen = 128;  // atoms screened per chunk (two waves)
@@ -420,13 +423,14 @@ constexpr int kSpreadBias = 8;      // packed window offsets are stored + bias
 constexpr int kSpreadMaxPts = kSpreadNBW * (kSpreadThreads / 64) * 64;  // tile points
 constexpr int kSpreadOutMax = (kSpreadMaxPts + kSpreadThreads - 1) / kSpreadThreads;  // scalar elements/thread
 
-// LDS floats of the candidate staging area (tile edges padded to 4, summed: S)
-__host__ __device__ __forceinline__ int spread_stride(int S) { return S + 1; }
-__host__ __device__ __forceinline__ int spread_stage_floats(int stride) {
-  return kSpreadCap * (kSpreadCGM + stride + 5);
+// LDS floats of the candidate staging area for padded edges summing to S
+__host__ __device__ __forceinline__ int spread_stage_floats(int S) { return kSpreadCap * (kSpreadCGM + S + 5); }
+__host__ __device__ __forceinline__ int spread_pad4(int b) { return (b + 3) & ~3; }
+// blocks along z of a tile edge (1, 2 or 4 supported); 0 if unsupported
+__host__ __device__ __forceinline__ int spread_nbz(int bz) {
+  const int n = spread_pad4(bz) >> 2;
+  return (n == 1 || n == 2 || n == 4) ? n : 0;
 }
-
-__device__ __forceinline__ int spread_pad4(int b) { return (b + 3) & ~3; }
 
 // window [d, d + P) (mod M) meets block [o, o + S) ?  (0 <= d, o < M)
 __device__ __forceinline__ bool win_meets(int o, int S, int d, int P, int M) {
@@ -437,16 +441,80 @@ __device__ __forceinline__ bool win_meets(int o, int S, int d, int P, int M) {
   return a < P || b < S;
 }
 
-template <int P>
-__device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg0, int ncg, int ncand,
-                                             const int *sz, float *cq, float *cw, const int *cd, const float *cf,
-                                             const int *ci, const float *wcf, const int (&bo)[kSpreadNBW][3],
-                                             const bool (&bval)[kSpreadNBW], const bool (&newcol)[kSpreadNBW],
+// one staged candidate as a lane needs it: its window weights at the lane's
+// x, at its y in each column and at its z in each z block
+template <int NBZ>
+struct SpreadCand {
+  static constexpr int CPW = kSpreadNBW / NBZ;
+  float wx, wy[CPW], wz[NBZ];
+};
+
+template <int NBZ>
+__device__ __forceinline__ void spread_load(const float *cw, int S, int kk, int xa, int ya, int za,
+                                            SpreadCand<NBZ> &o) {
+  constexpr int CPW = kSpreadNBW / NBZ;
+  const char *wk = reinterpret_cast<const char *>(cw + kk * S);
+  o.wx = *reinterpret_cast<const float *>(wk + xa);
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) o.wy[c] = *reinterpret_cast<const float *>(wk + ya + 16 * c);
+  if constexpr (NBZ == 4) {
+    const float4 z4 = *reinterpret_cast<const float4 *>(wk + za);
+    o.wz[0] = z4.x;
+    o.wz[1] = z4.y;
+    o.wz[2] = z4.z;
+    o.wz[3] = z4.w;
+  } else if constexpr (NBZ == 2) {
+    const float2 z2 = *reinterpret_cast<const float2 *>(wk + za);
+    o.wz[0] = z2.x;
+    o.wz[1] = z2.y;
+  } else {
+    o.wz[0] = *reinterpret_cast<const float *>(wk + za);
+  }
+}
+
+__device__ __forceinline__ int spread_take(unsigned long long &u) {
+  const int bit = __builtin_ctzll(u);
+  u &= u - 1ull;
+  return bit;
+}
+
+// add candidate `bit` of the current 64 to the blocks whose hit mask has
+// it; its charges come from lane `bit` of the per-lane charge registers
+// (v_readlane into SGPRs: a uniform operand of the FMAs, no LDS traffic)
+template <int NBZ>
+__device__ __forceinline__ void spread_accumulate(const SpreadCand<NBZ> &cnd, int bit, const float (&qreg)[kSpreadCGM],
+                                                  const unsigned long long (&m)[kSpreadNBW],
+                                                  float (&acc)[kSpreadNBW][kSpreadCGM]) {
+  constexpr int CPW = kSpreadNBW / NBZ;
+  float q[kSpreadCGM];
+#pragma unroll
+  for (int c = 0; c < kSpreadCGM; ++c)
+    q[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qreg[c]), bit));
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const float wxy = cnd.wx * cnd.wy[c];
+#pragma unroll
+    for (int z = 0; z < NBZ; ++z) {
+      const int j = c * NBZ + z;
+      if (!((m[j] >> bit) & 1ull)) continue;
+      const float wv = wxy * cnd.wz[z];
+#pragma unroll
+      for (int qq = 0; qq < kSpreadCGM; ++qq) acc[j][qq] = fmaf(wv, q[qq], acc[j][qq]);
+    }
+  }
+}
+
+template <int P, int NBZ>
+__device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg0, int ncg, int ncand, const int *sz,
+                                             float *cq, float *cw, const int *cd, const float *cf, const int *ci,
+                                             const float *wcf, const int (&bo)[3], bool wval,
                                              float (&acc)[kSpreadNBW][kSpreadCGM]) {
+  constexpr int CPW = kSpreadNBW / NBZ;
   const int tid = threadIdx.x, lane = tid & 63;
-  const int S = spread_stride(sz[0] + sz[1] + sz[2]);
+  const int S = sz[0] + sz[1] + sz[2];
   const int soff[3] = {0, sz[0], sz[0] + sz[1]};
-  // (1) per candidate and axis, the window weights over the padded tile edge
+  // (1) per candidate and axis, the window weights over the padded tile
+  // edge; z position zz is stored at (zz % 4) NBZ + zz / 4
   for (int t = tid; t < 3 * kSpreadCap; t += kSpreadThreads) {
     const int a = t / kSpreadCap, k = t - a * kSpreadCap;
     if (k >= ncand) continue;
@@ -460,29 +528,29 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
       int x = d + l;
       if (x < 0) x += Ma;
       if (x >= Ma) x -= Ma;
-      if (x < Ba) dst[x] += win_eval(wcf, (2.0f * (l + r)) / P - 1.0f);
+      if (x < Ba) dst[a == 2 ? (x & 3) * NBZ + (x >> 2) : x] += win_eval(wcf, (2.0f * (l + r)) / P - 1.0f);
     }
     if (a == 0) {
+      // all charge loads in flight at once (channel index clamped, unused
+      // channels zeroed afterwards)
       const int i = ci[k];
+      float qv[kSpreadCGM];
 #pragma unroll
-      for (int c = 0; c < kSpreadCGM; ++c) cq[k * kSpreadCGM + c] = c < ncg ? w.q_a[int64_t(cg0 + c) * g.N + i] : 0.0f;
+      for (int c = 0; c < kSpreadCGM; ++c) qv[c] = w.q_a[int64_t(cg0 + min(c, ncg - 1)) * g.N + i];
+#pragma unroll
+      for (int c = 0; c < kSpreadCGM; c += 4)
+        *reinterpret_cast<float4 *>(cq + k * kSpreadCGM + c) =
+            make_float4(c < ncg ? qv[c] : 0.0f, c + 1 < ncg ? qv[c + 1] : 0.0f, c + 2 < ncg ? qv[c + 2] : 0.0f,
+                        c + 3 < ncg ? qv[c + 3] : 0.0f);
     }
   }
   __syncthreads();
-  // (2) accumulate: 64 candidates per ballot, scalar walk over the hits.
-  // A wave's blocks run along z within a column, so the x and y weights
-  // are shared by consecutive blocks of one column.
+  // (2) accumulate: 64 candidates per ballot, scalar walk over the hits
   const int lx = lane >> 4, ly = (lane >> 2) & 3, lz = lane & 3;
-  int xa[kSpreadNBW], ya[kSpreadNBW], za[kSpreadNBW];
-#pragma unroll
-  for (int j = 0; j < kSpreadNBW; ++j) {
-    xa[j] = (bo[j][0] + lx) * 4;
-    ya[j] = (soff[1] + bo[j][1] + ly) * 4;
-    za[j] = (soff[2] + bo[j][2] + lz) * 4;
-  }
+  const int xa = (bo[0] + lx) * 4, ya = (soff[1] + bo[1] + ly) * 4, za = (soff[2] + lz * NBZ) * 4;
   for (int k0 = 0; k0 < ncand; k0 += 64) {
     const int k = k0 + lane;
-    const bool valid = k < ncand;
+    const bool valid = wval && k < ncand;
     const int pk = valid ? cd[k] : 0;
     int dd[3];
 #pragma unroll
@@ -490,56 +558,64 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
       dd[a] = ((pk >> (10 * a)) & 1023) - kSpreadBias;
       if (dd[a] < 0) dd[a] += g.M[a];
     }
+    const bool inx = win_meets(bo[0], 4, dd[0], P, g.M[0]);
+    bool iny[CPW], inz[NBZ];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) iny[c] = win_meets(bo[1] + 4 * c, 4, dd[1], P, g.M[1]);
+#pragma unroll
+    for (int z = 0; z < NBZ; ++z) inz[z] = win_meets(4 * z, 4, dd[2], P, g.M[2]);
     unsigned long long m[kSpreadNBW];
     unsigned long long u = 0ull;
 #pragma unroll
     for (int j = 0; j < kSpreadNBW; ++j) {
-      const bool hit = valid && bval[j] && win_meets(bo[j][0], 4, dd[0], P, g.M[0]) &&
-                       win_meets(bo[j][1], 4, dd[1], P, g.M[1]) && win_meets(bo[j][2], 4, dd[2], P, g.M[2]);
-      m[j] = __ballot(hit);
+      m[j] = __ballot(valid && inx && iny[j / NBZ] && inz[j % NBZ]);
       u |= m[j];
     }
-    while (u) {
-      const int b = __builtin_ctzll(u);
-      u &= u - 1ull;
-      const int kk = k0 + b;
-      float q[kSpreadCGM];
+    // software-pipelined walk over the hits, unrolled by two with two
+    // register sets: the LDS reads of the next hit are in flight while the
+    // current one is accumulated
+    if (!u) continue;
+    float qreg[kSpreadCGM];
+    {
+      const int kq = min(k, ncand - 1);
 #pragma unroll
       for (int c = 0; c < kSpreadCGM; c += 4) {
-        const float4 q4 = *reinterpret_cast<const float4 *>(cq + kk * kSpreadCGM + c);
-        q[c] = q4.x;
-        q[c + 1] = q4.y;
-        q[c + 2] = q4.z;
-        q[c + 3] = q4.w;
+        const float4 q4 = *reinterpret_cast<const float4 *>(cq + kq * kSpreadCGM + c);
+        qreg[c] = q4.x;
+        qreg[c + 1] = q4.y;
+        qreg[c + 2] = q4.z;
+        qreg[c + 3] = q4.w;
       }
-      const char *wk = reinterpret_cast<const char *>(cw + kk * S);
-      float wxy[kSpreadNBW], wv[kSpreadNBW];
-#pragma unroll
-      for (int j = 0; j < kSpreadNBW; ++j) {
-        if (j == 0 || newcol[j])
-          wxy[j] = *reinterpret_cast<const float *>(wk + xa[j]) * *reinterpret_cast<const float *>(wk + ya[j]);
-        else
-          wxy[j] = wxy[j - 1];
-      }
-#pragma unroll
-      for (int j = 0; j < kSpreadNBW; ++j) wv[j] = wxy[j] * *reinterpret_cast<const float *>(wk + za[j]);
-#pragma unroll
-      for (int j = 0; j < kSpreadNBW; ++j) {
-        if (!((m[j] >> b) & 1ull)) continue;
-#pragma unroll
-        for (int c = 0; c < kSpreadCGM; ++c) acc[j][c] = fmaf(wv[j], q[c], acc[j][c]);
-      }
+    }
+    // (the loads are unconditional -- past the last hit they re-read the
+    // current candidate -- so the wait before each accumulation counts
+    // exactly the reads issued after its own)
+    SpreadCand<NBZ> ca, cb;
+    int ba = spread_take(u), bb = 0;
+    spread_load<NBZ>(cw, S, k0 + ba, xa, ya, za, ca);
+    while (true) {
+      const bool hb = u != 0ull;
+      bb = hb ? spread_take(u) : ba;
+      spread_load<NBZ>(cw, S, k0 + bb, xa, ya, za, cb);
+      spread_accumulate<NBZ>(ca, ba, qreg, m, acc);
+      if (!hb) break;
+      const bool ha = u != 0ull;
+      ba = ha ? spread_take(u) : bb;
+      spread_load<NBZ>(cw, S, k0 + ba, xa, ya, za, ca);
+      spread_accumulate<NBZ>(cb, bb, qreg, m, acc);
+      if (!ha) break;
     }
   }
   __syncthreads();
 }
 
-template <int P>
+template <int P, int NBZ>
 __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, int bx) {
+  constexpr int CPW = kSpreadNBW / NBZ;
   extern __shared__ float smem[];
   const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
   const int sz[3] = {spread_pad4(Bx), spread_pad4(By), spread_pad4(Bz)};
-  const int S = spread_stride(sz[0] + sz[1] + sz[2]);
+  const int S = sz[0] + sz[1] + sz[2];
   float *cq = smem;                                                 // [cap][CGM]
   float *cw = cq + kSpreadCap * kSpreadCGM;                         // [cap][S]
   float *cf = cw + kSpreadCap * S;                                  // [cap][3] window offsets delta
@@ -558,24 +634,11 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
 
   for (int e = tid; e < kWinSeg * (kWinDeg + 1); e += kSpreadThreads) wcf[e] = t.win[e];
 
-  // 4x4x4 blocks, z fastest; wave w owns the per consecutive blocks
-  // [w per, w per + per), which run along z within a column
-  const int nbx = sz[0] >> 2, nby = sz[1] >> 2, nbz = sz[2] >> 2;
-  const int nblk = nbx * nby * nbz;
-  const int per = (nblk + kSpreadThreads / 64 - 1) / (kSpreadThreads / 64);
-  int bo[kSpreadNBW][3];
-  bool bval[kSpreadNBW], newcol[kSpreadNBW];
-#pragma unroll
-  for (int j = 0; j < kSpreadNBW; ++j) {
-    const int b = wave * per + j;
-    bval[j] = j < per && b < nblk;
-    const int bb = bval[j] ? b : 0;
-    const int col = bb / nbz, zb = bb - col * nbz;
-    bo[j][0] = (col / nby) * 4;
-    bo[j][1] = (col - (col / nby) * nby) * 4;
-    bo[j][2] = zb * 4;
-    newcol[j] = bval[j] && zb == 0;
-  }
+  // columns (x, y) of blocks, y fastest; wave w owns columns [CPW w, CPW w + CPW)
+  const int nby = sz[1] >> 2, ncol = (sz[0] >> 2) * nby;
+  const int col0 = wave * CPW;
+  const bool wval = col0 < ncol;
+  const int bo[3] = {wval ? (col0 / nby) * 4 : 0, wval ? (col0 % nby) * 4 : 0, 0};
   float acc[kSpreadNBW][kSpreadCGM];
 #pragma unroll
   for (int j = 0; j < kSpreadNBW; ++j)
@@ -644,7 +707,7 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
       base += kSpreadScreen;
     }
     if (ncand > kSpreadCap - kSpreadScreen || (done && ncand > 0)) {
-      spread_flush<P>(g, w, cg0, ncg, ncand, sz, cq, cw, cd, cf, ci, wcf, bo, bval, newcol, acc);
+      spread_flush<P, NBZ>(g, w, cg0, ncg, ncand, sz, cq, cw, cd, cf, ci, wcf, bo, wval, acc);
       ncand = 0;
     }
     if (done) break;
@@ -672,15 +735,16 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   const int lx = lane >> 4, ly = (lane >> 2) & 3, lz = lane & 3;
   for (int c0 = 0; c0 < ncg; c0 += cpp) {
     const int nc = min(cpp, ncg - c0);
+    if (wval) {
 #pragma unroll
-    for (int j = 0; j < kSpreadNBW; ++j) {
-      if (!bval[j]) continue;
-      const int x = bo[j][0] + lx, y = bo[j][1] + ly, z = bo[j][2] + lz;
-      if (x < Bx && y < By && z < Bz) {
-        float *dst = stage + (x * By + y) * Bz + z;
+      for (int j = 0; j < kSpreadNBW; ++j) {
+        const int x = bo[0] + lx, y = bo[1] + 4 * (j / NBZ) + ly, z = 4 * (j % NBZ) + lz;
+        if (x < Bx && y < By && z < Bz) {
+          float *dst = stage + (x * By + y) * Bz + z;
 #pragma unroll
-        for (int cc = 0; cc < kSpreadCGM; ++cc)
-          if (cc >= c0 && cc < c0 + nc) dst[(cc - c0) * nt] = acc[j][cc];
+          for (int cc = 0; cc < kSpreadCGM; ++cc)
+            if (cc >= c0 && cc < c0 + nc) dst[(cc - c0) * nt] = acc[j][cc];
+        }
       }
     }
     __syncthreads();
@@ -700,9 +764,9 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   }
 }
 
-template <int P>
+template <int P, int NBZ>
 __global__ __launch_bounds__(kSpreadThreads, 4) void k_spread(Geo g, Tables t, Work w, int cg0, int ncg) {
-  spread_body<P>(g, t, w, cg0, ncg, blockIdx.x);
+  spread_body<P, NBZ>(g, t, w, cg0, ncg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1240,15 +1304,17 @@ static inline unsigned nblocks(int64_t n, int per) { return unsigned((n + per - 
 
 size_t spread_lds_bytes(const Geo &g, int ncg) {
   (void)ncg;
-  const int S = (g.B[0] + 3) / 4 * 4 + (g.B[1] + 3) / 4 * 4 + (g.B[2] + 3) / 4 * 4;
-  return (size_t(spread_stage_floats(spread_stride(S))) + kWinSeg * (kWinDeg + 1)) * 4;
+  const int S = spread_pad4(g.B[0]) + spread_pad4(g.B[1]) + spread_pad4(g.B[2]);
+  return (size_t(spread_stage_floats(S)) + kWinSeg * (kWinDeg + 1)) * 4;
 }
 int spread_max_channels() { return kSpreadCGM; }
 bool spread_tile_ok(int bx, int by, int bz) {
-  const int nblk = ((bx + 3) / 4) * ((by + 3) / 4) * ((bz + 3) / 4);
-  const int S = (bx + 3) / 4 * 4 + (by + 3) / 4 * 4 + (bz + 3) / 4 * 4;
-  return nblk <= kSpreadNBW * kSpreadThreads / 64 && S <= kSpreadMaxS &&
-         bx * by * bz <= spread_stage_floats(spread_stride(S));
+  const int nbz = spread_nbz(bz);
+  if (nbz == 0) return false;
+  const int cpw = kSpreadNBW / nbz, nby = spread_pad4(by) / 4, ncol = (spread_pad4(bx) / 4) * nby;
+  const int S = spread_pad4(bx) + spread_pad4(by) + spread_pad4(bz);
+  return nby % cpw == 0 && ncol <= cpw * (kSpreadThreads / 64) && S <= kSpreadMaxS &&
+         bx * by * bz <= spread_stage_floats(S);
 }
 size_t gather_lds_bytes(const Geo &g, int ncg) {
   (void)ncg;
@@ -1324,14 +1390,24 @@ hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t
   return hipSuccess;
 }
 
-template <int P>
-static hipError_t spread_p(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
-  hipError_t e = lds_request(reinterpret_cast<const void *>(&k_spread<P>), spread_lds_bytes(g, ncg));
+template <int P, int NBZ>
+static hipError_t spread_pz(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
+  hipError_t e = lds_request(reinterpret_cast<const void *>(&k_spread<P, NBZ>), spread_lds_bytes(g, ncg));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_spread<P>, dim3(g.ncell), dim3(kSpreadThreads), spread_lds_bytes(g, ncg), st, g, t, w,
-                     cg0, ncg);
+  hipLaunchKernelGGL((k_spread<P, NBZ>), dim3(g.ncell), dim3(kSpreadThreads), spread_lds_bytes(g, ncg), st, g, t,
+                     w, cg0, ncg);
   LAUNCH_CHECK();
   return hipSuccess;
+}
+
+template <int P>
+static hipError_t spread_p(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
+  switch (spread_nbz(g.B[2])) {
+    case 1: return spread_pz<P, 1>(g, t, w, cg0, ncg, st);
+    case 2: return spread_pz<P, 2>(g, t, w, cg0, ncg, st);
+    case 4: return spread_pz<P, 4>(g, t, w, cg0, ncg, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_spread(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
@@ -1449,17 +1525,26 @@ __global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather
     case kBsOrder: order_body(g, it.w, vb); break;
     case kBsQsum: qsum_body(g, it.w, it.q, kQChunk, vb % it.qblocks, vb / it.qblocks); break;
     case kBsQreduce: qreduce_body(g, it.w, it.qblocks); break;
-    case kBsSpread:
+    case kBsSpread: {
+      const int nbz = spread_nbz(g.B[2]);
+#define PSWF_SPREAD_P(PP)                                                     \
+  case PP:                                                                     \
+    if (nbz == 4) spread_body<PP, 4>(g, it.t, it.w, 0, g.C, vb);               \
+    else if (nbz == 2) spread_body<PP, 2>(g, it.t, it.w, 0, g.C, vb);          \
+    else spread_body<PP, 1>(g, it.t, it.w, 0, g.C, vb);                        \
+    break;
       switch (g.P) {
-        case 2: spread_body<2>(g, it.t, it.w, 0, g.C, vb); break;
-        case 3: spread_body<3>(g, it.t, it.w, 0, g.C, vb); break;
-        case 4: spread_body<4>(g, it.t, it.w, 0, g.C, vb); break;
-        case 5: spread_body<5>(g, it.t, it.w, 0, g.C, vb); break;
-        case 6: spread_body<6>(g, it.t, it.w, 0, g.C, vb); break;
-        case 7: spread_body<7>(g, it.t, it.w, 0, g.C, vb); break;
-        default: spread_body<8>(g, it.t, it.w, 0, g.C, vb); break;
+        PSWF_SPREAD_P(2)
+        PSWF_SPREAD_P(3)
+        PSWF_SPREAD_P(4)
+        PSWF_SPREAD_P(5)
+        PSWF_SPREAD_P(6)
+        PSWF_SPREAD_P(7)
+        PSWF_SPREAD_P(8)
       }
+#undef PSWF_SPREAD_P
       break;
+    }
     case kBsZfwd: zfwd_body(g, it.t, it.az, it.w, it.nlines, vb); break;
     case kBsYfwd: {
       const int gx = (g.KZ + g.kb - 1) / g.kb;
