@@ -74,7 +74,8 @@ typedef struct {
   double tol;                        /* target relative tolerance, (0, 0.1]   */
   int32_t grid[3];                   /* M_x, M_y, M_z; 0: from tol. Each must
                                         factor into 2, 3, 5; M_z even;
-                                        support <= M <= PSWFLR_MAX_GRID      */
+                                        support <= M <= PSWFLR_MAX_GRID;
+                                        M_x M_y M_z < 2^30                   */
   int32_t support;                   /* P points per axis, 2..8; 0: from tol  */
   double c_spread;                   /* window bandwidth; <= 0: minimiser of a
                                         force-weighted aliasing estimate     */

@@ -15,7 +15,7 @@ import os
 import threading
 import time
 
-KERNEL_VERSION = 5
+KERNEL_VERSION = 6
 _LOCK = threading.Lock()
 
 
@@ -50,8 +50,8 @@ def _tile_fits(bx, by, bz, P, lds=160 * 1024):
     one, two or four blocks deep (NBZ), each wave owning NBZ blocks in each
     of 4/NBZ neighbouring y columns (so the y block count is a multiple of
     4/NBZ and there are at most 8 waves' worth of columns), padded edges
-    summing to <= 64.  Gather: a one-channel halo tile that fits LDS with at
-    most 128 (y, 16-wide z run) staging items."""
+    summing to <= 64.  Gather: a one-channel halo tile of at most 8192
+    elements (16 per thread)."""
     pad = lambda b: (b + 3) // 4 * 4
     nbz = pad(bz) // 4
     if nbz not in (1, 2, 4):
@@ -61,10 +61,10 @@ def _tile_fits(bx, by, bz, P, lds=160 * 1024):
     S = pad(bx) + pad(by) + pad(bz)
     if nby % cpw or (pad(bx) // 4) * nby > 8 * cpw or S > 64 or bx * by * bz > 256 * (12 + S + 5):
         return False
-    ey, ez = by + P - 1, bz + P - 1
-    if ey * ((ez + 15) // 16) > 128:
+    ex, ey, ez = bx + P - 1, by + P - 1, bz + P - 1
+    if ex * ey * (ez | 1) > 512 * 16:
         return False
-    return ((bx + P - 1) * ey * (ez | 1) + 96) * 4 <= lds
+    return (ex * ey * (ez | 1) + 96) * 4 <= lds
 
 
 def candidate_tiles(grid, P, limit=6):

@@ -1067,12 +1067,22 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis 
 constexpr int kGatherThreads = 512;
 constexpr int kGatherLanes = 4;                                 // lanes per atom
 constexpr int kGatherAtoms = kGatherThreads / kGatherLanes;     // atoms per pass
-constexpr int kGatherItems = 4;                                 // halo (y, 16-wide z run) items per thread
-constexpr unsigned kGatherOOB = 0x7ffffff0u;                    // byte offset past any grid plane
+constexpr int kGatherStage = 16;                                // halo elements staged per thread
+constexpr unsigned kGatherOOB = 0xfffffff0u;                    // byte offset past any grid channel
 // gfx9 raw buffer descriptor word 3 (32-bit dwords, range-checked offsets)
 constexpr int kBufferWord3 = 0x00020000;
 
 __host__ __device__ __forceinline__ int gather_sz(int ez) { return ez | 1; }  // odd row stride
+
+// one channel's halo elements at byte offsets goff (range-checked buffer
+// loads: offsets past the channel read as 0)
+__device__ __forceinline__ void gather_load_halo(const float *grid, int64_t chan, int c,
+                                                 const unsigned (&goff)[kGatherStage], float (&stage)[kGatherStage]) {
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float *>(grid + int64_t(c) * chan), 0, int(unsigned(chan * 4)), kBufferWord3);
+#pragma unroll
+  for (int r = 0; r < kGatherStage; ++r) stage[r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, goff[r], 0, 0));
+}
 
 template <int P>
 __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const Work &w, float *__restrict__ fout,
@@ -1093,26 +1103,26 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
   const int t0[3] = {cx * Bx, cy * By, cz * Bz};
   for (int k = tid; k < kWinSeg * (kWinDeg + 1); k += kGatherThreads) wcf[k] = t.win[k];
 
-  // halo rows this thread stages: items (y, z run) at (tid / 16) + 32 r,
-  // lane tid % 16 of the run; the same for every channel.  Byte offsets
-  // within an x-plane of the grid; unused items get an offset past the
-  // buffer range, which a buffer load returns as 0.
-  const int nzc = (EZ + 15) >> 4, nitems = EY * nzc;
-  unsigned gyz[kGatherItems];
-  int lofs[kGatherItems];
+  // halo elements this thread stages: linear LDS positions tid + 512 r of
+  // the [EX][EY][SZ] tile, the same for every channel.  Byte offsets within
+  // a channel of the grid; pad slots and unused positions get an offset
+  // past the buffer range, which a buffer load returns as 0.
+  const int ntile = EX * plane;
+  unsigned goff[kGatherStage];
 #pragma unroll
-  for (int r = 0; r < kGatherItems; ++r) {
-    const int it = (tid >> 4) + 32 * r;
-    const int y = it / nzc, z = (it - y * nzc) * 16 + (tid & 15);
-    int gy = t0[1] + y, gz = t0[2] + z;
+  for (int r = 0; r < kGatherStage; ++r) {
+    const int el = tid + kGatherThreads * r;
+    const int x = el / plane, rem = el - x * plane, y = rem / SZ, z = rem - y * SZ;
+    int gx = t0[0] + x, gy = t0[1] + y, gz = t0[2] + z;
+    if (gx >= g.M[0]) gx -= g.M[0];
     if (gy >= g.M[1]) gy -= g.M[1];
     if (gz >= g.M[2]) gz -= g.M[2];
-    const bool ok = it < nitems && z < EZ;
-    gyz[r] = ok ? unsigned(gy * g.M[2] + gz) * 4u : kGatherOOB;
-    lofs[r] = ok ? y * SZ + z : -1;
+    goff[r] = (el < ntile && z < EZ) ? unsigned((gx * g.M[1] + gy) * g.M[2] + gz) * 4u : kGatherOOB;
   }
-  const int MyMz = g.M[1] * g.M[2];
-  const int64_t chan = int64_t(g.M[0]) * MyMz;
+  const int64_t chan = int64_t(g.M[0]) * g.M[1] * g.M[2];
+  // the next channel's halo is loaded into registers while the current one
+  // is contracted, then written to LDS between two barriers
+  float stage[kGatherStage];
   const int l = tid & (kGatherLanes - 1);
   const float sg = mode == 2 ? -1.0f : 1.0f;
   __syncthreads();  // window coefficients
@@ -1159,32 +1169,17 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
     const int base = o[0] * plane + o[1] * SZ + o[2];
     float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 
+    gather_load_halo(w.grid, chan, 0, goff, stage);
     for (int c = 0; c < g.C; ++c) {
       const float qv = w.q_a[int64_t(c) * g.N + a];
       __syncthreads();  // the tile buffer is free
-      {
-        const float *gch = w.grid + int64_t(c) * chan;
-        for (int x0 = 0; x0 < EX; x0 += 4) {
-          float v[4][kGatherItems];
 #pragma unroll
-          for (int xi = 0; xi < 4; ++xi) {
-            int gx = t0[0] + min(x0 + xi, EX - 1);
-            if (gx >= g.M[0]) gx -= g.M[0];
-            const __amdgpu_buffer_rsrc_t plane_rs = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<float *>(gch + int64_t(gx) * MyMz), 0, MyMz * 4, kBufferWord3);
-#pragma unroll
-            for (int r = 0; r < kGatherItems; ++r) v[xi][r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(plane_rs, gyz[r], 0, 0));
-          }
-#pragma unroll
-          for (int xi = 0; xi < 4; ++xi) {
-            if (x0 + xi >= EX) break;
-#pragma unroll
-            for (int r = 0; r < kGatherItems; ++r)
-              if (lofs[r] >= 0) tile[(x0 + xi) * plane + lofs[r]] = v[xi][r];
-          }
-        }
+      for (int r = 0; r < kGatherStage; ++r) {
+        const int el = tid + kGatherThreads * r;
+        if (el < ntile) tile[el] = stage[r];
       }
       __syncthreads();
+      if (c + 1 < g.C) gather_load_halo(w.grid, chan, c + 1, goff, stage);
       float vphi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
 #pragma unroll 1
       for (int j = 0; j < R; ++j) {
@@ -1327,8 +1322,8 @@ bool gather_tile_ok(int bx, int by, int bz, int P) {
   g.B[1] = by;
   g.B[2] = bz;
   g.P = P;
-  const int ey = by + P - 1, ez = bz + P - 1;
-  return ey * ((ez + 15) / 16) <= 32 * kGatherItems && gather_lds_bytes(g, 1) <= 160 * 1024;
+  const int ex = bx + P - 1, ey = by + P - 1, ez = bz + P - 1;
+  return ex * ey * gather_sz(ez) <= kGatherThreads * kGatherStage && gather_lds_bytes(g, 1) <= 160 * 1024;
 }
 size_t zpass_lds_bytes(const Geo &g) { return (size_t(g.Nz) * (g.zlines + 1) + 2 * g.Nz + 1) * 8; }
 size_t ypass_lds_bytes(const Geo &g) { return (size_t(g.M[1]) * (g.kb + 1) + g.M[1]) * 8; }

@@ -132,6 +132,9 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
     if (!is_smooth235(M[a])) return fail(PSWFLR_ERR_UNSUPPORTED, "grid edges must factor into 2, 3 and 5");
   }
   if (M[2] % 2) return fail(PSWFLR_ERR_UNSUPPORTED, "M_z must be even (real-to-complex transform)");
+  // one channel's grid is addressed with 32-bit byte offsets
+  if (int64_t(M[0]) * M[1] * M[2] >= (int64_t(1) << 30))
+    return fail(PSWFLR_ERR_UNSUPPORTED, "a channel's grid must hold fewer than 2^30 points");
   double eta = 0.0, h[3];
   for (int a = 0; a < 3; ++a) {
     h[a] = p.box[a] / M[a];
