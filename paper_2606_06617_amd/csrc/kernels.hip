@@ -131,6 +131,27 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Copy `count` elements with every load of a thread in flight at once:
+// load(e) for e = tid, tid + 256, ... (up to 16 per thread per round) into
+// registers, then store(e, v).  Loads of the staging loops otherwise issue
+// one at a time behind a wait each.
+template <typename LoadF, typename StoreF>
+__device__ __forceinline__ void staged16(int count, LoadF &&load, StoreF &&store) {
+  for (int base = 0; base < count; base += 16 * PSWF_THREADS) {
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int e = base + int(threadIdx.x) + r * PSWF_THREADS;
+      v[r] = e < count ? load(e) : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int e = base + int(threadIdx.x) + r * PSWF_THREADS;
+      if (e < count) store(e, v[r]);
+    }
+  }
+}
+
 template <int R, int S, int MAXE>
 __device__ __forceinline__ void fft_stage(float2 *buf, int n, int ns, const FastDiv &nsd, int lw_log2, int ld,
                                           const float2 *tw, int lane, int wave) {
@@ -787,10 +808,13 @@ __device__ __forceinline__ void zfwd_body(const Geo &g, const Tables &t, const F
   for (int e = tid; e < Nz; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_z)[e];
   for (int e = tid; e <= Nz; e += PSWF_THREADS) twr[e] = reinterpret_cast<const float2 *>(t.tw_zr)[e];
   const float2 *src = reinterpret_cast<const float2 *>(w.grid) + line0 * Nz;
-  for (int e = tid; e < L * Nz; e += PSWF_THREADS) {
-    const int line = fdiv(e, g.div_nz), n = e - line * Nz;
-    buf[n * ld + line] = line < nl ? src[e] : make_float2(0.f, 0.f);
-  }
+  staged16(
+      L * Nz,
+      [&](int e) { return fdiv(e, g.div_nz) < nl ? src[e] : make_float2(0.f, 0.f); },
+      [&](int e, float2 v) {
+        const int line = fdiv(e, g.div_nz), n = e - line * Nz;
+        buf[n * ld + line] = v;
+      });
   __syncthreads();
   lds_fft<-1, 16>(buf, ax, llog - 2, ld, tw, tid);
   __syncthreads();
@@ -824,10 +848,13 @@ __device__ __forceinline__ void yfwd_body(const Geo &g, const Tables &t, const F
   const int ncol = min(kb, g.KZ - kz0);
   for (int e = tid; e < My; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_y)[e];
   const float2 *src = reinterpret_cast<const float2 *>(w.s1) + plane * My * g.KZ;
-  for (int e = tid; e < My * kb; e += PSWF_THREADS) {
-    const int y = e >> g.kb_log2, col = e & (kb - 1);
-    buf[y * ld + col] = col < ncol ? src[int64_t(y) * g.KZ + kz0 + col] : make_float2(0.f, 0.f);
-  }
+  staged16(
+      My * kb,
+      [&](int e) {
+        const int y = e >> g.kb_log2, col = e & (kb - 1);
+        return col < ncol ? src[int64_t(y) * g.KZ + kz0 + col] : make_float2(0.f, 0.f);
+      },
+      [&](int e, float2 v) { buf[(e >> g.kb_log2) * ld + (e & (kb - 1))] = v; });
   __syncthreads();
   lds_fft<-1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
   __syncthreads();
@@ -901,10 +928,13 @@ __device__ __forceinline__ void xmul_body(const Geo &g, const Tables &t, const F
   }
   const int64_t xstride = int64_t(g.NY) * g.KZ;
   float2 *col0 = reinterpret_cast<float2 *>(w.s2) + int64_t(c) * Mx * xstride + int64_t(iy) * g.KZ + kz0;
-  for (int e = tid; e < Mx * kb; e += PSWF_THREADS) {
-    const int x = e >> g.kb_log2, col = e & (kb - 1);
-    buf[x * ld + col] = col < ncol ? col0[x * xstride + col] : make_float2(0.f, 0.f);
-  }
+  staged16(
+      Mx * kb,
+      [&](int e) {
+        const int x = e >> g.kb_log2, col = e & (kb - 1);
+        return col < ncol ? col0[x * xstride + col] : make_float2(0.f, 0.f);
+      },
+      [&](int e, float2 v) { buf[(e >> g.kb_log2) * ld + (e & (kb - 1))] = v; });
   __syncthreads();
   lds_fft<-1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
   __syncthreads();
@@ -982,13 +1012,18 @@ __device__ __forceinline__ void yinv_body(const Geo &g, const Tables &t, const F
   for (int e = tid; e < My * ld; e += PSWF_THREADS) buf[e] = make_float2(0.f, 0.f);
   __syncthreads();
   const float2 *src = reinterpret_cast<const float2 *>(w.s2) + plane * g.NY * g.KZ;
-  for (int e = tid; e < g.NY * kb; e += PSWF_THREADS) {
-    const int iy = e >> g.kb_log2, col = e & (kb - 1);
-    const int kz = kz0 + col;
-    if (col >= ncol || kz >= t.blim[iy]) continue;
-    const int my = iy <= g.FY ? iy : My - g.NY + iy;
-    buf[my * ld + col] = src[int64_t(iy) * g.KZ + kz];
-  }
+  staged16(
+      g.NY * kb,
+      [&](int e) {
+        const int iy = e >> g.kb_log2, col = e & (kb - 1);
+        const int kz = kz0 + col;
+        return (col < ncol && kz < t.blim[iy]) ? src[int64_t(iy) * g.KZ + kz] : make_float2(0.f, 0.f);
+      },
+      [&](int e, float2 v) {
+        const int iy = e >> g.kb_log2, col = e & (kb - 1);
+        const int my = iy <= g.FY ? iy : My - g.NY + iy;
+        buf[my * ld + col] = v;
+      });
   __syncthreads();
   lds_fft<1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
   __syncthreads();
@@ -1019,22 +1054,35 @@ __device__ __forceinline__ void zinv_body(const Geo &g, const Tables &t, const F
   for (int e = tid; e < Nz; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_z)[e];
   for (int e = tid; e <= Nz; e += PSWF_THREADS) twr[e] = reinterpret_cast<const float2 *>(t.tw_zr)[e];
   __syncthreads();
+  // stage the KZ stored modes of each line (coalesced rows), then form the
+  // packed half-length spectrum in place, one (k, N - k) pair per thread
   const float2 *src = reinterpret_cast<const float2 *>(w.s1) + line0 * g.KZ;
-  for (int e = tid; e < L * Nz; e += PSWF_THREADS) {
-    const int line = fdiv(e, g.div_nz), k = e - line * Nz;
-    float2 z = make_float2(0.f, 0.f);
-    if (line < nl) {
-      const float2 xk = k < g.KZ ? src[int64_t(line) * g.KZ + k] : make_float2(0.f, 0.f);
-      const int km = Nz - k;  // 1..Nz
-      const float2 xm = km < g.KZ ? src[int64_t(line) * g.KZ + km] : make_float2(0.f, 0.f);
-      const float2 a = make_float2(xk.x + xm.x, xk.y - xm.y);    // X_k + conj X_{N-k}
-      const float2 b = make_float2(xk.x - xm.x, xk.y + xm.y);    // X_k - conj X_{N-k}
-      float2 wv = twr[k];
-      wv.y = -wv.y;                                              // exp(+2 pi i k / M_z)
+  staged16(
+      L * g.KZ,
+      [&](int e) { return fdiv(e, g.div_kz) < nl ? src[e] : make_float2(0.f, 0.f); },
+      [&](int e, float2 v) {
+        const int line = fdiv(e, g.div_kz), k = e - line * g.KZ;
+        buf[k * ld + line] = v;
+      });
+  __syncthreads();
+  const int half = Nz / 2;
+  for (int e = tid; e < L * (half + 1); e += PSWF_THREADS) {
+    const int line = e & (L - 1), k = e >> llog;  // k in [0, Nz/2]
+    const int km = Nz - k;                        // partner; Nz itself is the dropped Nyquist mode
+    const float2 xk = k < g.KZ ? buf[k * ld + line] : make_float2(0.f, 0.f);
+    const float2 xm = km < g.KZ ? buf[km * ld + line] : make_float2(0.f, 0.f);
+    // Z'_j = (X_j + conj X_{N-j}) + i exp(+2 pi i j / M_z) (X_j - conj X_{N-j})
+    auto zmode = [&](float2 xa, float2 xb, int j) {
+      const float2 a = make_float2(xa.x + xb.x, xa.y - xb.y);
+      const float2 b = make_float2(xa.x - xb.x, xa.y + xb.y);
+      float2 wv = twr[j];
+      wv.y = -wv.y;
       const float2 ib = cmul(wv, b);
-      z = make_float2(a.x - ib.y, a.y + ib.x);
-    }
-    buf[k * ld + line] = z;
+      return make_float2(a.x - ib.y, a.y + ib.x);
+    };
+    const float2 zk = zmode(xk, xm, k);
+    if (km < Nz && km != k) buf[km * ld + line] = zmode(xm, xk, km);
+    buf[k * ld + line] = zk;
   }
   __syncthreads();
   lds_fft<1, 16>(buf, ax, llog - 2, ld, tw, tid);
