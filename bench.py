@@ -84,6 +84,51 @@ def measured_traffic(workload_name, kernel):
     return rows[kernel]
 
 
+def serving_leg(nreq=400, seed=6, fractions=(0.5, 0.8, 0.95), slots=4):
+    """Continuous-batching latency on the Poisson request mix (sizes
+    log-uniform in [100, 5e4] atoms, density 0.1, channels p = 1 and 6,
+    tolerance 1e-5): the one-at-a-time capacity is measured first (one
+    slot, requests back to back), then the same requests arrive as Poisson
+    processes at the given fractions of it and are served with `slots`
+    overlapping evaluations.  Latency = completion - arrival, including the
+    host plan, both copies and the evaluation."""
+    from paper_2606_06617_amd import workloads as wl
+    from paper_2606_06617_amd.serving import HipExecutor, Server, latency_stats, make_requests
+
+    stream = wl.serving_stream(nreq=nreq, rate=1.0, seed=seed)
+    reqs = make_requests(stream)
+    # warm the host caches that plans of any box share (window bandwidth
+    # grid, kernel fits) and the device code paths
+    ex = HipExecutor(slots=1)
+    for r in reqs:
+        ex.prepare(r)
+    warm = Server(HipExecutor(slots=1))
+    warm.run_trace([reqs[i] for i in range(min(8, nreq))], realtime=False)
+    warm.close()
+    solo = Server(HipExecutor(slots=1))
+    t0 = time.perf_counter()
+    done = solo.run_trace(reqs, realtime=False)
+    span = time.perf_counter() - t0
+    solo.close()
+    capacity = nreq / span
+    out = {"requests_per_rate": nreq, "capacity_req_s": round(capacity, 1),
+           "atoms_per_request": "log-uniform [100, 50000]", "slots": slots, "rates": []}
+    rng = np.random.default_rng(seed + 1)
+    for f in fractions:
+        gaps = rng.exponential(1.0 / (f * capacity), size=nreq)
+        for r, t in zip(reqs, np.cumsum(gaps)):
+            r.t_arrival, r.t_done, r.t_admit, r.t_ready, r.error = float(t), None, None, None, None
+        srv = Server(HipExecutor(slots=slots))
+        res = srv.run_trace(reqs, realtime=True)
+        srv.close()
+        st = latency_stats(res)
+        out["rates"].append({"load": f, "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                             "mean_ms": round(st["mean_ms"], 3), "req_s": round(st["throughput_req_s"], 1),
+                             "max_concurrency": srv.max_concurrency})
+    del done
+    return out
+
+
 def cpu_baseline(w, n_sample=48):
     """The FP64 oracle (direct structure-factor sum over the same k-ball with
     energy, forces and virial) timed single-threaded on a bounded sample:
@@ -128,6 +173,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="ionic_1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching latency leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also launch one plain device-to-device copy of this many MiB (a known-size "
                          "kernel that calibrates FETCH_SIZE / WRITE_SIZE counter readings)")
@@ -229,6 +275,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         rec["calib_copy_bytes"] = 2 * src.numel() * 4
+    if not args.no_serving:
+        rec["serving"] = serving_leg()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)

@@ -327,8 +327,20 @@ PiecewisePoly fit_piecewise(F f, int nseg, int deg, double eps) {
 }
 
 PiecewisePoly make_window_poly(double c_s, int nseg, int deg, double eps) {
+  // plans of a serving mix share a handful of bandwidths: cache the fits
+  static std::mutex mu;
+  static std::map<std::tuple<long, int, int, long>, PiecewisePoly> cache;
+  const auto key = std::make_tuple(std::lround(c_s * 1e6), nseg, deg, std::lround(std::log10(eps) * 100));
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
   auto ws = prolate_cached(c_s);
-  return fit_piecewise([&](double x) { return (*ws)(x); }, nseg, deg, eps);
+  PiecewisePoly fit = fit_piecewise([&](double x) { return (*ws)(x); }, nseg, deg, eps);
+  std::lock_guard<std::mutex> lock(mu);
+  cache.emplace(key, fit);
+  return fit;
 }
 
 // ---------------------------------------------------------------------------
@@ -378,7 +390,25 @@ double phi_hat_deriv(const Prolate &ps, int p, double k, double c, double r_c) {
   throw std::invalid_argument("p must be 1..6");
 }
 
+static ChannelKernel build_channel_kernel(int p, double c, double r_c, double eps);
+
 ChannelKernel make_channel_kernel(int p, double c, double r_c, double eps) {
+  // box-independent: one fit per (p, c, r_c) serves every structure
+  static std::mutex mu;
+  static std::map<std::tuple<int, long, long, long>, ChannelKernel> cache;
+  const auto key = std::make_tuple(p, std::lround(c * 1e9), std::lround(r_c * 1e9), std::lround(std::log10(eps) * 100));
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  ChannelKernel ck = build_channel_kernel(p, c, r_c, eps);
+  std::lock_guard<std::mutex> lock(mu);
+  cache.emplace(key, ck);
+  return ck;
+}
+
+static ChannelKernel build_channel_kernel(int p, double c, double r_c, double eps) {
   auto psp = prolate_cached(c);
   const Prolate &ps = *psp;
   const double K = c / r_c, C0 = ps.C0();
@@ -512,24 +542,13 @@ double estimate_spread_error(int P, double eta, double c_s, double c_moll) {
   return std::sqrt(num / den);
 }
 
-double choose_c_spread(int P, double eta, double c_moll) {
-  static std::mutex mu;
-  static std::map<std::tuple<int, long, long>, double> cache;
-  // eta is rounded up to a multiple of 0.005 (a slightly coarser grid is the
-  // conservative side) so that boxes of nearby shapes share one search
-  eta = std::ceil(eta * 200.0 - 1e-9) / 200.0;
-  auto key = std::make_tuple(P, std::lround(eta * 1e4), std::lround(c_moll * 1e4));
-  {
-    std::lock_guard<std::mutex> lock(mu);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-  }
-  // golden-section search on log(error) over [2.2 P, 3.2 P]
+// minimiser of the estimate at one eta (golden-section search on [2.2 P, 3.2 P])
+static double search_c_spread(int P, double eta, double c_moll) {
   double a = 2.2 * P, b = 3.2 * P;
   const double g = 0.5 * (std::sqrt(5.0) - 1.0);
   double x1 = b - g * (b - a), x2 = a + g * (b - a);
   double f1 = estimate_spread_error(P, eta, x1, c_moll), f2 = estimate_spread_error(P, eta, x2, c_moll);
-  for (int it = 0; it < 18; ++it) {
+  for (int it = 0; it < 14; ++it) {  // bracket 0.01 P: the estimate is flat near its minimum
     if (f1 < f2) {
       b = x2; x2 = x1; f2 = f1; x1 = b - g * (b - a);
       f1 = estimate_spread_error(P, eta, x1, c_moll);
@@ -538,10 +557,40 @@ double choose_c_spread(int P, double eta, double c_moll) {
       f2 = estimate_spread_error(P, eta, x2, c_moll);
     }
   }
-  double best = std::round(0.5 * (a + b) * 1e3) / 1e3;
-  std::lock_guard<std::mutex> lock(mu);
-  cache[key] = best;
-  return best;
+  return 0.5 * (a + b);
+}
+
+double choose_c_spread(int P, double eta, double c_moll) {
+  // The minimiser is a smooth, slowly varying function of eta (the error
+  // is flat near it), so it is searched on a grid of eta with step 1/40 and
+  // interpolated linearly; grid points are computed on first use and cached,
+  // so plans for boxes of any shape after the first few cost no search.
+  static std::mutex mu;
+  static std::map<std::tuple<int, long, long>, double> cache;
+  const double step = 1.0 / 40.0;
+  const double u = std::max(eta, step) / step;
+  const long i0 = long(std::floor(u));
+  double v[2];
+  for (int j = 0; j < 2; ++j) {
+    const long i = i0 + j;
+    const auto key = std::make_tuple(P, i, std::lround(c_moll * 1e6));
+    bool hit = false;
+    {
+      std::lock_guard<std::mutex> lock(mu);
+      auto it = cache.find(key);
+      if (it != cache.end()) {
+        v[j] = it->second;
+        hit = true;
+      }
+    }
+    if (!hit) {
+      v[j] = search_c_spread(P, std::min(0.99, i * step), c_moll);
+      std::lock_guard<std::mutex> lock(mu);
+      cache[key] = v[j];
+    }
+  }
+  const double f = u - double(i0);
+  return std::round(((1.0 - f) * v[0] + f * v[1]) * 1e3) / 1e3;
 }
 
 bool is_smooth235(int m) {

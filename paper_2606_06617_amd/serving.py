@@ -5,8 +5,11 @@ exponents) arrive over time.  The scheduler keeps several evaluations in
 flight on separate HIP streams, so requests that arrive while others run are
 admitted as soon as a slot is free and their HBM footprint (workspace +
 inputs + outputs) fits the budget, and their work overlaps on the device.
-Plans (the per-box host set-up) are built on a worker pool as requests
-arrive, off the scheduling path.  Each request's result does not depend on
+Plans (the per-box host set-up, a fraction of a millisecond once the
+shared host caches are warm) are built as requests arrive: inline by
+default, or on a worker pool (plan_workers > 0) -- Python threads share one
+interpreter lock, which can delay the scheduling loop by its switch
+interval, so the pool only pays when plan building is slow.  Each request's result does not depend on
 what else is in flight: every kernel works on one structure's own buffers
 and all reductions have a fixed order.
 
@@ -119,10 +122,11 @@ class Server:
     A request whose footprint alone exceeds the budget is rejected.
     """
 
-    def __init__(self, executor, budget=None, plan_workers=4, clock=time.perf_counter):
+    def __init__(self, executor, budget=None, plan_workers=0, clock=time.perf_counter):
         self.ex = executor
         self.budget = int(budget) if budget is not None else executor.budget_default()
-        self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=plan_workers)
+        self.pool = (concurrent.futures.ThreadPoolExecutor(max_workers=plan_workers)
+                     if plan_workers > 0 else None)
         self.clock = clock
         self.pending = collections.deque()        # (req, future of (plan, footprint))
         self.inflight = {}                         # slot -> (req, plan, token)
@@ -138,7 +142,15 @@ class Server:
     def submit(self, req):
         if self.t0 is None:
             self.t0 = self.clock()
-        self.pending.append((req, self.pool.submit(self.ex.prepare, req)))
+        if self.pool is not None:
+            fut = self.pool.submit(self.ex.prepare, req)
+        else:
+            fut = concurrent.futures.Future()
+            try:
+                fut.set_result(self.ex.prepare(req))
+            except Exception as exc:  # failed at admission, reported there
+                fut.set_exception(exc)
+        self.pending.append((req, fut))
 
     def _retire(self):
         for slot in list(self.inflight):
@@ -209,7 +221,8 @@ class Server:
         return order
 
     def close(self):
-        self.pool.shutdown(wait=True)
+        if self.pool is not None:
+            self.pool.shutdown(wait=True)
 
 
 def latency_stats(reqs):

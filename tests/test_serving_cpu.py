@@ -66,10 +66,12 @@ def _drive(server, clock, reqs, dt=1e-4, tmax=10.0):
     return order
 
 
-def test_admission_respects_budget_and_overlaps():
+@pytest.mark.parametrize("plan_workers", [0, 2])
+def test_admission_respects_budget_and_overlaps(plan_workers):
     clock = FakeClock()
     ex = SimExecutor(clock, slots=4)
-    srv = Server(ex, budget=250_000, clock=clock)   # at most two 1000-atom requests in flight
+    # at most two 1000-atom requests in flight; plans inline or on a pool
+    srv = Server(ex, budget=250_000, clock=clock, plan_workers=plan_workers)
     reqs = [_req(i, 1000, 0.0) for i in range(6)]
     out = _drive(srv, clock, reqs)
     assert all(r.error is None and r.t_done is not None for r in out)
