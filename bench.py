@@ -84,6 +84,46 @@ def measured_traffic(workload_name, kernel):
     return rows[kernel]
 
 
+def batch_leg(reps=10):
+    """The 64-structure training batch (N in [200, 4000], grids 24^3-64^3,
+    p = 1 and 6, forces and virial): one batched call (a launch per stage
+    over all structures) against the same structures evaluated one after
+    another, both with workspaces reused; atoms/s over the batch."""
+    import torch
+
+    from paper_2606_06617_amd import workloads as wl
+    from paper_2606_06617_amd.api import Plan, execute_batch
+
+    structs = wl.diff_batch()
+    dev = torch.device("cuda:0")
+    plans = [Plan(st["box"], st["ps"], r_c=R_C, c=C_MOL, grid=st["grid"], support=st["support"] or 0,
+                  max_atoms=st["pos"].shape[0]) for st in structs]
+    inputs = [(torch.from_numpy(st["pos"]).to(dev), torch.from_numpy(st["q"]).to(dev)) for st in structs]
+    atoms = sum(int(x[0].shape[0]) for x in inputs)
+    outs, ws = execute_batch(plans, inputs)
+    for _ in range(2):
+        outs, ws = execute_batch(plans, inputs, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        outs, ws = execute_batch(plans, inputs, workspace=ws)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    wss = [p.new_workspace(dev) for p in plans]
+    for p, (pos, q), w_ in zip(plans, inputs, wss):
+        p.execute(pos, q, forces=True, virial=True, workspace=w_)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for p, (pos, q), w_ in zip(plans, inputs, wss):
+            p.execute(pos, q, forces=True, virial=True, workspace=w_)
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / reps
+    return {"structures": len(structs), "atoms": atoms, "support": plans[0].info["support"],
+            "batched_ms": round(t_batch * 1e3, 3), "batched_atoms_s": round(atoms / t_batch, 1),
+            "sequential_ms": round(t_seq * 1e3, 3), "sequential_atoms_s": round(atoms / t_seq, 1)}
+
+
 def serving_leg(nreq=400, seed=6, fractions=(0.5, 0.8, 0.95), slots=4):
     """Continuous-batching latency on the Poisson request mix (sizes
     log-uniform in [100, 5e4] atoms, density 0.1, channels p = 1 and 6,
@@ -174,6 +214,7 @@ def main():
     ap.add_argument("--workload", default="ionic_1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching latency leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-structure batch leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also launch one plain device-to-device copy of this many MiB (a known-size "
                          "kernel that calibrates FETCH_SIZE / WRITE_SIZE counter readings)")
@@ -275,6 +316,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         rec["calib_copy_bytes"] = 2 * src.numel() * 4
+    if not args.no_batch:
+        rec["batch"] = batch_leg()
     if not args.no_serving:
         rec["serving"] = serving_leg()
     if not args.no_cpu_baseline:

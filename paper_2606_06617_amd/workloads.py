@@ -118,15 +118,16 @@ def ionic(n=1_000_000, nlatent=4, ps=(1, 3, 6), grid=256, support=8, seed=3):
                    "ionic_%d" % n)
 
 
-def smooth_size(x, lo=None, hi=None, primes=(2, 3)):
-    """Smallest integer >= x whose prime factors are all in `primes`."""
+def smooth_size(x, lo=None, hi=None, primes=(2, 3), even=True):
+    """Smallest integer >= x whose prime factors are all in `primes` (and
+    even if asked: the z axis of the real-to-complex transform needs it)."""
     m = max(1, int(math.ceil(x - 1e-9)))
     while True:
         r = m
         for pr in primes:
             while r % pr == 0:
                 r //= pr
-        if r == 1:
+        if r == 1 and (m % 2 == 0 or not even):
             break
         m += 1
     if lo is not None:
