@@ -15,7 +15,7 @@ import os
 import threading
 import time
 
-KERNEL_VERSION = 6
+KERNEL_VERSION = 7
 _LOCK = threading.Lock()
 
 
@@ -59,7 +59,7 @@ def _tile_fits(bx, by, bz, P, lds=160 * 1024):
     cpw = 4 // nbz
     nby = pad(by) // 4
     S = pad(bx) + pad(by) + pad(bz)
-    if nby % cpw or (pad(bx) // 4) * nby > 8 * cpw or S > 64 or bx * by * bz > 256 * (12 + S + 5):
+    if nby % cpw or (pad(bx) // 4) * nby > 8 * cpw or S > 64 or bx * by * bz > 256 * (12 + S):
         return False
     ex, ey, ez = bx + P - 1, by + P - 1, bz + P - 1
     if ex * ey * (ez | 1) > 512 * 16:
@@ -75,6 +75,11 @@ def candidate_tiles(grid, P, limit=6):
         for by in _divisors(grid[1]):
             for bz in _divisors(grid[2]):
                 if not _tile_fits(bx, by, bz, P):
+                    continue
+                cells = 1
+                for m, b in zip(grid, (bx, by, bz)):
+                    cells *= min(min(m // b - 1, (P - 2) // b + 1) + 1, 8)
+                if cells > 64:
                     continue
                 eff = bx / (bx + P - 1) * by / (by + P - 1) * bz / (bz + P - 1)
                 ncell = (grid[0] // bx) * (grid[1] // by) * (grid[2] // bz)

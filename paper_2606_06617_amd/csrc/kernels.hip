@@ -436,7 +436,9 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nbl
 // summation order is fixed, so the result is bitwise reproducible.
 constexpr int kSpreadThreads = 512;
 constexpr int kSpreadCap = 256;     // candidates staged per flush
-constexpr int kSpreadScreen = 128;  // atoms screened per chunk (two waves)
+constexpr int kSpreadScreenPer = 1; // atoms screened per thread per round
+constexpr int kSpreadList = kSpreadCap + kSpreadScreenPer * 512;  // screened-candidate list
+constexpr int kSpreadMaxCells = 64; // candidate cells of a tile
 constexpr int kSpreadCGM = 12;      // channels per launch
 constexpr int kSpreadNBW = 4;       // 4x4x4 blocks per wave
 constexpr int kSpreadMaxS = 64;     // padded tile edges Sx + Sy + Sz
@@ -444,8 +446,13 @@ constexpr int kSpreadBias = 8;      // packed window offsets are stored + bias
 constexpr int kSpreadMaxPts = kSpreadNBW * (kSpreadThreads / 64) * 64;  // tile points
 constexpr int kSpreadOutMax = (kSpreadMaxPts + kSpreadThreads - 1) / kSpreadThreads;  // scalar elements/thread
 
-// LDS floats of the candidate staging area for padded edges summing to S
-__host__ __device__ __forceinline__ int spread_stage_floats(int S) { return kSpreadCap * (kSpreadCGM + S + 5); }
+// LDS floats of the candidate staging area (charges and weights) for padded
+// edges summing to S; the screened-candidate list, the candidate-cell table
+// and the window coefficients follow it
+__host__ __device__ __forceinline__ int spread_stage_floats(int S) { return kSpreadCap * (kSpreadCGM + S); }
+__host__ __device__ __forceinline__ int spread_lds_floats(int S) {
+  return spread_stage_floats(S) + 5 * kSpreadList + 2 * kSpreadMaxCells + 1 + kWinSeg * (kWinDeg + 1);
+}
 __host__ __device__ __forceinline__ int spread_pad4(int b) { return (b + 3) & ~3; }
 // blocks along z of a tile edge (1, 2 or 4 supported); 0 if unsupported
 __host__ __device__ __forceinline__ int spread_nbz(int bz) {
@@ -535,29 +542,38 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
   const int S = sz[0] + sz[1] + sz[2];
   const int soff[3] = {0, sz[0], sz[0] + sz[1]};
   // (1) per candidate and axis, the window weights over the padded tile
-  // edge; z position zz is stored at (zz % 4) NBZ + zz / 4
+  // edge (zero outside the window); z position zz is stored at
+  // (zz % 4) NBZ + zz / 4.  The window positions of one candidate are
+  // distinct (P <= M), so they are plain stores after a zero fill whose
+  // start rotates with the candidate (no bank conflicts between lanes).
   for (int t = tid; t < 3 * kSpreadCap; t += kSpreadThreads) {
     const int a = t / kSpreadCap, k = t - a * kSpreadCap;
     if (k >= ncand) continue;
+    float qv[kSpreadCGM];
+    if (a == 0) {
+      // all charge loads in flight at once (channel index clamped, unused
+      // channels zeroed when stored)
+      const int i = ci[k];
+#pragma unroll
+      for (int c = 0; c < kSpreadCGM; ++c) qv[c] = w.q_a[int64_t(cg0 + min(c, ncg - 1)) * g.N + i];
+    }
     const int d = ((cd[k] >> (10 * a)) & 1023) - kSpreadBias;  // tile-relative window start
     const float r = cf[3 * k + a];
     float *dst = cw + k * S + soff[a];
-    for (int x = 0; x < sz[a]; ++x) dst[x] = 0.0f;
+    const int sa = sz[a];
+    for (int x = 0, xx = k % sa; x < sa; ++x) {
+      dst[xx] = 0.0f;
+      if (++xx == sa) xx = 0;
+    }
     const int Ma = g.M[a], Ba = g.B[a];
 #pragma unroll
     for (int l = 0; l < P; ++l) {
       int x = d + l;
       if (x < 0) x += Ma;
       if (x >= Ma) x -= Ma;
-      if (x < Ba) dst[a == 2 ? (x & 3) * NBZ + (x >> 2) : x] += win_eval(wcf, (2.0f * (l + r)) / P - 1.0f);
+      if (x < Ba) dst[a == 2 ? (x & 3) * NBZ + (x >> 2) : x] = win_eval(wcf, (2.0f * (l + r)) / P - 1.0f);
     }
     if (a == 0) {
-      // all charge loads in flight at once (channel index clamped, unused
-      // channels zeroed afterwards)
-      const int i = ci[k];
-      float qv[kSpreadCGM];
-#pragma unroll
-      for (int c = 0; c < kSpreadCGM; ++c) qv[c] = w.q_a[int64_t(cg0 + min(c, ncg - 1)) * g.N + i];
 #pragma unroll
       for (int c = 0; c < kSpreadCGM; c += 4)
         *reinterpret_cast<float4 *>(cq + k * kSpreadCGM + c) =
@@ -639,12 +655,14 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   const int S = sz[0] + sz[1] + sz[2];
   float *cq = smem;                                                 // [cap][CGM]
   float *cw = cq + kSpreadCap * kSpreadCGM;                         // [cap][S]
-  float *cf = cw + kSpreadCap * S;                                  // [cap][3] window offsets delta
-  int *cd = reinterpret_cast<int *>(cf + 3 * kSpreadCap);           // [cap] packed window starts
-  int *ci = cd + kSpreadCap;                                        // [cap] atom index
-  float *wcf = reinterpret_cast<float *>(ci + kSpreadCap);          // window coefficients
-  // (the write-out stage below reuses everything up to wcf)
-  __shared__ int wcount[kSpreadScreen / 64];
+  float *lf = cw + kSpreadCap * S;                                  // [list][3] window offsets delta
+  int *ld = reinterpret_cast<int *>(lf + 3 * kSpreadList);          // [list] packed window starts
+  int *li = ld + kSpreadList;                                       // [list] atom index
+  int *rb = li + kSpreadList;                                       // [cells] first atom of a candidate cell
+  int *rs = rb + kSpreadMaxCells;                                   // [cells + 1] prefix of their sizes
+  float *wcf = reinterpret_cast<float *>(rs + kSpreadMaxCells + 1); // window coefficients
+  // (the write-out stage below reuses the cq and cw area)
+  __shared__ int wcount[kSpreadScreenPer * (kSpreadThreads / 64)];
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps block bookkeeping scalar
@@ -667,71 +685,129 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
     for (int c = 0; c < kSpreadCGM; ++c) acc[j][c] = 0.0f;
 
   // candidate cells: this tile's cell and the ones before it along each
-  // axis that can hold a window start reaching into the tile
-  int clist[3][8], ccount[3];
+  // axis that can hold a window start reaching into the tile.  Their atom
+  // ranges (consecutive in the cell-sorted order) are tabulated with a
+  // prefix of their sizes, so the whole candidate set is screened with
+  // every load of a round in flight at once.
+  int ccount[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int J = min(g.nc[a] - 1, (P - 2) / g.B[a] + 1);
-    ccount[a] = min(J + 1, 8);
-    for (int j = 0; j < ccount[a]; ++j) clist[a][j] = (ctile[a] - j + 8 * g.nc[a]) % g.nc[a];
+  for (int a = 0; a < 3; ++a) ccount[a] = min(min(g.nc[a] - 1, (P - 2) / g.B[a] + 1) + 1, 8);
+  const int ncells = ccount[0] * ccount[1] * ccount[2];  // <= kSpreadMaxCells
+  for (int ic = tid; ic < ncells; ic += kSpreadThreads) {
+    const int iz = ic % ccount[2], iy = (ic / ccount[2]) % ccount[1], ix = ic / (ccount[2] * ccount[1]);
+    const int cc = (((ctile[0] - ix + 8 * g.nc[0]) % g.nc[0]) * g.nc[1] + (ctile[1] - iy + 8 * g.nc[1]) % g.nc[1]) *
+                       g.nc[2] +
+                   (ctile[2] - iz + 8 * g.nc[2]) % g.nc[2];
+    rb[ic] = w.cell_start[cc];
+    rs[ic + 1] = w.cell_start[cc + 1] - w.cell_start[cc];
   }
   __syncthreads();
-
-  // walk the candidate cells chunk by chunk; flush the staged candidates
-  // whenever the next chunk might not fit, and at the end
-  const int ncells = ccount[0] * ccount[1] * ccount[2];
-  int ncand = 0, icell = -1, s = 0, e = 0, base = 0;
-  while (true) {
-    while (base >= e && icell < ncells) {
-      if (++icell >= ncells) break;
-      const int iz = icell % ccount[2], iy = (icell / ccount[2]) % ccount[1], ix = icell / (ccount[2] * ccount[1]);
-      const int cc = (clist[0][ix] * g.nc[1] + clist[1][iy]) * g.nc[2] + clist[2][iz];
-      s = w.cell_start[cc];
-      e = w.cell_start[cc + 1];
-      base = s;
+  if (tid == 0) {
+    int acc_n = 0;
+    rs[0] = 0;
+    for (int ic = 0; ic < ncells; ++ic) {
+      acc_n += rs[ic + 1];
+      rs[ic + 1] = acc_n;
     }
-    const bool done = icell >= ncells;
-    if (!done) {
-      const int i = base + tid;
-      bool ok = false;
-      float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
-      int d[3] = {0, 0, 0};
-      if (tid < kSpreadScreen && i < e) {
-        r = reinterpret_cast<const float4 *>(w.rec_a)[i];
-        const unsigned pk = __float_as_uint(r.w);
-        ok = true;
+  }
+  __syncthreads();
+  const int total = rs[ncells];
+
+  // rounds of up to kSpreadScreenPer atoms per thread: screened candidates
+  // are appended to the list in screening order (deterministic); the list
+  // is flushed kSpreadCap candidates at a time
+  int nlist = 0, c0 = 0;
+  for (int base = 0; base < total || c0 < nlist; base += kSpreadScreenPer * kSpreadThreads) {
+    if (base < total) {
+      float4 rr[kSpreadScreenPer];
+      int ai[kSpreadScreenPer];
+#pragma unroll
+      for (int j = 0; j < kSpreadScreenPer; ++j) {
+        const int e = base + tid + j * kSpreadThreads;
+        int i = -1;
+        if (e < total) {
+          int lo = 0, hi = ncells;  // rs[lo] <= e < rs[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (rs[mid] <= e) lo = mid;
+            else hi = mid;
+          }
+          i = rb[lo] + (e - rs[lo]);
+        }
+        ai[j] = i;
+        rr[j] = i >= 0 ? reinterpret_cast<const float4 *>(w.rec_a)[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      unsigned long long mk[kSpreadScreenPer];
+      int dk[kSpreadScreenPer];
+#pragma unroll
+      for (int j = 0; j < kSpreadScreenPer; ++j) {
+        bool ok = ai[j] >= 0;
+        int pk = 0;
+        const unsigned pn = __float_as_uint(rr[j].w);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          int dd = unpack_n0(pk, a) - t0[a];
+          int dd = unpack_n0(pn, a) - t0[a];
           if (dd < 0) dd += g.M[a];
           const bool in = dd < g.B[a];
           ok = ok && (in || dd > g.M[a] - P);
-          d[a] = in ? dd : dd - g.M[a];
+          pk |= ((in ? dd : dd - g.M[a]) + kSpreadBias) << (10 * a);
         }
+        dk[j] = ok ? pk : -1;
+        mk[j] = __ballot(ok);
+        if (lane == 0) wcount[j * (kSpreadThreads / 64) + wave] = __popcll(mk[j]);
       }
-      const unsigned long long m = __ballot(ok);
-      if (lane == 0 && wave < kSpreadScreen / 64) wcount[wave] = __popcll(m);
       __syncthreads();
-      if (ok) {
-        int off = ncand;
-        for (int k = 0; k < wave; ++k) off += wcount[k];
-        const int slot = off + __popcll(m & ((1ull << lane) - 1ull));
-        cd[slot] = (d[0] + kSpreadBias) | ((d[1] + kSpreadBias) << 10) | ((d[2] + kSpreadBias) << 20);
-        cf[3 * slot] = r.x;
-        cf[3 * slot + 1] = r.y;
-        cf[3 * slot + 2] = r.z;
-        ci[slot] = i;
-      }
+      // slot = list length + candidates of earlier parts j' < j of this
+      // round + those of earlier waves in part j
+      int before = nlist;
 #pragma unroll
-      for (int k = 0; k < kSpreadScreen / 64; ++k) ncand += wcount[k];
+      for (int j = 0; j < kSpreadScreenPer; ++j) {
+        int off = before;
+        for (int wq = 0; wq < wave; ++wq) off += wcount[j * (kSpreadThreads / 64) + wq];
+        if (dk[j] >= 0) {
+          const int slot = off + __popcll(mk[j] & ((1ull << lane) - 1ull));
+          ld[slot] = dk[j];
+          lf[3 * slot] = rr[j].x;
+          lf[3 * slot + 1] = rr[j].y;
+          lf[3 * slot + 2] = rr[j].z;
+          li[slot] = ai[j];
+        }
+        for (int wq = 0; wq < kSpreadThreads / 64; ++wq) before += wcount[j * (kSpreadThreads / 64) + wq];
+      }
+      nlist = before;
       __syncthreads();
-      base += kSpreadScreen;
     }
-    if (ncand > kSpreadCap - kSpreadScreen || (done && ncand > 0)) {
-      spread_flush<P, NBZ>(g, w, cg0, ncg, ncand, sz, cq, cw, cd, cf, ci, wcf, bo, wval, acc);
-      ncand = 0;
+    const bool last = base + kSpreadScreenPer * kSpreadThreads >= total;
+    while (nlist - c0 >= kSpreadCap || (last && c0 < nlist)) {
+      const int n = min(kSpreadCap, nlist - c0);
+      spread_flush<P, NBZ>(g, w, cg0, ncg, n, sz, cq, cw, ld + c0, lf + 3 * c0, li + c0, wcf, bo, wval, acc);
+      c0 += n;
     }
-    if (done) break;
+    // keep the unflushed tail (fewer than kSpreadCap <= threads entries)
+    // at the front of the list
+    if (c0 > 0) {
+      const int rem = nlist - c0;
+      int dv = 0, iv = 0;
+      float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+      if (tid < rem) {
+        dv = ld[c0 + tid];
+        iv = li[c0 + tid];
+        f0 = lf[3 * (c0 + tid)];
+        f1 = lf[3 * (c0 + tid) + 1];
+        f2 = lf[3 * (c0 + tid) + 2];
+      }
+      __syncthreads();
+      if (tid < rem) {
+        ld[tid] = dv;
+        li[tid] = iv;
+        lf[3 * tid] = f0;
+        lf[3 * tid + 1] = f1;
+        lf[3 * tid + 2] = f2;
+      }
+      nlist = rem;
+      c0 = 0;
+      __syncthreads();
+    }
   }
 
   // write the tile through LDS, several channels per pass, as coalesced
@@ -1348,7 +1424,14 @@ static inline unsigned nblocks(int64_t n, int per) { return unsigned((n + per - 
 size_t spread_lds_bytes(const Geo &g, int ncg) {
   (void)ncg;
   const int S = spread_pad4(g.B[0]) + spread_pad4(g.B[1]) + spread_pad4(g.B[2]);
-  return (size_t(spread_stage_floats(S)) + kWinSeg * (kWinDeg + 1)) * 4;
+  return size_t(spread_lds_floats(S)) * 4;
+}
+int spread_max_cells() { return kSpreadMaxCells; }
+// candidate cells a tile of edges b has to screen (see spread_body)
+int spread_candidate_cells(const int *nc, const int *b, int P) {
+  int n = 1;
+  for (int a = 0; a < 3; ++a) n *= std::min(std::min(nc[a] - 1, (P - 2) / b[a] + 1) + 1, 8);
+  return n;
 }
 int spread_max_channels() { return kSpreadCGM; }
 bool spread_tile_ok(int bx, int by, int bz) {

@@ -20,6 +20,8 @@ size_t xpass_lds_bytes(const Geo &g);
 int qsum_blocks(const Geo &g);
 int spread_max_channels();   // channels per spreading launch
 bool spread_tile_ok(int bx, int by, int bz);  // tile fits the spreading kernel's blocks and LDS
+int spread_candidate_cells(const int *nc, const int *b, int P);  // cells a tile screens
+int spread_max_cells();
 
 hipError_t enqueue_sort(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st);
 hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t st);

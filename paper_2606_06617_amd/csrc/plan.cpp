@@ -202,6 +202,10 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
       for (int by : divisors(M[1]))
         for (int bz : divisors(M[2])) {
           if (!spread_tile_ok(bx, by, bz) || !gather_tile_ok(bx, by, bz, P)) continue;
+          {
+            const int b3[3] = {bx, by, bz}, n3[3] = {M[0] / bx, M[1] / by, M[2] / bz};
+            if (spread_candidate_cells(n3, b3, P) > spread_max_cells()) continue;
+          }
           const double eff = double(bx) / (bx + P - 1) * double(by) / (by + P - 1) * double(bz) / (bz + P - 1);
           const long vol = long(bx) * by * bz;
           if (eff > best_eff + 1e-12 || (std::fabs(eff - best_eff) <= 1e-12 && vol > best_vol)) {
@@ -215,6 +219,11 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
         const int b = p.tile[a] > 0 ? p.tile[a] : best[a];
         if (b <= 0 || M[a] % b != 0) return fail(PSWFLR_ERR_INVALID_ARG, "tile edges must divide the grid");
         best[a] = b;
+      }
+      {
+        const int n3[3] = {M[0] / best[0], M[1] / best[1], M[2] / best[2]};
+        if (spread_candidate_cells(n3, best, P) > spread_max_cells())
+          return fail(PSWFLR_ERR_UNSUPPORTED, "tile too small for the support: too many candidate cells");
       }
       if (!spread_tile_ok(best[0], best[1], best[2]))
         return fail(PSWFLR_ERR_UNSUPPORTED, "tile exceeds the spreading kernel's 32 4x4x4 blocks");
