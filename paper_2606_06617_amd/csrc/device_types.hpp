@@ -59,6 +59,7 @@ struct Geo {
   int M[3];               // grid
   int Nz;                 // M_z / 2 (complex length of the z transform)
   int KZ;                 // half-spectrum z columns kept
+  int KZP;                // row stride of the z-column arrays (KZ padded for aligned column blocks)
   int NY, FY;             // y frequencies kept: fy in [-FY, FY], NY = 2 FY + 1
   int P;                  // window support
   int B[3];               // tile edge per axis
@@ -104,8 +105,8 @@ struct Tables {
 // Workspace carve-up (device pointers), produced per call.
 struct Work {
   float *grid;            // [C][Mx][My][Mz]
-  float *s1;              // [C][Mx][My][KZ] complex
-  float *s2;              // [C][Mx][NY][KZ] complex
+  float *s1;              // [C][Mx][My][KZP] complex
+  float *s2;              // [C][Mx][NY][KZP] complex
   float *rec_a, *rec_b;   // [N][4]: delta_x, delta_y, delta_z, packed n0 bits
   float *q_a, *q_b;       // [C][N] in cell order
   int *perm_a, *perm_b;   // cell order -> caller order

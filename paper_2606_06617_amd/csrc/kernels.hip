@@ -894,7 +894,7 @@ __device__ __forceinline__ void zfwd_body(const Geo &g, const Tables &t, const F
   __syncthreads();
   lds_fft<-1, 16>(buf, ax, llog - 2, ld, tw, tid);
   __syncthreads();
-  float2 *dst = reinterpret_cast<float2 *>(w.s1) + line0 * g.KZ;
+  float2 *dst = reinterpret_cast<float2 *>(w.s1) + line0 * g.KZP;
   for (int e = tid; e < nl * g.KZ; e += PSWF_THREADS) {
     const int line = fdiv(e, g.div_kz), k = e - line * g.KZ;
     const float2 zk = buf[(k == Nz ? 0 : k) * ld + line];
@@ -903,7 +903,7 @@ __device__ __forceinline__ void zfwd_body(const Geo &g, const Tables &t, const F
     // E = (Z_k + conj Z_{N-k}) / 2, O = (Z_k - conj Z_{N-k}) / (2i)
     const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
     const float2 O = make_float2(0.5f * (zk.y + zc.y), -0.5f * (zk.x - zc.x));
-    dst[e] = cadd(E, cmul(twr[k], O));
+    dst[line * g.KZP + k] = cadd(E, cmul(twr[k], O));
   }
 }
 
@@ -923,23 +923,23 @@ __device__ __forceinline__ void yfwd_body(const Geo &g, const Tables &t, const F
   const int64_t plane = by;  // c * Mx + x
   const int ncol = min(kb, g.KZ - kz0);
   for (int e = tid; e < My; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_y)[e];
-  const float2 *src = reinterpret_cast<const float2 *>(w.s1) + plane * My * g.KZ;
+  const float2 *src = reinterpret_cast<const float2 *>(w.s1) + plane * My * g.KZP;
   staged16(
       My * kb,
       [&](int e) {
         const int y = e >> g.kb_log2, col = e & (kb - 1);
-        return col < ncol ? src[int64_t(y) * g.KZ + kz0 + col] : make_float2(0.f, 0.f);
+        return col < ncol ? src[int64_t(y) * g.KZP + kz0 + col] : make_float2(0.f, 0.f);
       },
       [&](int e, float2 v) { buf[(e >> g.kb_log2) * ld + (e & (kb - 1))] = v; });
   __syncthreads();
   lds_fft<-1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
   __syncthreads();
-  float2 *dst = reinterpret_cast<float2 *>(w.s2) + plane * g.NY * g.KZ;
+  float2 *dst = reinterpret_cast<float2 *>(w.s2) + plane * g.NY * g.KZP;
   for (int e = tid; e < g.NY * kb; e += PSWF_THREADS) {
     const int iy = e >> g.kb_log2, col = e & (kb - 1);
     if (col >= ncol) continue;
     const int my = iy <= g.FY ? iy : My - g.NY + iy;
-    dst[int64_t(iy) * g.KZ + kz0 + col] = buf[my * ld + col];
+    dst[int64_t(iy) * g.KZP + kz0 + col] = buf[my * ld + col];
   }
 }
 
@@ -1002,8 +1002,8 @@ __device__ __forceinline__ void xmul_body(const Geo &g, const Tables &t, const F
     fc[e] = t.kf[c * kKerCoef + e];
     gc[e] = t.kg[c * kKerCoef + e];
   }
-  const int64_t xstride = int64_t(g.NY) * g.KZ;
-  float2 *col0 = reinterpret_cast<float2 *>(w.s2) + int64_t(c) * Mx * xstride + int64_t(iy) * g.KZ + kz0;
+  const int64_t xstride = int64_t(g.NY) * g.KZP;
+  float2 *col0 = reinterpret_cast<float2 *>(w.s2) + int64_t(c) * Mx * xstride + int64_t(iy) * g.KZP + kz0;
   staged16(
       Mx * kb,
       [&](int e) {
@@ -1087,13 +1087,13 @@ __device__ __forceinline__ void yinv_body(const Geo &g, const Tables &t, const F
   for (int e = tid; e < My; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_y)[e];
   for (int e = tid; e < My * ld; e += PSWF_THREADS) buf[e] = make_float2(0.f, 0.f);
   __syncthreads();
-  const float2 *src = reinterpret_cast<const float2 *>(w.s2) + plane * g.NY * g.KZ;
+  const float2 *src = reinterpret_cast<const float2 *>(w.s2) + plane * g.NY * g.KZP;
   staged16(
       g.NY * kb,
       [&](int e) {
         const int iy = e >> g.kb_log2, col = e & (kb - 1);
         const int kz = kz0 + col;
-        return (col < ncol && kz < t.blim[iy]) ? src[int64_t(iy) * g.KZ + kz] : make_float2(0.f, 0.f);
+        return (col < ncol && kz < t.blim[iy]) ? src[int64_t(iy) * g.KZP + kz] : make_float2(0.f, 0.f);
       },
       [&](int e, float2 v) {
         const int iy = e >> g.kb_log2, col = e & (kb - 1);
@@ -1103,10 +1103,10 @@ __device__ __forceinline__ void yinv_body(const Geo &g, const Tables &t, const F
   __syncthreads();
   lds_fft<1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
   __syncthreads();
-  float2 *dst = reinterpret_cast<float2 *>(w.s1) + plane * My * g.KZ;
+  float2 *dst = reinterpret_cast<float2 *>(w.s1) + plane * My * g.KZP;
   for (int e = tid; e < My * kb; e += PSWF_THREADS) {
     const int y = e >> g.kb_log2, col = e & (kb - 1);
-    if (col < ncol) dst[int64_t(y) * g.KZ + kz0 + col] = buf[y * ld + col];
+    if (col < ncol) dst[int64_t(y) * g.KZP + kz0 + col] = buf[y * ld + col];
   }
 }
 
@@ -1132,10 +1132,13 @@ __device__ __forceinline__ void zinv_body(const Geo &g, const Tables &t, const F
   __syncthreads();
   // stage the KZ stored modes of each line (coalesced rows), then form the
   // packed half-length spectrum in place, one (k, N - k) pair per thread
-  const float2 *src = reinterpret_cast<const float2 *>(w.s1) + line0 * g.KZ;
+  const float2 *src = reinterpret_cast<const float2 *>(w.s1) + line0 * g.KZP;
   staged16(
       L * g.KZ,
-      [&](int e) { return fdiv(e, g.div_kz) < nl ? src[e] : make_float2(0.f, 0.f); },
+      [&](int e) {
+        const int line = fdiv(e, g.div_kz);
+        return line < nl ? src[line * g.KZP + (e - line * g.KZ)] : make_float2(0.f, 0.f);
+      },
       [&](int e, float2 v) {
         const int line = fdiv(e, g.div_kz), k = e - line * g.KZ;
         buf[k * ld + line] = v;
@@ -1361,11 +1364,19 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
   }
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin by index; give each XCD a
+// contiguous range of tiles so that neighbouring tiles, whose halos overlap,
+// run at the same time behind the same L2.
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+  const int q = n >> 3, r = n & 7, xcd = b & 7, j = b >> 3;
+  return xcd * q + min(xcd, r) + j;
+}
+
 template <int P>
 __global__ __launch_bounds__(kGatherThreads, 4) void k_gather(Geo g, Tables t, Work w, float *__restrict__ fout,
                                                             float *__restrict__ pout, int mode,
                                                             const double *__restrict__ grad) {
-  gather_body<P>(g, t, w, fout, pout, mode, grad, blockIdx.x);
+  gather_body<P>(g, t, w, fout, pout, mode, grad, xcd_contiguous(blockIdx.x, gridDim.x));
 }
 
 // Final FP64 reduction: energy [3C] (E_k, E_0, E_self) and virial [6].

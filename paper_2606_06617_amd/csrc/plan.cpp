@@ -253,6 +253,12 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   g.kb = std::max(1, std::min(16, floor_pow2(4096 / std::max(M[0], M[1]))));
   g.kb_log2 = 0;
   while ((1 << g.kb_log2) < g.kb) ++g.kb_log2;
+  // z-column arrays: rows padded so that each block of kb columns starts on
+  // a kb * 8-byte (at least 64-byte) boundary
+  {
+    const int al = std::max(g.kb, 8);
+    g.KZP = (g.KZ + al - 1) / al * al;
+  }
   g.zlines = std::max(1, floor_pow2(4096 / g.Nz));
   g.div_nz = make_fastdiv(g.Nz);
   g.div_kz = make_fastdiv(g.KZ);
@@ -368,8 +374,8 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   // ---- workspace layout for max_atoms ----
   const int64_t Nm = std::max<int64_t>(max_atoms, 1);
   const size_t grid_b = size_t(C) * M[0] * M[1] * M[2] * 4;
-  const size_t s1_b = size_t(C) * M[0] * M[1] * g.KZ * 8;
-  const size_t s2_b = size_t(C) * M[0] * g.NY * g.KZ * 8;
+  const size_t s1_b = size_t(C) * M[0] * M[1] * g.KZP * 8;
+  const size_t s2_b = size_t(C) * M[0] * g.NY * g.KZP * 8;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t off = o;
