@@ -15,7 +15,7 @@ import os
 import threading
 import time
 
-KERNEL_VERSION = 7
+KERNEL_VERSION = 8
 _LOCK = threading.Lock()
 
 
@@ -62,9 +62,10 @@ def _tile_fits(bx, by, bz, P, lds=160 * 1024):
     if nby % cpw or (pad(bx) // 4) * nby > 8 * cpw or S > 64 or bx * by * bz > 256 * (12 + S):
         return False
     ex, ey, ez = bx + P - 1, by + P - 1, bz + P - 1
-    if ex * ey * (ez | 1) > 512 * 16:
+    if ex * ey * ez > 512 * 16:
         return False
-    return (ex * ey * (ez | 1) + 96) * 4 <= lds
+    sz = 8 if ez <= 8 else 8 + (ez - 8 + 31) // 32 * 32   # row stride = 8 (mod 32)
+    return (ex * ey * sz + 96) * 4 <= lds
 
 
 def candidate_tiles(grid, P, limit=6):

@@ -81,6 +81,8 @@ struct Geo {
   int kb_log2;
   FastDiv div_nz;         // by Nz
   FastDiv div_kz;         // by KZ
+  FastDiv div_gez;        // by the gather halo's z extent B_z + P - 1
+  FastDiv div_geyz;       // by its y-z plane (B_y + P - 1)(B_z + P - 1)
 };
 
 // Device pointers into a plan's table allocation.

@@ -1199,7 +1199,12 @@ constexpr unsigned kGatherOOB = 0xfffffff0u;                    // byte offset p
 // gfx9 raw buffer descriptor word 3 (32-bit dwords, range-checked offsets)
 constexpr int kBufferWord3 = 0x00020000;
 
-__host__ __device__ __forceinline__ int gather_sz(int ez) { return ez | 1; }  // odd row stride
+// Row stride of the halo tile: the smallest s >= ez with s = 8 (mod 32).
+// LDS has 32 banks; the four lanes of an atom read rows y, y+1, y+2, y+3
+// (or y+4..y+7), which then fall on banks b, b+8, b+16, b+24: an atom
+// occupies the residue class of its base address mod 8, and atoms of
+// distinct classes never share a bank.
+__host__ __device__ __forceinline__ int gather_sz(int ez) { return ez <= 8 ? 8 : 8 + (ez - 8 + 31) / 32 * 32; }
 
 // one channel's halo elements at byte offsets goff (range-checked buffer
 // loads: offsets past the channel read as 0)
@@ -1230,21 +1235,24 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
   const int t0[3] = {cx * Bx, cy * By, cz * Bz};
   for (int k = tid; k < kWinSeg * (kWinDeg + 1); k += kGatherThreads) wcf[k] = t.win[k];
 
-  // halo elements this thread stages: linear LDS positions tid + 512 r of
-  // the [EX][EY][SZ] tile, the same for every channel.  Byte offsets within
-  // a channel of the grid; pad slots and unused positions get an offset
-  // past the buffer range, which a buffer load returns as 0.
-  const int ntile = EX * plane;
+  // halo elements this thread stages: elements tid + 512 r of the
+  // [EX][EY][EZ] region (LDS offsets with row stride SZ), the same for every
+  // channel.  Byte offsets within a channel of the grid; unused slots get an
+  // offset past the buffer range, which a buffer load returns as 0.
+  const int nhalo = EX * EY * EZ;
   unsigned goff[kGatherStage];
+  int loff[kGatherStage];
 #pragma unroll
   for (int r = 0; r < kGatherStage; ++r) {
     const int el = tid + kGatherThreads * r;
-    const int x = el / plane, rem = el - x * plane, y = rem / SZ, z = rem - y * SZ;
+    const int x = fdiv(el, g.div_geyz), rem = el - x * (EY * EZ), y = fdiv(rem, g.div_gez), z = rem - y * EZ;
     int gx = t0[0] + x, gy = t0[1] + y, gz = t0[2] + z;
     if (gx >= g.M[0]) gx -= g.M[0];
     if (gy >= g.M[1]) gy -= g.M[1];
     if (gz >= g.M[2]) gz -= g.M[2];
-    goff[r] = (el < ntile && z < EZ) ? unsigned((gx * g.M[1] + gy) * g.M[2] + gz) * 4u : kGatherOOB;
+    const bool ok = el < nhalo;
+    goff[r] = ok ? unsigned((gx * g.M[1] + gy) * g.M[2] + gz) * 4u : kGatherOOB;
+    loff[r] = ok ? x * plane + y * SZ + z : -1;
   }
   const int64_t chan = int64_t(g.M[0]) * g.M[1] * g.M[2];
   // the next channel's halo is loaded into registers while the current one
@@ -1254,12 +1262,45 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
   const float sg = mode == 2 ? -1.0f : 1.0f;
   __syncthreads();  // window coefficients
 
+  __shared__ int rhist[8], order[kGatherAtoms];
+  __shared__ float4 rbuf[kGatherAtoms];
   for (int p0 = s; p0 < e; p0 += kGatherAtoms) {
     const int na = min(kGatherAtoms, e - p0);
-    const int k = tid / kGatherLanes;
-    const bool act = k < na;
-    const int a = p0 + min(k, na - 1);
-    const float4 rr = reinterpret_cast<const float4 *>(w.rec_a)[a];
+    // place atoms so that the 16 atoms of a wave spread over the 8 bank
+    // residue classes (z offset mod 8): sort by class, wave w takes sorted
+    // positions w, w + 8, w + 16, ...  (only lane placement changes: each
+    // atom's arithmetic is the same wherever it runs)
+    float4 rmine = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (tid < na) rmine = reinterpret_cast<const float4 *>(w.rec_a)[p0 + tid];
+    gather_load_halo(w.grid, chan, 0, goff, stage);  // in flight during the set-up
+    if (tid < 8) rhist[tid] = 0;
+    __syncthreads();
+    int rcls = 0;
+    if (tid < na) {
+      int oz = unpack_n0(__float_as_uint(rmine.w), 2) - t0[2];
+      if (oz < 0) oz += g.M[2];
+      rcls = oz & 7;
+      rbuf[tid] = rmine;
+      atomicAdd(&rhist[rcls], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int run = 0;
+      for (int c = 0; c < 8; ++c) {
+        const int h = rhist[c];
+        rhist[c] = run;
+        run += h;
+      }
+    }
+    __syncthreads();
+    if (tid < na) order[atomicAdd(&rhist[rcls], 1)] = tid;
+    __syncthreads();
+    const int slot = tid / kGatherLanes;                                  // 16 per wave
+    const int pos = (slot % (64 / kGatherLanes)) * 8 + slot / (64 / kGatherLanes);
+    const bool act = pos < na;
+    const int kloc = order[min(pos, na - 1)];
+    const int a = p0 + kloc;
+    const float4 rr = rbuf[kloc];
     const unsigned pk = __float_as_uint(rr.w);
     int o[3];
 #pragma unroll
@@ -1296,15 +1337,12 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
     const int base = o[0] * plane + o[1] * SZ + o[2];
     float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 
-    gather_load_halo(w.grid, chan, 0, goff, stage);
     for (int c = 0; c < g.C; ++c) {
       const float qv = w.q_a[int64_t(c) * g.N + a];
       __syncthreads();  // the tile buffer is free
 #pragma unroll
-      for (int r = 0; r < kGatherStage; ++r) {
-        const int el = tid + kGatherThreads * r;
-        if (el < ntile) tile[el] = stage[r];
-      }
+      for (int r = 0; r < kGatherStage; ++r)
+        if (loff[r] >= 0) tile[loff[r]] = stage[r];
       __syncthreads();
       if (c + 1 < g.C) gather_load_halo(w.grid, chan, c + 1, goff, stage);
       float vphi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
@@ -1465,7 +1503,7 @@ bool gather_tile_ok(int bx, int by, int bz, int P) {
   g.B[2] = bz;
   g.P = P;
   const int ex = bx + P - 1, ey = by + P - 1, ez = bz + P - 1;
-  return ex * ey * gather_sz(ez) <= kGatherThreads * kGatherStage && gather_lds_bytes(g, 1) <= 160 * 1024;
+  return ex * ey * ez <= kGatherThreads * kGatherStage && gather_lds_bytes(g, 1) <= 160 * 1024;
 }
 size_t zpass_lds_bytes(const Geo &g) { return (size_t(g.Nz) * (g.zlines + 1) + 2 * g.Nz + 1) * 8; }
 size_t ypass_lds_bytes(const Geo &g) { return (size_t(g.M[1]) * (g.kb + 1) + g.M[1]) * 8; }

@@ -262,6 +262,8 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   g.zlines = std::max(1, floor_pow2(4096 / g.Nz));
   g.div_nz = make_fastdiv(g.Nz);
   g.div_kz = make_fastdiv(g.KZ);
+  g.div_gez = make_fastdiv(g.B[2] + P - 1);
+  g.div_geyz = make_fastdiv((g.B[1] + P - 1) * (g.B[2] + P - 1));
   bool ok1, ok2, ok3;
   pl.az = factorise(g.Nz, &ok1);
   pl.ay = factorise(M[1], &ok2);
