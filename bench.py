@@ -67,9 +67,12 @@ def algorithmic_flops(info, N, C):
     return {"spread": 2 * P ** 3 * N * C, "gather": 8 * P ** 3 * N * C}
 
 
-def stage_kernel(stage, P):
-    """Name (as in rocprofv3 summaries) of the kernel a timed stage launches."""
-    return {"spread": "k_spread<%d>" % P, "fft_z": "k_zfwd", "fft_y": "k_yfwd", "fft_x_scale": "k_xmul",
+def stage_kernel(stage, info):
+    """Name (as in rocprofv3 summaries) of the kernel a timed stage launches;
+    the spread is instantiated per support and z blocks per tile edge."""
+    P = info["support"]
+    nbz = (info["tile"][2] + 3) // 4
+    return {"spread": "k_spread<%d,%d>" % (P, nbz), "fft_z": "k_zfwd", "fft_y": "k_yfwd", "fft_x_scale": "k_xmul",
             "ifft_y": "k_yinv", "ifft_z": "k_zinv", "gather": "k_gather<%d>" % P}.get(stage)
 
 
@@ -272,7 +275,7 @@ def main():
     flops = algorithmic_flops(info, N, C)
     dom = max(algo.keys(), key=lambda k: stage_ms[k])
     t_dom = avg_launch_ms[dom] * 1e-3
-    traffic = measured_traffic(args.workload, stage_kernel(dom, info["support"]))
+    traffic = measured_traffic(args.workload, stage_kernel(dom, info))
     if flops.get(dom, 0) / (FP32_PEAK_TFLOPS * 1e12) > algo[dom] / (HBM_PEAK_GBS * 1e9):
         achieved = flops[dom] / t_dom / 1e12
         roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,

@@ -259,8 +259,18 @@ __device__ __forceinline__ void zero_int_body(int *p, int n, int bx) {
 
 __global__ __launch_bounds__(PSWF_THREADS) void k_zero_int(int *p, int n) { zero_int_body(p, n, blockIdx.x); }
 
-__device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const float *__restrict__ pos, int bx) {
-  const int64_t i = int64_t(bx) * PSWF_THREADS + threadIdx.x;
+__device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const float *__restrict__ pos,
+                                         const float *__restrict__ q, int bx) {
+  // charges staged atom-major, [N][C], so that the reorder reads one
+  // contiguous row per atom instead of C scattered words; consecutive
+  // threads write consecutive words of the block's rows
+  const int64_t b0 = int64_t(bx) * PSWF_THREADS;
+  const int nrow = g.N - b0 < PSWF_THREADS ? int(g.N - b0) : PSWF_THREADS;
+  for (int f = threadIdx.x; f < nrow * g.C; f += PSWF_THREADS) {
+    const int a = f / g.C, ch = f - a * g.C;
+    w.q_b[b0 * g.C + f] = q[int64_t(ch) * g.N + b0 + a];
+  }
+  const int64_t i = b0 + threadIdx.x;
   if (i >= g.N) return;
   unsigned packed = 0;
   float dl[3];
@@ -286,11 +296,12 @@ __device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const floa
   w.cell_of[i] = c;
   w.slot[i] = atomicAdd(&w.cell_count[c], 1);
   float4 r = make_float4(dl[0], dl[1], dl[2], __uint_as_float(packed));
-  reinterpret_cast<float4 *>(w.rec_a)[i] = r;  // staged in caller order
+  reinterpret_cast<float4 *>(w.rec_b)[i] = r;  // staged in caller order
 }
 
-__global__ __launch_bounds__(PSWF_THREADS) void k_bin(Geo g, Work w, const float *__restrict__ pos) {
-  bin_body(g, w, pos, blockIdx.x);
+__global__ __launch_bounds__(PSWF_THREADS) void k_bin(Geo g, Work w, const float *__restrict__ pos,
+                                                      const float *__restrict__ q) {
+  bin_body(g, w, pos, q, blockIdx.x);
 }
 
 // exclusive scan of cell counts (single block)
@@ -320,19 +331,16 @@ __device__ __forceinline__ void scan_body(const Work &w, int ncell, int64_t N) {
 
 __global__ __launch_bounds__(1024) void k_scan(Work w, int ncell, int64_t N) { scan_body(w, ncell, N); }
 
-// scatter into cell order (arbitrary order inside a cell)
-__device__ __forceinline__ void scatter_body(const Geo &g, const Work &w, const float *__restrict__ q, int bx) {
+// scatter the caller index into cell order (arbitrary order inside a cell);
+// records and charges follow in the per-cell ordering pass
+__device__ __forceinline__ void scatter_body(const Geo &g, const Work &w, int bx) {
   const int64_t i = int64_t(bx) * PSWF_THREADS + threadIdx.x;
   if (i >= g.N) return;
   const int dst = w.cell_start[w.cell_of[i]] + w.slot[i];
-  reinterpret_cast<float4 *>(w.rec_b)[dst] = reinterpret_cast<const float4 *>(w.rec_a)[i];
   w.perm_b[dst] = int(i);
-  for (int c = 0; c < g.C; ++c) w.q_b[int64_t(c) * g.N + dst] = q[int64_t(c) * g.N + i];
 }
 
-__global__ __launch_bounds__(PSWF_THREADS) void k_scatter(Geo g, Work w, const float *__restrict__ q) {
-  scatter_body(g, w, q, blockIdx.x);
-}
+__global__ __launch_bounds__(PSWF_THREADS) void k_scatter(Geo g, Work w) { scatter_body(g, w, blockIdx.x); }
 
 // deterministic order inside each cell: ascending caller index
 __device__ __forceinline__ void order_body(const Geo &g, const Work &w, int bx) {
@@ -351,9 +359,10 @@ __device__ __forceinline__ void order_body(const Geo &g, const Work &w, int bx) 
     int rank = 0;
     for (int m = 0; m < n; ++m) rank += (in_lds ? keys[m] : w.perm_b[s + m]) < key;
     const int dst = s + rank;
-    reinterpret_cast<float4 *>(w.rec_a)[dst] = reinterpret_cast<const float4 *>(w.rec_b)[s + k];
+    reinterpret_cast<float4 *>(w.rec_a)[dst] = reinterpret_cast<const float4 *>(w.rec_b)[key];
     w.perm_a[dst] = key;
-    for (int c = 0; c < g.C; ++c) w.q_a[int64_t(c) * g.N + dst] = w.q_b[int64_t(c) * g.N + s + k];
+    const float *qr = w.q_b + int64_t(key) * g.C;
+    for (int c = 0; c < g.C; ++c) w.q_a[int64_t(c) * g.N + dst] = qr[c];
   }
 }
 
@@ -1085,20 +1094,23 @@ __device__ __forceinline__ void yinv_body(const Geo &g, const Tables &t, const F
   const int64_t plane = by;
   const int ncol = min(kb, g.KZ - kz0);
   for (int e = tid; e < My; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_y)[e];
-  for (int e = tid; e < My * ld; e += PSWF_THREADS) buf[e] = make_float2(0.f, 0.f);
-  __syncthreads();
+  // rows |f_y| > FY are zero; the kept rows are all loaded below
+  const int ngap = My - g.NY;
+  for (int e = tid; e < ngap * kb; e += PSWF_THREADS)
+    buf[(g.FY + 1 + (e >> g.kb_log2)) * ld + (e & (kb - 1))] = make_float2(0.f, 0.f);
   const float2 *src = reinterpret_cast<const float2 *>(w.s2) + plane * g.NY * g.KZP;
+  // the loads do not wait for the column limits: columns the x pass skipped
+  // (k_z >= blim) still hold forward data and are masked after the load
   staged16(
       g.NY * kb,
       [&](int e) {
         const int iy = e >> g.kb_log2, col = e & (kb - 1);
-        const int kz = kz0 + col;
-        return (col < ncol && kz < t.blim[iy]) ? src[int64_t(iy) * g.KZP + kz] : make_float2(0.f, 0.f);
+        return col < ncol ? src[int64_t(iy) * g.KZP + kz0 + col] : make_float2(0.f, 0.f);
       },
       [&](int e, float2 v) {
         const int iy = e >> g.kb_log2, col = e & (kb - 1);
         const int my = iy <= g.FY ? iy : My - g.NY + iy;
-        buf[my * ld + col] = v;
+        buf[my * ld + col] = kz0 + col < t.blim[iy] ? v : make_float2(0.f, 0.f);
       });
   __syncthreads();
   lds_fft<1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
@@ -1541,13 +1553,13 @@ hipError_t enqueue_sort(const Geo &g, const Work &w, const float *pos, const flo
                      w.cell_count, g.ncell);
   LAUNCH_CHECK();
   if (g.N > 0) {
-    hipLaunchKernelGGL(k_bin, dim3(nblocks(g.N, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, w, pos);
+    hipLaunchKernelGGL(k_bin, dim3(nblocks(g.N, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, w, pos, q);
     LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, w, g.ncell, g.N);
   LAUNCH_CHECK();
   if (g.N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter, dim3(nblocks(g.N, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, w, q);
+  hipLaunchKernelGGL(k_scatter, dim3(nblocks(g.N, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, w);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_order, dim3(g.ncell), dim3(PSWF_THREADS), 0, st, g, w);
   LAUNCH_CHECK();
@@ -1694,9 +1706,9 @@ __global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather
   const Geo &g = it.g;
   switch (STAGE) {
     case kBsZero: zero_int_body(it.w.cell_count, g.ncell, vb); break;
-    case kBsBin: bin_body(g, it.w, it.pos, vb); break;
+    case kBsBin: bin_body(g, it.w, it.pos, it.q, vb); break;
     case kBsScan: scan_body(it.w, g.ncell, g.N); break;
-    case kBsScatter: scatter_body(g, it.w, it.q, vb); break;
+    case kBsScatter: scatter_body(g, it.w, vb); break;
     case kBsOrder: order_body(g, it.w, vb); break;
     case kBsQsum: qsum_body(g, it.w, it.q, kQChunk, vb % it.qblocks, vb / it.qblocks); break;
     case kBsQreduce: qreduce_body(g, it.w, it.qblocks); break;

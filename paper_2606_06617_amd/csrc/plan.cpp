@@ -484,12 +484,12 @@ pswflr_status pswflr_plan_create(const pswflr_params *params, int64_t max_atoms,
     pl = new pswflr_plan_s();
     pswflr_status s = build_plan(*params, max_atoms, *pl);
     if (s != PSWFLR_OK) {
-      if (pl->dtab) hipFree(pl->dtab);
+      if (pl->dtab) (void)hipFree(pl->dtab);
       delete pl;
       return s;
     }
   } catch (const std::exception &e) {
-    if (pl && pl->dtab) hipFree(pl->dtab);
+    if (pl && pl->dtab) (void)hipFree(pl->dtab);
     delete pl;
     return fail(PSWFLR_ERR_INTERNAL, e.what());
   }
@@ -505,7 +505,7 @@ pswflr_status pswflr_plan_info(pswflr_plan plan, pswflr_info *out) {
 
 pswflr_status pswflr_plan_destroy(pswflr_plan plan) {
   if (!plan) return PSWFLR_OK;
-  if (plan->dtab) hipFree(plan->dtab);
+  if (plan->dtab) (void)hipFree(plan->dtab);
   delete plan;
   return PSWFLR_OK;
 }

@@ -35,11 +35,11 @@ def source_hash(path=KERNEL_SOURCE):
 
 
 def short_name(name):
-    """pswf::k_spread<8>(pswf::Geo, ...) -> k_spread<8>"""
+    """void pswf::k_spread<8, 4>(pswf::Geo, ...) -> k_spread<8,4>"""
     n = name.split("(")[0]
     if n.startswith("void "):
         n = n[5:]
-    return n.replace("pswf::", "")
+    return n.replace("pswf::", "").replace(" ", "")
 
 
 def kernel_stats(path):
