@@ -118,6 +118,44 @@ struct Dft<8, S> {
   }
 };
 
+template <int S>
+struct Dft<16, S> {
+  // 16 = 4 x 4: DFT-4 over the stride-4 subsequences, twiddles w16^(n2 k1),
+  // DFT-4 across them; output in natural order
+  __device__ __forceinline__ static void run(float2 *x) {
+    const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;  // cos, sin (pi/8)
+    const float r = 0.70710678118654752440f;
+    float2 a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      a[n2][0] = x[n2];
+      a[n2][1] = x[4 + n2];
+      a[n2][2] = x[8 + n2];
+      a[n2][3] = x[12 + n2];
+      Dft<4, S>::run(a[n2]);
+    }
+    // w16^e = (cos(2 pi e / 16), S sin(2 pi e / 16))
+    a[1][1] = cmul(a[1][1], make_float2(c1, S * s1));
+    a[1][2] = cmul(a[1][2], make_float2(r, S * r));
+    a[1][3] = cmul(a[1][3], make_float2(s1, S * c1));
+    a[2][1] = cmul(a[2][1], make_float2(r, S * r));
+    a[2][2] = mul_isig<S>(a[2][2]);
+    a[2][3] = cmul(a[2][3], make_float2(-r, S * r));
+    a[3][1] = cmul(a[3][1], make_float2(s1, S * c1));
+    a[3][2] = cmul(a[3][2], make_float2(-r, S * r));
+    a[3][3] = cmul(a[3][3], make_float2(-c1, -S * s1));
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      float2 b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Dft<4, S>::run(b);
+      x[k1] = b[0];
+      x[k1 + 4] = b[1];
+      x[k1 + 8] = b[2];
+      x[k1 + 12] = b[3];
+    }
+  }
+};
+
 // One Stockham stage over the lines owned by one wave (LW = 2^lw_log2
 // lines, wave w owns lines [w LW, (w + 1) LW)), each of length n stored in
 // LDS as buf[idx * ld + line].  Butterfly j of a line reads x[j + r n/R],
@@ -216,6 +254,39 @@ __device__ void lds_fft(float2 *buf, const FftAxis &ax, int lw_log2, int ld, con
     ns *= R;
   }
 }
+
+// Register FFTs of lines of N = N1 N2 points (N1 a multiple of N2) by the
+// four-step split n = N2 n1 + n2, k = k1 + N1 k2:
+//   X[k1 + N1 k2] = sum_n2 w_N2^(n2 k2) w_N^(n2 k1) sum_n1 w_N1^(n1 k1) x[N2 n1 + n2].
+// A line is served by N2 threads.  Thread j enters with v[n1] = x[N2 n1 + j],
+// does the inner DFT and the twiddles in registers (rfft_inner), passes
+// v[k1] through LDS to the thread that owns column k1 = j + N2 q (q < N1/N2)
+// and does the outer DFTs there (rfft_outer), leaving
+// v[q N2 + k2] = X[j + N2 q + N1 k2].  With N1 = N2 the output layout is the
+// input layout of the next transform.  tw[m] = exp(-2 pi i m / N).
+template <int N1, int S>
+__device__ __forceinline__ void rfft_inner(float2 *v, int j, const float2 *tw) {
+  Dft<N1, S>::run(v);
+#pragma unroll
+  for (int k1 = 1; k1 < N1; ++k1) {
+    float2 w = tw[j * k1];
+    if (S > 0) w.y = -w.y;
+    v[k1] = cmul(v[k1], w);
+  }
+}
+
+template <int N1, int N2, int S>
+__device__ __forceinline__ void rfft_outer(float2 *v) {
+#pragma unroll
+  for (int q = 0; q < N1 / N2; ++q) Dft<N2, S>::run(v + q * N2);
+}
+
+// geometry served by the register FFTs: 256-point x / y lines in blocks of
+// 16 columns, 128-point (packed 256-real) z lines in blocks of 32
+__host__ __device__ __forceinline__ bool zreg_ok(const Geo &g) { return g.Nz == 128 && g.zlines == 32; }
+__host__ __device__ __forceinline__ bool yreg_ok(const Geo &g) { return g.M[1] == 256 && g.kb == 16; }
+__host__ __device__ __forceinline__ bool xreg_ok(const Geo &g) { return g.M[0] == 256 && g.kb == 16; }
+constexpr int kZregLine = 152;  // LDS float2 per z line: 16 x 9 exchange slots, padded to 8 (mod 16)
 
 // ---------------------------------------------------------------------------
 // Window psi_s(t), t in [-1, 1): piecewise polynomial in |t| (even function).
@@ -876,10 +947,61 @@ __global__ __launch_bounds__(kSpreadThreads, 4) void k_spread(Geo g, Tables t, W
 }
 
 // ---------------------------------------------------------------------------
+// z R2C on the register FFT: 32 lines of Nz = 128 per workgroup, 8 threads
+// per line (one wave holds 8 whole lines, so the exchanges are wave-local).
+__device__ __forceinline__ void zfwd_reg(const Geo &g, const Tables &t, const Work &w, int64_t nlines_total, int bx) {
+  extern __shared__ float smem[];
+  constexpr int Nz = 128;
+  float2 *ex = reinterpret_cast<float2 *>(smem);
+  float2 *tw = ex + 32 * kZregLine;
+  float2 *twr = tw + Nz;
+  const int tid = threadIdx.x, j = tid & 7, l = tid >> 3;
+  const int64_t line0 = int64_t(bx) * 32;
+  const bool on = line0 + l < nlines_total;
+  const float2 *src = reinterpret_cast<const float2 *>(w.grid) + (line0 + l) * Nz + j;
+  float2 v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) v[n1] = on ? src[8 * n1] : make_float2(0.f, 0.f);
+  for (int e = tid; e < Nz; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_z)[e];
+  for (int e = tid; e <= Nz; e += PSWF_THREADS) twr[e] = reinterpret_cast<const float2 *>(t.tw_zr)[e];
+  __syncthreads();
+  float2 *xl = ex + l * kZregLine;
+  rfft_inner<16, -1>(v, j, tw);
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) xl[k1 * 9 + j] = v[k1];
+  wave_sync();
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) v[q * 8 + n2] = xl[(j + 8 * q) * 9 + n2];
+  rfft_outer<16, 8, -1>(v);
+  wave_sync();
+  // natural order for the real-to-complex split
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) xl[j + 8 * q + 16 * k2] = v[q * 8 + k2];
+  wave_sync();
+  if (!on) return;
+  float2 *dst = reinterpret_cast<float2 *>(w.s1) + (line0 + l) * g.KZP;
+  for (int k = j; k < g.KZ; k += 8) {
+    const float2 zk = xl[k == Nz ? 0 : k];
+    const float2 zc = xl[(Nz - k) & (Nz - 1)];
+    // E = (Z_k + conj Z_{N-k}) / 2, O = (Z_k - conj Z_{N-k}) / (2i)
+    const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
+    const float2 O = make_float2(0.5f * (zk.y + zc.y), -0.5f * (zk.x - zc.x));
+    dst[k] = cadd(E, cmul(twr[k], O));
+  }
+}
+
 // z R2C (step ii, first axis): lines of M_z reals -> KZ complex columns.
 // The real line is packed as z_n = x_2n + i x_2n+1, transformed with length
 // Nz = M_z / 2 and split: X_k = E_k + exp(-2 pi i k / M_z) O_k.
 __device__ __forceinline__ void zfwd_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int64_t nlines_total, int bx) {
+  if (zreg_ok(g)) {
+    zfwd_reg(g, t, w, nlines_total, bx);
+    return;
+  }
   extern __shared__ float smem[];
   const int L = g.zlines, ld = L + 1, Nz = g.Nz;
   int llog = 0;
@@ -920,9 +1042,48 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zfwd(Geo g, Tables t, FftAxis 
   zfwd_body(g, t, ax, w, nlines_total, blockIdx.x);
 }
 
+// y forward on the register FFT (M_y = 256, 16 columns per workgroup):
+// thread (col, j) loads rows 16 n1 + j of its column; the exchange crosses
+// waves, so it is a workgroup barrier.
+__device__ __forceinline__ void yfwd_reg(const Geo &g, const Tables &t, const Work &w, int bx, int by) {
+  extern __shared__ float smem[];
+  float2 *ex = reinterpret_cast<float2 *>(smem);  // [k1][n2][col]
+  float2 *tw = ex + 256 * 16;
+  const int tid = threadIdx.x, col = tid & 15, j = tid >> 4;
+  const int kz0 = bx * 16;
+  const int64_t plane = by;
+  const bool on = kz0 + col < g.KZ;
+  const float2 *src = reinterpret_cast<const float2 *>(w.s1) + plane * 256 * g.KZP + kz0 + col;
+  float2 v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) v[n1] = on ? src[int64_t(16 * n1 + j) * g.KZP] : make_float2(0.f, 0.f);
+  tw[tid] = reinterpret_cast<const float2 *>(t.tw_y)[tid];
+  __syncthreads();
+  rfft_inner<16, -1>(v, j, tw);
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) ex[(k1 * 16 + j) * 16 + col] = v[k1];
+  __syncthreads();
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) v[n2] = ex[(j * 16 + n2) * 16 + col];
+  rfft_outer<16, 16, -1>(v);
+  if (!on) return;
+  // v[k2] = X[j + 16 k2]; keep |f_y| <= FY
+  float2 *dst = reinterpret_cast<float2 *>(w.s2) + plane * g.NY * g.KZP + kz0 + col;
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) {
+    const int k = j + 16 * k2;
+    if (k <= g.FY) dst[int64_t(k) * g.KZP] = v[k2];
+    else if (k >= 256 - g.FY) dst[int64_t(k - 256 + g.NY) * g.KZP] = v[k2];
+  }
+}
+
 // y forward (step ii, second axis): plane (c, x), a block of kb z columns;
 // keeps only |f_y| <= FY.
 __device__ __forceinline__ void yfwd_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int bx, int by) {
+  if (yreg_ok(g)) {
+    yfwd_reg(g, t, w, bx, by);
+    return;
+  }
   extern __shared__ float smem[];
   const int kb = g.kb, ld = kb + 1, My = g.M[1];
   float2 *buf = reinterpret_cast<float2 *>(smem);
@@ -989,12 +1150,110 @@ __device__ __forceinline__ float2 kernel_eval(const float *fc, const float *gc, 
   return make_float2(phi, dph);
 }
 
+// Fused x pass on the register FFT (M_x = 256, 16 columns per workgroup).
+// The forward transform leaves thread (col, j) with X[j + 16 k2], which is
+// both where the multiply needs it and the input layout of the inverse.
+__device__ __forceinline__ void xmul_reg(const Geo &g, const Tables &t, const Work &w, int mode, const double *__restrict__ grad, int bx, int by) {
+  extern __shared__ float smem[];
+  float2 *ex = reinterpret_cast<float2 *>(smem);  // [k1][n2][col]
+  float2 *tw = ex + 256 * 16;
+  float *fc = reinterpret_cast<float *>(tw + 256);
+  float *gc = fc + kKerCoef;
+  __shared__ double red[7][PSWF_THREADS / 64];
+  const int tid = threadIdx.x, col = tid & 15, j = tid >> 4;
+  const int blk = bx, c = by;
+  const int iy = t.xblk[4 * blk], kz0 = t.xblk[4 * blk + 1], ncol = t.xblk[4 * blk + 2];
+  const bool on = col < ncol;
+  const int64_t xstride = int64_t(g.NY) * g.KZP;
+  float2 *col0 = reinterpret_cast<float2 *>(w.s2) + int64_t(c) * 256 * xstride + int64_t(iy) * g.KZP + kz0 + col;
+  float2 v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) v[n1] = on ? col0[(16 * n1 + j) * xstride] : make_float2(0.f, 0.f);
+  const KChan kc = t.kch[c];
+  tw[tid] = reinterpret_cast<const float2 *>(t.tw_x)[tid];
+  for (int e = tid; e < kKerCoef; e += PSWF_THREADS) {
+    fc[e] = t.kf[c * kKerCoef + e];
+    gc[e] = t.kg[c * kKerCoef + e];
+  }
+  __syncthreads();
+  rfft_inner<16, -1>(v, j, tw);
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) ex[(k1 * 16 + j) * 16 + col] = v[k1];
+  __syncthreads();
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) v[n2] = ex[(j * 16 + n2) * 16 + col];
+  rfft_outer<16, 16, -1>(v);
+
+  const int fy = iy <= g.FY ? iy : iy - g.NY;
+  const float ky = fy * g.kunit[1];
+  const float dy = t.Dy[iy];
+  const int kz = kz0 + col;
+  const float kzv = kz * g.kunit[2];
+  const float dyz = on ? dy * t.Dz[kz] : 0.0f;
+  const float wz = (kz == 0) ? 1.0f : 2.0f;
+  const float scale = (mode == 2 ? float(grad[c]) : 1.0f) * g.invV;
+  float acc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) {
+    const int mx = j + 16 * k2;
+    const int fx = mx <= 128 ? mx : mx - 256;
+    const float kx = fx * g.kunit[0];
+    const float k2v = kx * kx + ky * ky + kzv * kzv;
+    float mult = 0.0f;
+    if (on && k2v > 0.0f && k2v <= g.kc2 && mx != 128) {
+      const float k = sqrtf(k2v);
+      const float2 ph = kernel_eval(fc, gc, kc, k * g.kinv);
+      const float D = t.Dx[mx] * dyz;
+      const float s2 = (v[k2].x * v[k2].x + v[k2].y * v[k2].y) * D * wz;
+      acc[0] += ph.x * s2;
+      const float vd = ph.y * s2;
+      acc[1] += vd * kx * kx;
+      acc[2] += vd * ky * ky;
+      acc[3] += vd * kzv * kzv;
+      acc[4] += vd * kx * ky;
+      acc[5] += vd * kx * kzv;
+      acc[6] += vd * ky * kzv;
+      mult = ph.x * D * scale;
+    }
+    v[k2] = cscale(v[k2], mult);
+  }
+  // block reduction in FP64, fixed order
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    double d = double(acc[i]);
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_down(d, off, 64);
+    if (lane == 0) red[i][wave] = d;
+  }
+  __syncthreads();
+  if (tid < 7) {
+    double sum = 0.0;
+    for (int k = 0; k < PSWF_THREADS / 64; ++k) sum += red[tid][k];
+    w.epart[(int64_t(c) * g.nxblk + blk) * 8 + tid] = sum;
+  }
+  if (mode == 0) return;
+  rfft_inner<16, 1>(v, j, tw);
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) ex[(k1 * 16 + j) * 16 + col] = v[k1];
+  __syncthreads();
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) v[n2] = ex[(j * 16 + n2) * 16 + col];
+  rfft_outer<16, 16, 1>(v);
+  if (!on) return;
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) col0[(j + 16 * k2) * xstride] = v[k2];
+}
+
 // Fused x pass (steps ii-iv and the first inverse axis): x transform of one
 // block of (f_y, k_z) columns, diagonal scaling by Phi_p h^6 / What^2 / V,
 // FP64 block partials of the energy and virial, inverse x transform.
 // mode 0: energy only (no write-back), 1: full, 2: adjoint with the scale
 // grad[c] folded into the kernel.
 __device__ __forceinline__ void xmul_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int mode, const double *__restrict__ grad, int bx, int by) {
+  if (xreg_ok(g)) {
+    xmul_reg(g, t, w, mode, grad, bx, by);
+    return;
+  }
   extern __shared__ float smem[];
   const int kb = g.kb, ld = kb + 1, Mx = g.M[0];
   float2 *buf = reinterpret_cast<float2 *>(smem);
@@ -1083,8 +1342,55 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_xmul(Geo g, Tables t, FftAxis 
   xmul_body(g, t, ax, w, mode, grad, blockIdx.x, blockIdx.y);
 }
 
+// inverse y on the register FFT (M_y = 256, 16 columns per workgroup)
+__device__ __forceinline__ void yinv_reg(const Geo &g, const Tables &t, const Work &w, int bx, int by) {
+  extern __shared__ float smem[];
+  float2 *ex = reinterpret_cast<float2 *>(smem);  // [k1][n2][col]
+  float2 *tw = ex + 256 * 16;
+  const int tid = threadIdx.x, col = tid & 15, j = tid >> 4;
+  const int kz0 = bx * 16;
+  const int64_t plane = by;
+  const int kz = kz0 + col;
+  const bool on = kz < g.KZ;
+  const float2 *src = reinterpret_cast<const float2 *>(w.s2) + plane * g.NY * g.KZP + kz;
+  // row m = 16 n1 + j holds f_y = m (m <= FY) or m - 256 (m >= 256 - FY),
+  // stored at iy = m or m - 256 + NY; the other rows are zero
+  float2 v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    const int m = 16 * n1 + j;
+    const int iy = m <= g.FY ? m : m - 256 + g.NY;
+    const bool kept = on && (m <= g.FY || m >= 256 - g.FY);
+    v[n1] = kept ? src[int64_t(iy) * g.KZP] : make_float2(0.f, 0.f);
+  }
+  tw[tid] = reinterpret_cast<const float2 *>(t.tw_y)[tid];
+  // columns the x pass skipped (k_z >= blim) still hold forward data
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    const int m = 16 * n1 + j;
+    const int iy = m <= g.FY ? m : m - 256 + g.NY;
+    if ((m <= g.FY || m >= 256 - g.FY) && kz >= t.blim[iy]) v[n1] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  rfft_inner<16, 1>(v, j, tw);
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) ex[(k1 * 16 + j) * 16 + col] = v[k1];
+  __syncthreads();
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) v[n2] = ex[(j * 16 + n2) * 16 + col];
+  rfft_outer<16, 16, 1>(v);
+  if (!on) return;
+  float2 *dst = reinterpret_cast<float2 *>(w.s1) + plane * 256 * g.KZP + kz;
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) dst[int64_t(j + 16 * k2) * g.KZP] = v[k2];
+}
+
 // inverse y: kept rows (zero elsewhere and for columns the x pass skipped)
 __device__ __forceinline__ void yinv_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int bx, int by) {
+  if (yreg_ok(g)) {
+    yinv_reg(g, t, w, bx, by);
+    return;
+  }
   extern __shared__ float smem[];
   const int kb = g.kb, ld = kb + 1, My = g.M[1];
   float2 *buf = reinterpret_cast<float2 *>(smem);
@@ -1126,9 +1432,69 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_yinv(Geo g, Tables t, FftAxis 
   yinv_body(g, t, ax, w, blockIdx.x, blockIdx.y);
 }
 
+// z C2R on the register FFT: 32 lines of Nz = 128 per workgroup
+__device__ __forceinline__ void zinv_reg(const Geo &g, const Tables &t, const Work &w, int64_t nlines_total, int bx) {
+  extern __shared__ float smem[];
+  constexpr int Nz = 128;
+  float2 *ex = reinterpret_cast<float2 *>(smem);
+  float2 *tw = ex + 32 * kZregLine;
+  float2 *twr = tw + Nz;
+  const int tid = threadIdx.x, j = tid & 7, l = tid >> 3;
+  const int64_t line0 = int64_t(bx) * 32;
+  const bool on = line0 + l < nlines_total;
+  float2 *xl = ex + l * kZregLine;
+  // stored modes k < KZ of the line, zero up to and including k = Nz
+  const float2 *src = reinterpret_cast<const float2 *>(w.s1) + (line0 + l) * g.KZP;
+  float2 x[17];
+#pragma unroll
+  for (int i = 0; i < 17; ++i) {
+    const int k = j + 8 * i;
+    x[i] = (on && k < g.KZ) ? src[k] : make_float2(0.f, 0.f);
+  }
+  for (int e = tid; e < Nz; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_z)[e];
+  for (int e = tid; e <= Nz; e += PSWF_THREADS) twr[e] = reinterpret_cast<const float2 *>(t.tw_zr)[e];
+#pragma unroll
+  for (int i = 0; i < 17; ++i)
+    if (j + 8 * i <= Nz) xl[j + 8 * i] = x[i];
+  __syncthreads();
+  // Z'_k = (X_k + conj X_{N-k}) + i exp(+2 pi i k / M_z) (X_k - conj X_{N-k}), k = 8 n1 + j
+  float2 v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    const int k = 8 * n1 + j;
+    const float2 xa = xl[k], xb = xl[Nz - k];
+    const float2 a = make_float2(xa.x + xb.x, xa.y - xb.y);
+    const float2 b = make_float2(xa.x - xb.x, xa.y + xb.y);
+    float2 wv = twr[k];
+    wv.y = -wv.y;
+    const float2 ib = cmul(wv, b);
+    v[n1] = make_float2(a.x - ib.y, a.y + ib.x);
+  }
+  rfft_inner<16, 1>(v, j, tw);
+  wave_sync();
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) xl[k1 * 9 + j] = v[k1];
+  wave_sync();
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) v[q * 8 + n2] = xl[(j + 8 * q) * 9 + n2];
+  rfft_outer<16, 8, 1>(v);
+  if (!on) return;
+  float2 *dst = reinterpret_cast<float2 *>(w.grid) + (line0 + l) * Nz + j;
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) dst[8 * q + 16 * k2] = v[q * 8 + k2];
+}
+
 // z C2R: Z'_k = (X_k + conj X_{N-k}) + i exp(+2 pi i k / M_z)(X_k - conj X_{N-k}),
 // inverse transform of length Nz gives x_2m + i x_2m+1.
 __device__ __forceinline__ void zinv_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int64_t nlines_total, int bx) {
+  if (zreg_ok(g)) {
+    zinv_reg(g, t, w, nlines_total, bx);
+    return;
+  }
   extern __shared__ float smem[];
   const int L = g.zlines, ld = L + 1, Nz = g.Nz;
   int llog = 0;
@@ -1517,7 +1883,10 @@ bool gather_tile_ok(int bx, int by, int bz, int P) {
   const int ex = bx + P - 1, ey = by + P - 1, ez = bz + P - 1;
   return ex * ey * ez <= kGatherThreads * kGatherStage && gather_lds_bytes(g, 1) <= 160 * 1024;
 }
-size_t zpass_lds_bytes(const Geo &g) { return (size_t(g.Nz) * (g.zlines + 1) + 2 * g.Nz + 1) * 8; }
+size_t zpass_lds_bytes(const Geo &g) {
+  if (zreg_ok(g)) return (size_t(32) * kZregLine + 2 * g.Nz + 1) * 8;
+  return (size_t(g.Nz) * (g.zlines + 1) + 2 * g.Nz + 1) * 8;
+}
 size_t ypass_lds_bytes(const Geo &g) { return (size_t(g.M[1]) * (g.kb + 1) + g.M[1]) * 8; }
 size_t xpass_lds_bytes(const Geo &g) {
   return (size_t(g.M[0]) * (g.kb + 1) + g.M[0]) * 8 + 2 * kKerCoef * 4;
