@@ -15,7 +15,7 @@ import os
 import threading
 import time
 
-KERNEL_VERSION = 8
+KERNEL_VERSION = 9
 _LOCK = threading.Lock()
 
 
@@ -65,7 +65,7 @@ def _tile_fits(bx, by, bz, P, lds=160 * 1024):
     if ex * ey * ez > 512 * 16:
         return False
     sz = 8 if ez <= 8 else 8 + (ez - 8 + 31) // 32 * 32   # row stride = 8 (mod 32)
-    return (ex * ey * sz + 96) * 4 <= lds
+    return (ex * ey * sz + 3 + 96) * 4 <= lds
 
 
 def candidate_tiles(grid, P, limit=6):

@@ -290,12 +290,23 @@ constexpr int kZregLine = 152;  // LDS float2 per z line: 16 x 9 exchange slots,
 
 // ---------------------------------------------------------------------------
 // Window psi_s(t), t in [-1, 1): piecewise polynomial in |t| (even function).
+// The 12 coefficients of a segment are read as three 16-byte LDS loads
+// (the table is 16-byte aligned), all in flight before the Horner chain.
+static_assert(kWinDeg + 1 == 12, "window segments are read as three float4");
+__device__ __forceinline__ void win_coef(const float *wc, int s, float (&c)[12]) {
+  const float4 *c4 = reinterpret_cast<const float4 *>(wc + s * (kWinDeg + 1));
+  const float4 a = c4[0], b = c4[1], d = c4[2];
+  c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
+  c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
+  c[8] = d.x; c[9] = d.y; c[10] = d.z; c[11] = d.w;
+}
 __device__ __forceinline__ float win_eval(const float *wc, float t) {
   float a = fabsf(t);
   float y = a * kWinSeg;
   int s = min(int(y), kWinSeg - 1);
   float tau = 2.0f * (y - s) - 1.0f;
-  const float *c = wc + s * (kWinDeg + 1);
+  float c[12];
+  win_coef(wc, s, c);
   float r = c[kWinDeg];
 #pragma unroll
   for (int d = kWinDeg - 1; d >= 0; --d) r = fmaf(r, tau, c[d]);
@@ -307,7 +318,8 @@ __device__ __forceinline__ float2 win_eval_d(const float *wc, float t) {
   float y = a * kWinSeg;
   int s = min(int(y), kWinSeg - 1);
   float tau = 2.0f * (y - s) - 1.0f;
-  const float *c = wc + s * (kWinDeg + 1);
+  float c[12];
+  win_coef(wc, s, c);
   float r = c[kWinDeg], dr = 0.0f;
 #pragma unroll
   for (int d = kWinDeg - 1; d >= 0; --d) {
@@ -531,7 +543,7 @@ constexpr int kSpreadOutMax = (kSpreadMaxPts + kSpreadThreads - 1) / kSpreadThre
 // and the window coefficients follow it
 __host__ __device__ __forceinline__ int spread_stage_floats(int S) { return kSpreadCap * (kSpreadCGM + S); }
 __host__ __device__ __forceinline__ int spread_lds_floats(int S) {
-  return spread_stage_floats(S) + 5 * kSpreadList + 2 * kSpreadMaxCells + 1 + kWinSeg * (kWinDeg + 1);
+  return spread_stage_floats(S) + 5 * kSpreadList + 2 * kSpreadMaxCells + 1 + 3 + kWinSeg * (kWinDeg + 1);
 }
 __host__ __device__ __forceinline__ int spread_pad4(int b) { return (b + 3) & ~3; }
 // blocks along z of a tile edge (1, 2 or 4 supported); 0 if unsupported
@@ -740,7 +752,7 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   int *li = ld + kSpreadList;                                       // [list] atom index
   int *rb = li + kSpreadList;                                       // [cells] first atom of a candidate cell
   int *rs = rb + kSpreadMaxCells;                                   // [cells + 1] prefix of their sizes
-  float *wcf = reinterpret_cast<float *>(rs + kSpreadMaxCells + 1); // window coefficients
+  float *wcf = smem + ((int(reinterpret_cast<float *>(rs + kSpreadMaxCells + 1) - smem) + 3) & ~3);  // window coefficients, 16-byte aligned
   // (the write-out stage below reuses the cq and cw area)
   __shared__ int wcount[kSpreadScreenPer * (kSpreadThreads / 64)];
 
@@ -1038,8 +1050,13 @@ __device__ __forceinline__ void zfwd_body(const Geo &g, const Tables &t, const F
   }
 }
 
+// REG: the register FFT path (the planner's 256-point geometry)
+template <bool REG>
 __global__ __launch_bounds__(PSWF_THREADS) void k_zfwd(Geo g, Tables t, FftAxis ax, Work w, int64_t nlines_total) {
-  zfwd_body(g, t, ax, w, nlines_total, blockIdx.x);
+  if (REG)
+    zfwd_reg(g, t, w, nlines_total, blockIdx.x);
+  else
+    zfwd_body(g, t, ax, w, nlines_total, blockIdx.x);
 }
 
 // y forward on the register FFT (M_y = 256, 16 columns per workgroup):
@@ -1113,8 +1130,13 @@ __device__ __forceinline__ void yfwd_body(const Geo &g, const Tables &t, const F
   }
 }
 
+// REG: the register FFT path (the planner's 256-point geometry)
+template <bool REG>
 __global__ __launch_bounds__(PSWF_THREADS) void k_yfwd(Geo g, Tables t, FftAxis ax, Work w) {
-  yfwd_body(g, t, ax, w, blockIdx.x, blockIdx.y);
+  if (REG)
+    yfwd_reg(g, t, w, blockIdx.x, blockIdx.y);
+  else
+    yfwd_body(g, t, ax, w, blockIdx.x, blockIdx.y);
 }
 
 // Fourier kernel at kappa: (Phi, Phi'/k) from the per-channel polynomials.
@@ -1337,9 +1359,14 @@ __device__ __forceinline__ void xmul_body(const Geo &g, const Tables &t, const F
   }
 }
 
+// REG: the register FFT path (the planner's 256-point geometry)
+template <bool REG>
 __global__ __launch_bounds__(PSWF_THREADS) void k_xmul(Geo g, Tables t, FftAxis ax, Work w, int mode,
                                                         const double *__restrict__ grad) {
-  xmul_body(g, t, ax, w, mode, grad, blockIdx.x, blockIdx.y);
+  if (REG)
+    xmul_reg(g, t, w, mode, grad, blockIdx.x, blockIdx.y);
+  else
+    xmul_body(g, t, ax, w, mode, grad, blockIdx.x, blockIdx.y);
 }
 
 // inverse y on the register FFT (M_y = 256, 16 columns per workgroup)
@@ -1428,8 +1455,13 @@ __device__ __forceinline__ void yinv_body(const Geo &g, const Tables &t, const F
   }
 }
 
+// REG: the register FFT path (the planner's 256-point geometry)
+template <bool REG>
 __global__ __launch_bounds__(PSWF_THREADS) void k_yinv(Geo g, Tables t, FftAxis ax, Work w) {
-  yinv_body(g, t, ax, w, blockIdx.x, blockIdx.y);
+  if (REG)
+    yinv_reg(g, t, w, blockIdx.x, blockIdx.y);
+  else
+    yinv_body(g, t, ax, w, blockIdx.x, blockIdx.y);
 }
 
 // z C2R on the register FFT: 32 lines of Nz = 128 per workgroup
@@ -1551,8 +1583,13 @@ __device__ __forceinline__ void zinv_body(const Geo &g, const Tables &t, const F
   }
 }
 
+// REG: the register FFT path (the planner's 256-point geometry)
+template <bool REG>
 __global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis ax, Work w, int64_t nlines_total) {
-  zinv_body(g, t, ax, w, nlines_total, blockIdx.x);
+  if (REG)
+    zinv_reg(g, t, w, nlines_total, blockIdx.x);
+  else
+    zinv_body(g, t, ax, w, nlines_total, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1604,7 +1641,7 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
   const int SZ = gather_sz(EZ);
   const int plane = EY * SZ;
   float *tile = smem;                                           // [EX][EY][SZ]
-  float *wcf = smem + EX * plane;
+  float *wcf = smem + ((EX * plane + 3) & ~3);                 // window coefficients, 16-byte aligned
   const int tid = threadIdx.x;
   const int cell = bx;
   const int s = w.cell_start[cell], e = w.cell_start[cell + 1];
@@ -1788,11 +1825,27 @@ __device__ __forceinline__ int xcd_contiguous(int b, int n) {
   return xcd * q + min(xcd, r) + j;
 }
 
+// Order of tiles within an XCD's range: compact groups of up to 4 x 4 x 4
+// tiles (the largest of 4, 2, 1 dividing the tile count per axis) instead
+// of whole rows, so that the tiles resident at once share most of their
+// halo planes in every direction, not only along y and z.
+__device__ __forceinline__ int tile_grouped(int i, const int *nc) {
+  int gd[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) gd[a] = (nc[a] & 3) == 0 ? 4 : ((nc[a] & 1) == 0 ? 2 : 1);
+  const int gsize = gd[0] * gd[1] * gd[2];
+  const int gi = i / gsize, wi = i - gi * gsize;
+  const int ngy = nc[1] / gd[1], ngz = nc[2] / gd[2];
+  const int gz = gi % ngz, gy = (gi / ngz) % ngy, gx = gi / (ngz * ngy);
+  const int iz = wi % gd[2], iy = (wi / gd[2]) % gd[1], ix = wi / (gd[2] * gd[1]);
+  return ((gx * gd[0] + ix) * nc[1] + gy * gd[1] + iy) * nc[2] + gz * gd[2] + iz;
+}
+
 template <int P>
 __global__ __launch_bounds__(kGatherThreads, 4) void k_gather(Geo g, Tables t, Work w, float *__restrict__ fout,
                                                             float *__restrict__ pout, int mode,
                                                             const double *__restrict__ grad) {
-  gather_body<P>(g, t, w, fout, pout, mode, grad, xcd_contiguous(blockIdx.x, gridDim.x));
+  gather_body<P>(g, t, w, fout, pout, mode, grad, tile_grouped(xcd_contiguous(blockIdx.x, gridDim.x), g.nc));
 }
 
 // Final FP64 reduction: energy [3C] (E_k, E_0, E_self) and virial [6].
@@ -1872,7 +1925,7 @@ bool spread_tile_ok(int bx, int by, int bz) {
 size_t gather_lds_bytes(const Geo &g, int ncg) {
   (void)ncg;
   const size_t EX = g.B[0] + g.P - 1, EY = g.B[1] + g.P - 1, EZ = g.B[2] + g.P - 1;
-  return (EX * EY * gather_sz(int(EZ)) + kWinSeg * (kWinDeg + 1)) * 4;
+  return (EX * EY * gather_sz(int(EZ)) + 3 + kWinSeg * (kWinDeg + 1)) * 4;
 }
 bool gather_tile_ok(int bx, int by, int bz, int P) {
   Geo g{};
@@ -1981,14 +2034,14 @@ hipError_t launch_spread(const Geo &g, const Tables &t, const Work &w, int cg0, 
 
 hipError_t launch_zfwd(const Geo &g, const Tables &t, const FftAxis &az, const Work &w, hipStream_t st) {
   const int64_t lines = int64_t(g.C) * g.M[0] * g.M[1];
-  hipLaunchKernelGGL(k_zfwd, dim3(nblocks(lines, g.zlines)), dim3(PSWF_THREADS), zpass_lds_bytes(g), st, g, t,
+  hipLaunchKernelGGL(zreg_ok(g) ? k_zfwd<true> : k_zfwd<false>, dim3(nblocks(lines, g.zlines)), dim3(PSWF_THREADS), zpass_lds_bytes(g), st, g, t,
                      az, w, lines);
   LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t launch_yfwd(const Geo &g, const Tables &t, const FftAxis &ay, const Work &w, hipStream_t st) {
-  hipLaunchKernelGGL(k_yfwd, dim3(nblocks(g.KZ, g.kb), g.C * g.M[0]), dim3(PSWF_THREADS), ypass_lds_bytes(g),
+  hipLaunchKernelGGL(yreg_ok(g) ? k_yfwd<true> : k_yfwd<false>, dim3(nblocks(g.KZ, g.kb), g.C * g.M[0]), dim3(PSWF_THREADS), ypass_lds_bytes(g),
                      st, g, t, ay, w);
   LAUNCH_CHECK();
   return hipSuccess;
@@ -1997,14 +2050,14 @@ hipError_t launch_yfwd(const Geo &g, const Tables &t, const FftAxis &ay, const W
 hipError_t launch_xmul(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int mode,
                        const double *grad, hipStream_t st) {
   if (g.nxblk == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_xmul, dim3(g.nxblk, g.C), dim3(PSWF_THREADS), xpass_lds_bytes(g), st, g, t, ax, w, mode,
+  hipLaunchKernelGGL(xreg_ok(g) ? k_xmul<true> : k_xmul<false>, dim3(g.nxblk, g.C), dim3(PSWF_THREADS), xpass_lds_bytes(g), st, g, t, ax, w, mode,
                      grad);
   LAUNCH_CHECK();
   return hipSuccess;
 }
 
 hipError_t launch_yinv(const Geo &g, const Tables &t, const FftAxis &ay, const Work &w, hipStream_t st) {
-  hipLaunchKernelGGL(k_yinv, dim3(nblocks(g.KZ, g.kb), g.C * g.M[0]), dim3(PSWF_THREADS), ypass_lds_bytes(g),
+  hipLaunchKernelGGL(yreg_ok(g) ? k_yinv<true> : k_yinv<false>, dim3(nblocks(g.KZ, g.kb), g.C * g.M[0]), dim3(PSWF_THREADS), ypass_lds_bytes(g),
                      st, g, t, ay, w);
   LAUNCH_CHECK();
   return hipSuccess;
@@ -2012,7 +2065,7 @@ hipError_t launch_yinv(const Geo &g, const Tables &t, const FftAxis &ay, const W
 
 hipError_t launch_zinv(const Geo &g, const Tables &t, const FftAxis &az, const Work &w, hipStream_t st) {
   const int64_t lines = int64_t(g.C) * g.M[0] * g.M[1];
-  hipLaunchKernelGGL(k_zinv, dim3(nblocks(lines, g.zlines)), dim3(PSWF_THREADS), zpass_lds_bytes(g), st, g, t,
+  hipLaunchKernelGGL(zreg_ok(g) ? k_zinv<true> : k_zinv<false>, dim3(nblocks(lines, g.zlines)), dim3(PSWF_THREADS), zpass_lds_bytes(g), st, g, t,
                      az, w, lines);
   LAUNCH_CHECK();
   return hipSuccess;
