@@ -15,7 +15,7 @@ import os
 import threading
 import time
 
-KERNEL_VERSION = 9
+KERNEL_VERSION = 10
 _LOCK = threading.Lock()
 
 
@@ -64,7 +64,7 @@ def _tile_fits(bx, by, bz, P, lds=160 * 1024):
     ex, ey, ez = bx + P - 1, by + P - 1, bz + P - 1
     if ex * ey * ez > 512 * 16:
         return False
-    sz = 8 if ez <= 8 else 8 + (ez - 8 + 31) // 32 * 32   # row stride = 8 (mod 32)
+    sz = 8 if ez <= 8 else 8 + (ez - 8 + 15) // 16 * 16   # row stride = 8 (mod 16)
     return (ex * ey * sz + 3 + 96) * 4 <= lds
 
 

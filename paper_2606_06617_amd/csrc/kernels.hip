@@ -1614,12 +1614,12 @@ constexpr unsigned kGatherOOB = 0xfffffff0u;                    // byte offset p
 // gfx9 raw buffer descriptor word 3 (32-bit dwords, range-checked offsets)
 constexpr int kBufferWord3 = 0x00020000;
 
-// Row stride of the halo tile: the smallest s >= ez with s = 8 (mod 32).
+// Row stride of the halo tile: the smallest s >= ez with s = 8 (mod 16).
 // LDS has 32 banks; the four lanes of an atom read rows y, y+1, y+2, y+3
-// (or y+4..y+7), which then fall on banks b, b+8, b+16, b+24: an atom
-// occupies the residue class of its base address mod 8, and atoms of
-// distinct classes never share a bank.
-__host__ __device__ __forceinline__ int gather_sz(int ez) { return ez <= 8 ? 8 : 8 + (ez - 8 + 31) / 32 * 32; }
+// (or y+4..y+7), which then fall on four banks 8 apart, so the 64 lanes of
+// a wave meet a bank about four times at most (a wave64 read costs the same
+// up to four-way).
+__host__ __device__ __forceinline__ int gather_sz(int ez) { return ez <= 8 ? 8 : 8 + (ez - 8 + 15) / 16 * 16; }
 
 // one channel's halo elements at byte offsets goff (range-checked buffer
 // loads: offsets past the channel read as 0)
@@ -1673,49 +1673,21 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
   // the next channel's halo is loaded into registers while the current one
   // is contracted, then written to LDS between two barriers
   float stage[kGatherStage];
+  gather_load_halo(w.grid, chan, 0, goff, stage);  // in flight during the set-up
   const int l = tid & (kGatherLanes - 1);
   const float sg = mode == 2 ? -1.0f : 1.0f;
   __syncthreads();  // window coefficients
 
-  __shared__ int rhist[8], order[kGatherAtoms];
-  __shared__ float4 rbuf[kGatherAtoms];
   for (int p0 = s; p0 < e; p0 += kGatherAtoms) {
     const int na = min(kGatherAtoms, e - p0);
-    // place atoms so that the 16 atoms of a wave spread over the 8 bank
-    // residue classes (z offset mod 8): sort by class, wave w takes sorted
-    // positions w, w + 8, w + 16, ...  (only lane placement changes: each
-    // atom's arithmetic is the same wherever it runs)
-    float4 rmine = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (tid < na) rmine = reinterpret_cast<const float4 *>(w.rec_a)[p0 + tid];
-    gather_load_halo(w.grid, chan, 0, goff, stage);  // in flight during the set-up
-    if (tid < 8) rhist[tid] = 0;
-    __syncthreads();
-    int rcls = 0;
-    if (tid < na) {
-      int oz = unpack_n0(__float_as_uint(rmine.w), 2) - t0[2];
-      if (oz < 0) oz += g.M[2];
-      rcls = oz & 7;
-      rbuf[tid] = rmine;
-      atomicAdd(&rhist[rcls], 1);
-    }
-    __syncthreads();
-    if (tid == 0) {
-      int run = 0;
-      for (int c = 0; c < 8; ++c) {
-        const int h = rhist[c];
-        rhist[c] = run;
-        run += h;
-      }
-    }
-    __syncthreads();
-    if (tid < na) order[atomicAdd(&rhist[rcls], 1)] = tid;
-    __syncthreads();
-    const int slot = tid / kGatherLanes;                                  // 16 per wave
-    const int pos = (slot % (64 / kGatherLanes)) * 8 + slot / (64 / kGatherLanes);
-    const bool act = pos < na;
-    const int kloc = order[min(pos, na - 1)];
-    const int a = p0 + kloc;
-    const float4 rr = rbuf[kloc];
+    // four lanes per atom; the lanes of an atom load its record together
+    const int slot = tid / kGatherLanes;
+    const bool act = slot < na;
+    const int a = p0 + min(slot, na - 1);
+    const float4 rr = reinterpret_cast<const float4 *>(w.rec_a)[a];
+    const int dst_atom = w.perm_a[a];  // used only at the end: loaded early
+    float qv = w.q_a[a];               // channel 0; later channels are loaded one ahead
+    if (p0 > s) gather_load_halo(w.grid, chan, 0, goff, stage);
     const unsigned pk = __float_as_uint(rr.w);
     int o[3];
 #pragma unroll
@@ -1753,13 +1725,16 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
     float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 
     for (int c = 0; c < g.C; ++c) {
-      const float qv = w.q_a[int64_t(c) * g.N + a];
       __syncthreads();  // the tile buffer is free
 #pragma unroll
       for (int r = 0; r < kGatherStage; ++r)
         if (loff[r] >= 0) tile[loff[r]] = stage[r];
       __syncthreads();
-      if (c + 1 < g.C) gather_load_halo(w.grid, chan, c + 1, goff, stage);
+      const float qc = qv;
+      if (c + 1 < g.C) {
+        gather_load_halo(w.grid, chan, c + 1, goff, stage);
+        qv = w.q_a[int64_t(c + 1) * g.N + a];
+      }
       float vphi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
 #pragma unroll 1
       for (int j = 0; j < R; ++j) {
@@ -1788,9 +1763,9 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
         gy = fmaf(dwyj, sp, gy);
         gz = fmaf(wyj, szz, gz);
       }
-      f0 = fmaf(qv, gx, f0);
-      f1 = fmaf(qv, gy, f1);
-      f2 = fmaf(qv, gz, f2);
+      f0 = fmaf(qc, gx, f0);
+      f1 = fmaf(qc, gy, f1);
+      f2 = fmaf(qc, gz, f2);
       if (pout) {
 #pragma unroll
         for (int off = 1; off < kGatherLanes; off <<= 1) vphi += __shfl_xor(vphi, off, kGatherLanes);
@@ -1798,7 +1773,7 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
           const double gsc = mode == 2 ? grad[c] : 1.0;
           // potential includes the zero-frequency term dE_0/dq = 2 a Q_net
           const float zero = float(2.0 * t.zero_V[c] / g.V * w.qsum[2 * c] * gsc);
-          pout[int64_t(c) * g.N + w.perm_a[a]] = vphi + zero;
+          pout[int64_t(c) * g.N + dst_atom] = vphi + zero;
         }
       }
     }
@@ -1809,7 +1784,7 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
       f2 += __shfl_xor(f2, off, kGatherLanes);
     }
     if (act && l == 0 && fout) {
-      const int64_t oo = 3 * int64_t(w.perm_a[a]);
+      const int64_t oo = 3 * int64_t(dst_atom);
       fout[oo] = sg * f0;
       fout[oo + 1] = sg * f1;
       fout[oo + 2] = sg * f2;
