@@ -15,7 +15,7 @@ import os
 import threading
 import time
 
-KERNEL_VERSION = 10
+KERNEL_VERSION = 11
 _LOCK = threading.Lock()
 
 
@@ -51,7 +51,7 @@ def _tile_fits(bx, by, bz, P, lds=160 * 1024):
     of 4/NBZ neighbouring y columns (so the y block count is a multiple of
     4/NBZ and there are at most 8 waves' worth of columns), padded edges
     summing to <= 64.  Gather: a one-channel halo tile of at most 8192
-    elements (16 per thread)."""
+    elements (16 per thread), two such buffers in LDS."""
     pad = lambda b: (b + 3) // 4 * 4
     nbz = pad(bz) // 4
     if nbz not in (1, 2, 4):
@@ -62,10 +62,7 @@ def _tile_fits(bx, by, bz, P, lds=160 * 1024):
     if nby % cpw or (pad(bx) // 4) * nby > 8 * cpw or S > 64 or bx * by * bz > 256 * (12 + S):
         return False
     ex, ey, ez = bx + P - 1, by + P - 1, bz + P - 1
-    if ex * ey * ez > 512 * 16:
-        return False
-    sz = 8 if ez <= 8 else 8 + (ez - 8 + 15) // 16 * 16   # row stride = 8 (mod 16)
-    return (ex * ey * sz + 3 + 96) * 4 <= lds
+    return ex * ey * ez <= 512 * 16 and (2 * 512 * 16 + 96) * 4 <= lds
 
 
 def candidate_tiles(grid, P, limit=6):

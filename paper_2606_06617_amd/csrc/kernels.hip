@@ -1614,21 +1614,21 @@ constexpr unsigned kGatherOOB = 0xfffffff0u;                    // byte offset p
 // gfx9 raw buffer descriptor word 3 (32-bit dwords, range-checked offsets)
 constexpr int kBufferWord3 = 0x00020000;
 
-// Row stride of the halo tile: the smallest s >= ez with s = 8 (mod 16).
-// LDS has 32 banks; the four lanes of an atom read rows y, y+1, y+2, y+3
-// (or y+4..y+7), which then fall on four banks 8 apart, so the 64 lanes of
-// a wave meet a bank about four times at most (a wave64 read costs the same
-// up to four-way).
-__host__ __device__ __forceinline__ int gather_sz(int ez) { return ez <= 8 ? 8 : 8 + (ez - 8 + 15) / 16 * 16; }
 
-// one channel's halo elements at byte offsets goff (range-checked buffer
-// loads: offsets past the channel read as 0)
-__device__ __forceinline__ void gather_load_halo(const float *grid, int64_t chan, int c,
-                                                 const unsigned (&goff)[kGatherStage], float (&stage)[kGatherStage]) {
+// One channel's halo straight into LDS (buffer loads with the LDS bit: no
+// registers, no LDS store instructions).  Wave wv moves elements
+// wv 64 + 512 r + lane of the [EX][EY][EZ] region, which land at those
+// float offsets of buf; goff holds each element's byte offset in the channel
+// (offsets past the channel read as 0).  Completion is tracked by vmcnt.
+constexpr int kGatherTileMax = kGatherThreads * kGatherStage;  // floats per tile buffer
+__device__ __forceinline__ void gather_dma_halo(const float *grid, int64_t chan, int c, const unsigned (&goff)[kGatherStage],
+                                                float *buf, int wv) {
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float *>(grid + int64_t(c) * chan), 0, int(unsigned(chan * 4)), kBufferWord3);
 #pragma unroll
-  for (int r = 0; r < kGatherStage; ++r) stage[r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, goff[r], 0, 0));
+  for (int r = 0; r < kGatherStage; ++r)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        rs, (__attribute__((address_space(3))) void *)(buf + wv * 64 + kGatherThreads * r), 4, goff[r], 0, 0, 0);
 }
 
 template <int P>
@@ -1638,10 +1638,11 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
   extern __shared__ float smem[];
   const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
   const int EX = Bx + P - 1, EY = By + P - 1, EZ = Bz + P - 1;
-  const int SZ = gather_sz(EZ);
+  const int SZ = EZ;                                            // rows unpadded: the DMA fills linear runs
   const int plane = EY * SZ;
-  float *tile = smem;                                           // [EX][EY][SZ]
-  float *wcf = smem + ((EX * plane + 3) & ~3);                 // window coefficients, 16-byte aligned
+  float *tile0 = smem;                                          // two [EX][EY][EZ] buffers, channels alternate
+  float *tile1 = smem + kGatherTileMax;
+  float *wcf = smem + 2 * kGatherTileMax;                      // window coefficients, 16-byte aligned
   const int tid = threadIdx.x;
   const int cell = bx;
   const int s = w.cell_start[cell], e = w.cell_start[cell + 1];
@@ -1650,13 +1651,13 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
   const int t0[3] = {cx * Bx, cy * By, cz * Bz};
   for (int k = tid; k < kWinSeg * (kWinDeg + 1); k += kGatherThreads) wcf[k] = t.win[k];
 
-  // halo elements this thread stages: elements tid + 512 r of the
-  // [EX][EY][EZ] region (LDS offsets with row stride SZ), the same for every
-  // channel.  Byte offsets within a channel of the grid; unused slots get an
-  // offset past the buffer range, which a buffer load returns as 0.
+  // halo elements this thread moves: elements tid + 512 r of the
+  // [EX][EY][EZ] region, the same for every channel.  Byte offsets within a
+  // channel of the grid; unused slots get an offset past the buffer range,
+  // which a buffer load returns as 0.
   const int nhalo = EX * EY * EZ;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   unsigned goff[kGatherStage];
-  int loff[kGatherStage];
 #pragma unroll
   for (int r = 0; r < kGatherStage; ++r) {
     const int el = tid + kGatherThreads * r;
@@ -1665,15 +1666,12 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
     if (gx >= g.M[0]) gx -= g.M[0];
     if (gy >= g.M[1]) gy -= g.M[1];
     if (gz >= g.M[2]) gz -= g.M[2];
-    const bool ok = el < nhalo;
-    goff[r] = ok ? unsigned((gx * g.M[1] + gy) * g.M[2] + gz) * 4u : kGatherOOB;
-    loff[r] = ok ? x * plane + y * SZ + z : -1;
+    goff[r] = el < nhalo ? unsigned((gx * g.M[1] + gy) * g.M[2] + gz) * 4u : kGatherOOB;
   }
   const int64_t chan = int64_t(g.M[0]) * g.M[1] * g.M[2];
-  // the next channel's halo is loaded into registers while the current one
-  // is contracted, then written to LDS between two barriers
-  float stage[kGatherStage];
-  gather_load_halo(w.grid, chan, 0, goff, stage);  // in flight during the set-up
+  // channel c is read from buffer c & 1 while channel c + 1 streams into
+  // the other one: one barrier per channel
+  gather_dma_halo(w.grid, chan, 0, goff, tile0, wv);  // in flight during the set-up
   const int l = tid & (kGatherLanes - 1);
   const float sg = mode == 2 ? -1.0f : 1.0f;
   __syncthreads();  // window coefficients
@@ -1687,7 +1685,10 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
     const float4 rr = reinterpret_cast<const float4 *>(w.rec_a)[a];
     const int dst_atom = w.perm_a[a];  // used only at the end: loaded early
     float qv = w.q_a[a];               // channel 0; later channels are loaded one ahead
-    if (p0 > s) gather_load_halo(w.grid, chan, 0, goff, stage);
+    if (p0 > s) {
+      __syncthreads();  // the previous pass has finished with both buffers
+      gather_dma_halo(w.grid, chan, 0, goff, tile0, wv);
+    }
     const unsigned pk = __float_as_uint(rr.w);
     int o[3];
 #pragma unroll
@@ -1725,14 +1726,14 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
     float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 
     for (int c = 0; c < g.C; ++c) {
-      __syncthreads();  // the tile buffer is free
-#pragma unroll
-      for (int r = 0; r < kGatherStage; ++r)
-        if (loff[r] >= 0) tile[loff[r]] = stage[r];
+      // this wave's part of channel c has landed; after the barrier all of
+      // it has, and every wave is done with channel c - 1
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
+      const float *tile = (c & 1) ? tile1 : tile0;
       const float qc = qv;
       if (c + 1 < g.C) {
-        gather_load_halo(w.grid, chan, c + 1, goff, stage);
+        gather_dma_halo(w.grid, chan, c + 1, goff, (c & 1) ? tile0 : tile1, wv);
         qv = w.q_a[int64_t(c + 1) * g.N + a];
       }
       float vphi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
@@ -1741,17 +1742,22 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
         const int yo = min(l + kGatherLanes * j, P - 1);
         const float *b = tile + base + yo * SZ;
         float sp = 0.f, sx = 0.f, szz = 0.f;
+        // rows double-buffered in registers: row lx + 1 is read while row
+        // lx is contracted
+        float gv[2][P];
+#pragma unroll
+        for (int lz = 0; lz < P; ++lz) gv[0][lz] = b[lz];
 #pragma unroll
         for (int lx = 0; lx < P; ++lx) {
-          const float *row = b + lx * plane;
-          float gv[P];
+          if (lx + 1 < P) {
 #pragma unroll
-          for (int lz = 0; lz < P; ++lz) gv[lz] = row[lz];
+            for (int lz = 0; lz < P; ++lz) gv[(lx + 1) & 1][lz] = b[(lx + 1) * plane + lz];
+          }
           float a0 = 0.f, a1 = 0.f;
 #pragma unroll
           for (int lz = 0; lz < P; ++lz) {
-            a0 = fmaf(wz[lz], gv[lz], a0);
-            a1 = fmaf(dwz[lz], gv[lz], a1);
+            a0 = fmaf(wz[lz], gv[lx & 1][lz], a0);
+            a1 = fmaf(dwz[lz], gv[lx & 1][lz], a1);
           }
           sp = fmaf(wx[lx], a0, sp);
           sx = fmaf(dwx[lx], a0, sx);
@@ -1900,7 +1906,10 @@ bool spread_tile_ok(int bx, int by, int bz) {
 size_t gather_lds_bytes(const Geo &g, int ncg) {
   (void)ncg;
   const size_t EX = g.B[0] + g.P - 1, EY = g.B[1] + g.P - 1, EZ = g.B[2] + g.P - 1;
-  return (EX * EY * gather_sz(int(EZ)) + 3 + kWinSeg * (kWinDeg + 1)) * 4;
+  (void)EX;
+  (void)EY;
+  (void)EZ;
+  return (2 * size_t(kGatherTileMax) + kWinSeg * (kWinDeg + 1)) * 4;
 }
 bool gather_tile_ok(int bx, int by, int bz, int P) {
   Geo g{};
