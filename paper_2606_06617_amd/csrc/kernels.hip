@@ -1010,10 +1010,6 @@ __device__ __forceinline__ void zfwd_reg(const Geo &g, const Tables &t, const Wo
 // The real line is packed as z_n = x_2n + i x_2n+1, transformed with length
 // Nz = M_z / 2 and split: X_k = E_k + exp(-2 pi i k / M_z) O_k.
 __device__ __forceinline__ void zfwd_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int64_t nlines_total, int bx) {
-  if (zreg_ok(g)) {
-    zfwd_reg(g, t, w, nlines_total, bx);
-    return;
-  }
   extern __shared__ float smem[];
   const int L = g.zlines, ld = L + 1, Nz = g.Nz;
   int llog = 0;
@@ -1097,10 +1093,6 @@ __device__ __forceinline__ void yfwd_reg(const Geo &g, const Tables &t, const Wo
 // y forward (step ii, second axis): plane (c, x), a block of kb z columns;
 // keeps only |f_y| <= FY.
 __device__ __forceinline__ void yfwd_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int bx, int by) {
-  if (yreg_ok(g)) {
-    yfwd_reg(g, t, w, bx, by);
-    return;
-  }
   extern __shared__ float smem[];
   const int kb = g.kb, ld = kb + 1, My = g.M[1];
   float2 *buf = reinterpret_cast<float2 *>(smem);
@@ -1272,10 +1264,6 @@ __device__ __forceinline__ void xmul_reg(const Geo &g, const Tables &t, const Wo
 // mode 0: energy only (no write-back), 1: full, 2: adjoint with the scale
 // grad[c] folded into the kernel.
 __device__ __forceinline__ void xmul_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int mode, const double *__restrict__ grad, int bx, int by) {
-  if (xreg_ok(g)) {
-    xmul_reg(g, t, w, mode, grad, bx, by);
-    return;
-  }
   extern __shared__ float smem[];
   const int kb = g.kb, ld = kb + 1, Mx = g.M[0];
   float2 *buf = reinterpret_cast<float2 *>(smem);
@@ -1414,10 +1402,6 @@ __device__ __forceinline__ void yinv_reg(const Geo &g, const Tables &t, const Wo
 
 // inverse y: kept rows (zero elsewhere and for columns the x pass skipped)
 __device__ __forceinline__ void yinv_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int bx, int by) {
-  if (yreg_ok(g)) {
-    yinv_reg(g, t, w, bx, by);
-    return;
-  }
   extern __shared__ float smem[];
   const int kb = g.kb, ld = kb + 1, My = g.M[1];
   float2 *buf = reinterpret_cast<float2 *>(smem);
@@ -1523,10 +1507,6 @@ __device__ __forceinline__ void zinv_reg(const Geo &g, const Tables &t, const Wo
 // z C2R: Z'_k = (X_k + conj X_{N-k}) + i exp(+2 pi i k / M_z)(X_k - conj X_{N-k}),
 // inverse transform of length Nz gives x_2m + i x_2m+1.
 __device__ __forceinline__ void zinv_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int64_t nlines_total, int bx) {
-  if (zreg_ok(g)) {
-    zinv_reg(g, t, w, nlines_total, bx);
-    return;
-  }
   extern __shared__ float smem[];
   const int L = g.zlines, ld = L + 1, Nz = g.Nz;
   int llog = 0;
@@ -2103,7 +2083,7 @@ __device__ __forceinline__ int find_item(const int *__restrict__ prefix, int n, 
 }
 
 template <int STAGE, int THREADS>
-__global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather) ? 4 : 1)) void k_batch(const BatchItem *__restrict__ items,
+__global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather) ? 4 : 3)) void k_batch(const BatchItem *__restrict__ items,
                                                     const int *__restrict__ prefix, int n, int mode) {
   const int b = blockIdx.x;
   const int s = find_item(prefix, n, b);
