@@ -65,6 +65,17 @@ def _tile_fits(bx, by, bz, P, lds=160 * 1024):
     return ex * ey * ez <= 512 * 16 and (2 * 512 * 16 + 96) * 4 <= lds
 
 
+def tile_feasible(grid, tile, P):
+    """A tile the library accepts: the kernels' limits and at most 64
+    candidate cells for the spread's screening."""
+    if any(m % b for m, b in zip(grid, tile)) or not _tile_fits(tile[0], tile[1], tile[2], P):
+        return False
+    cells = 1
+    for m, b in zip(grid, tile):
+        cells *= min(min(m // b - 1, (P - 2) // b + 1) + 1, 8)
+    return cells <= 64
+
+
 def candidate_tiles(grid, P, limit=6):
     """Feasible tiles ranked by useful-work fraction, plus the most parallel
     feasible ones (small grids)."""
@@ -72,12 +83,7 @@ def candidate_tiles(grid, P, limit=6):
     for bx in _divisors(grid[0]):
         for by in _divisors(grid[1]):
             for bz in _divisors(grid[2]):
-                if not _tile_fits(bx, by, bz, P):
-                    continue
-                cells = 1
-                for m, b in zip(grid, (bx, by, bz)):
-                    cells *= min(min(m // b - 1, (P - 2) // b + 1) + 1, 8)
-                if cells > 64:
+                if not tile_feasible(grid, (bx, by, bz), P):
                     continue
                 eff = bx / (bx + P - 1) * by / (by + P - 1) * bz / (bz + P - 1)
                 ncell = (grid[0] // bx) * (grid[1] // by) * (grid[2] // bz)
