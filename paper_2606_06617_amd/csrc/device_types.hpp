@@ -8,6 +8,7 @@
 namespace pswf {
 
 constexpr int kMaxRadixStages = 8;
+constexpr int kMaxChannels = 64;   // channels per plan (the ABI limit)
 constexpr int kWinSeg = 8;     // window polynomial: segments on |t| in [0, 1]
 constexpr int kWinDeg = 11;    // degree per segment
 constexpr int kKerSeg = 16;    // kernel polynomials: segments on kappa in [0, 1]

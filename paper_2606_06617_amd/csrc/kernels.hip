@@ -1811,41 +1811,42 @@ __global__ __launch_bounds__(kGatherThreads, 4) void k_gather(Geo g, Tables t, W
 
 // Final FP64 reduction: energy [3C] (E_k, E_0, E_self) and virial [6].
 __device__ __forceinline__ void finalize_body(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial) {
-  __shared__ double red[8][PSWF_THREADS];
-  __shared__ double vir[6];
-  const int tid = threadIdx.x;
-  if (tid < 6) vir[tid] = 0.0;
-  __syncthreads();
-  for (int c = 0; c < g.C; ++c) {
+  // one wave per channel at a time (channels c = wave, wave + 4, ...): lane
+  // sums over the x-pass blocks, then a fixed-order wave reduction; the
+  // channels' virial terms are added in channel order by one thread
+  __shared__ double vch[kMaxChannels][6];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int c = wave; c < g.C; c += PSWF_THREADS / 64) {
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int b = tid; b < g.nxblk; b += PSWF_THREADS)
+    for (int b = lane; b < g.nxblk; b += 64)
+#pragma unroll
       for (int i = 0; i < 7; ++i) acc[i] += w.epart[(int64_t(c) * g.nxblk + b) * 8 + i];
-    for (int i = 0; i < 7; ++i) red[i][tid] = acc[i];
-    __syncthreads();
-    for (int off = PSWF_THREADS / 2; off > 0; off >>= 1) {
-      if (tid < off)
-        for (int i = 0; i < 7; ++i) red[i][tid] += red[i][tid + off];
-      __syncthreads();
-    }
-    if (tid == 0) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+      for (int off = 32; off > 0; off >>= 1) acc[i] += __shfl_down(acc[i], off, 64);
+    if (lane == 0) {
       const double inv2V = 0.5 / g.V;
-      const double Ek = red[0][0] * inv2V;
+      const double Ek = acc[0] * inv2V;
       const double Q = w.qsum[2 * c], Q2 = w.qsum[2 * c + 1];
       const double E0 = t.zero_V[c] / g.V * Q * Q;
       energy[3 * c] = Ek;
       energy[3 * c + 1] = E0;
       energy[3 * c + 2] = t.self_coef[c] * Q2;
       // W_ab = (1/2V) sum |F|^2 D (Phi delta_ab + Phi'/k k_a k_b) + E_0 delta_ab
-      vir[0] += Ek + E0 + red[1][0] * inv2V;
-      vir[1] += Ek + E0 + red[2][0] * inv2V;
-      vir[2] += Ek + E0 + red[3][0] * inv2V;
-      vir[3] += red[4][0] * inv2V;
-      vir[4] += red[5][0] * inv2V;
-      vir[5] += red[6][0] * inv2V;
+      vch[c][0] = Ek + E0 + acc[1] * inv2V;
+      vch[c][1] = Ek + E0 + acc[2] * inv2V;
+      vch[c][2] = Ek + E0 + acc[3] * inv2V;
+      vch[c][3] = acc[4] * inv2V;
+      vch[c][4] = acc[5] * inv2V;
+      vch[c][5] = acc[6] * inv2V;
     }
-    __syncthreads();
   }
-  if (virial && tid < 6) virial[tid] = vir[tid];
+  __syncthreads();
+  if (virial && tid < 6) {
+    double v = 0.0;
+    for (int c = 0; c < g.C; ++c) v += vch[c][tid];
+    virial[tid] = v;
+  }
 }
 
 __global__ __launch_bounds__(PSWF_THREADS) void k_finalize(Geo g, Tables t, Work w, double *energy, double *virial) {

@@ -24,6 +24,8 @@
 
 using namespace pswf;
 
+static_assert(kMaxChannels == PSWFLR_MAX_CHANNELS, "device channel limit follows the ABI");
+
 namespace {
 
 const double kPi = 3.14159265358979323846264338327950288;
