@@ -69,10 +69,13 @@ def algorithmic_flops(info, N, C):
 
 def stage_kernel(stage, info):
     """Name (as in rocprofv3 summaries) of the kernel a timed stage launches;
-    the spread is instantiated per support and z blocks per tile edge."""
+    the spread is instantiated per support, z blocks per tile edge and
+    channel accumulators."""
     P = info["support"]
     nbz = (info["tile"][2] + 3) // 4
-    return {"spread": "k_spread<%d,%d>" % (P, nbz), "fft_z": "k_zfwd", "fft_y": "k_yfwd", "fft_x_scale": "k_xmul",
+    cg = int(info["cg_spread"])
+    cgt = 2 if cg <= 2 else (4 if cg <= 4 else 12)   # accumulator counts the spread is built for
+    return {"spread": "k_spread<%d,%d,%d>" % (P, nbz, cgt), "fft_z": "k_zfwd", "fft_y": "k_yfwd", "fft_x_scale": "k_xmul",
             "ifft_y": "k_yinv", "ifft_z": "k_zinv", "gather": "k_gather<%d>" % P}.get(stage)
 
 

@@ -531,7 +531,10 @@ constexpr int kSpreadCap = 256;     // candidates staged per flush
 constexpr int kSpreadScreenPer = 1; // atoms screened per thread per round
 constexpr int kSpreadList = kSpreadCap + kSpreadScreenPer * 512;  // screened-candidate list
 constexpr int kSpreadMaxCells = 64; // candidate cells of a tile
-constexpr int kSpreadCGM = 12;      // channels per launch
+constexpr int kSpreadCGM = 12;      // channels per launch (most)
+// accumulator counts the spread is instantiated for: 2, 4 or 12
+__host__ __device__ constexpr int spread_cg4(int cg) { return (cg + 3) / 4 * 4; }
+__host__ __device__ constexpr int spread_cg_template(int ncg) { return ncg <= 2 ? 2 : (ncg <= 4 ? 4 : kSpreadCGM); }
 constexpr int kSpreadNBW = 4;       // 4x4x4 blocks per wave
 constexpr int kSpreadMaxS = 64;     // padded tile edges Sx + Sy + Sz
 constexpr int kSpreadBias = 8;      // packed window offsets are stored + bias
@@ -601,14 +604,14 @@ __device__ __forceinline__ int spread_take(unsigned long long &u) {
 // add candidate `bit` of the current 64 to the blocks whose hit mask has
 // it; its charges come from lane `bit` of the per-lane charge registers
 // (v_readlane into SGPRs: a uniform operand of the FMAs, no LDS traffic)
-template <int NBZ>
-__device__ __forceinline__ void spread_accumulate(const SpreadCand<NBZ> &cnd, int bit, const float (&qreg)[kSpreadCGM],
+template <int NBZ, int CG>
+__device__ __forceinline__ void spread_accumulate(const SpreadCand<NBZ> &cnd, int bit, const float (&qreg)[spread_cg4(CG)],
                                                   const unsigned long long (&m)[kSpreadNBW],
-                                                  float (&acc)[kSpreadNBW][kSpreadCGM]) {
+                                                  float (&acc)[kSpreadNBW][CG]) {
   constexpr int CPW = kSpreadNBW / NBZ;
-  float q[kSpreadCGM];
+  float q[CG];
 #pragma unroll
-  for (int c = 0; c < kSpreadCGM; ++c)
+  for (int c = 0; c < CG; ++c)
     q[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qreg[c]), bit));
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
@@ -619,16 +622,16 @@ __device__ __forceinline__ void spread_accumulate(const SpreadCand<NBZ> &cnd, in
       if (!((m[j] >> bit) & 1ull)) continue;
       const float wv = wxy * cnd.wz[z];
 #pragma unroll
-      for (int qq = 0; qq < kSpreadCGM; ++qq) acc[j][qq] = fmaf(wv, q[qq], acc[j][qq]);
+      for (int qq = 0; qq < CG; ++qq) acc[j][qq] = fmaf(wv, q[qq], acc[j][qq]);
     }
   }
 }
 
-template <int P, int NBZ>
+template <int P, int NBZ, int CG>
 __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg0, int ncg, int ncand, const int *sz,
                                              float *cq, float *cw, const int *cd, const float *cf, const int *ci,
                                              const float *wcf, const int (&bo)[3], bool wval,
-                                             float (&acc)[kSpreadNBW][kSpreadCGM]) {
+                                             float (&acc)[kSpreadNBW][CG]) {
   constexpr int CPW = kSpreadNBW / NBZ;
   const int tid = threadIdx.x, lane = tid & 63;
   const int S = sz[0] + sz[1] + sz[2];
@@ -641,13 +644,13 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
   for (int t = tid; t < 3 * kSpreadCap; t += kSpreadThreads) {
     const int a = t / kSpreadCap, k = t - a * kSpreadCap;
     if (k >= ncand) continue;
-    float qv[kSpreadCGM];
+    float qv[spread_cg4(CG)];
     if (a == 0) {
       // all charge loads in flight at once (channel index clamped, unused
       // channels zeroed when stored)
       const int i = ci[k];
 #pragma unroll
-      for (int c = 0; c < kSpreadCGM; ++c) qv[c] = w.q_a[int64_t(cg0 + min(c, ncg - 1)) * g.N + i];
+      for (int c = 0; c < spread_cg4(CG); ++c) qv[c] = w.q_a[int64_t(cg0 + min(c, ncg - 1)) * g.N + i];
     }
     const int d = ((cd[k] >> (10 * a)) & 1023) - kSpreadBias;  // tile-relative window start
     const float r = cf[3 * k + a];
@@ -667,7 +670,7 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
     }
     if (a == 0) {
 #pragma unroll
-      for (int c = 0; c < kSpreadCGM; c += 4)
+      for (int c = 0; c < spread_cg4(CG); c += 4)
         *reinterpret_cast<float4 *>(cq + k * kSpreadCGM + c) =
             make_float4(c < ncg ? qv[c] : 0.0f, c + 1 < ncg ? qv[c + 1] : 0.0f, c + 2 < ncg ? qv[c + 2] : 0.0f,
                         c + 3 < ncg ? qv[c + 3] : 0.0f);
@@ -704,11 +707,11 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
     // register sets: the LDS reads of the next hit are in flight while the
     // current one is accumulated
     if (!u) continue;
-    float qreg[kSpreadCGM];
+    float qreg[spread_cg4(CG)];
     {
       const int kq = min(k, ncand - 1);
 #pragma unroll
-      for (int c = 0; c < kSpreadCGM; c += 4) {
+      for (int c = 0; c < spread_cg4(CG); c += 4) {
         const float4 q4 = *reinterpret_cast<const float4 *>(cq + kq * kSpreadCGM + c);
         qreg[c] = q4.x;
         qreg[c + 1] = q4.y;
@@ -726,19 +729,19 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
       const bool hb = u != 0ull;
       bb = hb ? spread_take(u) : ba;
       spread_load<NBZ>(cw, S, k0 + bb, xa, ya, za, cb);
-      spread_accumulate<NBZ>(ca, ba, qreg, m, acc);
+      spread_accumulate<NBZ, CG>(ca, ba, qreg, m, acc);
       if (!hb) break;
       const bool ha = u != 0ull;
       ba = ha ? spread_take(u) : bb;
       spread_load<NBZ>(cw, S, k0 + ba, xa, ya, za, ca);
-      spread_accumulate<NBZ>(cb, bb, qreg, m, acc);
+      spread_accumulate<NBZ, CG>(cb, bb, qreg, m, acc);
       if (!ha) break;
     }
   }
   __syncthreads();
 }
 
-template <int P, int NBZ>
+template <int P, int NBZ, int CG>
 __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, int bx) {
   constexpr int CPW = kSpreadNBW / NBZ;
   extern __shared__ float smem[];
@@ -770,11 +773,11 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   const int col0 = wave * CPW;
   const bool wval = col0 < ncol;
   const int bo[3] = {wval ? (col0 / nby) * 4 : 0, wval ? (col0 % nby) * 4 : 0, 0};
-  float acc[kSpreadNBW][kSpreadCGM];
+  float acc[kSpreadNBW][CG];
 #pragma unroll
   for (int j = 0; j < kSpreadNBW; ++j)
 #pragma unroll
-    for (int c = 0; c < kSpreadCGM; ++c) acc[j][c] = 0.0f;
+    for (int c = 0; c < CG; ++c) acc[j][c] = 0.0f;
 
   // candidate cells: this tile's cell and the ones before it along each
   // axis that can hold a window start reaching into the tile.  Their atom
@@ -872,7 +875,7 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
     const bool last = base + kSpreadScreenPer * kSpreadThreads >= total;
     while (nlist - c0 >= kSpreadCap || (last && c0 < nlist)) {
       const int n = min(kSpreadCap, nlist - c0);
-      spread_flush<P, NBZ>(g, w, cg0, ncg, n, sz, cq, cw, ld + c0, lf + 3 * c0, li + c0, wcf, bo, wval, acc);
+      spread_flush<P, NBZ, CG>(g, w, cg0, ncg, n, sz, cq, cw, ld + c0, lf + 3 * c0, li + c0, wcf, bo, wval, acc);
       c0 += n;
     }
     // keep the unflushed tail (fewer than kSpreadCap <= threads entries)
@@ -931,7 +934,7 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
         if (x < Bx && y < By && z < Bz) {
           float *dst = stage + (x * By + y) * Bz + z;
 #pragma unroll
-          for (int cc = 0; cc < kSpreadCGM; ++cc)
+          for (int cc = 0; cc < CG; ++cc)
             if (cc >= c0 && cc < c0 + nc) dst[(cc - c0) * nt] = acc[j][cc];
         }
       }
@@ -953,9 +956,10 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   }
 }
 
-template <int P, int NBZ>
+// CG: channel accumulators per point (2, 4 or 12); a launch covers ncg <= CG
+template <int P, int NBZ, int CG>
 __global__ __launch_bounds__(kSpreadThreads, 4) void k_spread(Geo g, Tables t, Work w, int cg0, int ncg) {
-  spread_body<P, NBZ>(g, t, w, cg0, ncg, blockIdx.x);
+  spread_body<P, NBZ, CG>(g, t, w, cg0, ncg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1964,14 +1968,23 @@ hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t
   return hipSuccess;
 }
 
-template <int P, int NBZ>
-static hipError_t spread_pz(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
-  hipError_t e = lds_request(reinterpret_cast<const void *>(&k_spread<P, NBZ>), spread_lds_bytes(g, ncg));
+template <int P, int NBZ, int CG>
+static hipError_t spread_pzc(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
+  hipError_t e = lds_request(reinterpret_cast<const void *>(&k_spread<P, NBZ, CG>), spread_lds_bytes(g, ncg));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_spread<P, NBZ>), dim3(g.ncell), dim3(kSpreadThreads), spread_lds_bytes(g, ncg), st, g, t,
+  hipLaunchKernelGGL((k_spread<P, NBZ, CG>), dim3(g.ncell), dim3(kSpreadThreads), spread_lds_bytes(g, ncg), st, g, t,
                      w, cg0, ncg);
   LAUNCH_CHECK();
   return hipSuccess;
+}
+
+template <int P, int NBZ>
+static hipError_t spread_pz(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
+  switch (spread_cg_template(g.CG_spread)) {
+    case 2: return spread_pzc<P, NBZ, 2>(g, t, w, cg0, ncg, st);
+    case 4: return spread_pzc<P, NBZ, 4>(g, t, w, cg0, ncg, st);
+    default: return spread_pzc<P, NBZ, kSpreadCGM>(g, t, w, cg0, ncg, st);
+  }
 }
 
 template <int P>
@@ -2100,12 +2113,16 @@ __global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather
     case kBsQsum: qsum_body(g, it.w, it.q, kQChunk, vb % it.qblocks, vb / it.qblocks); break;
     case kBsQreduce: qreduce_body(g, it.w, it.qblocks); break;
     case kBsSpread: {
-      const int nbz = spread_nbz(g.B[2]);
+      const int nbz = spread_nbz(g.B[2]), cgt = spread_cg_template(g.C);
+#define PSWF_SPREAD_PZ(PP, ZZ)                                                 \
+  if (cgt == 2) spread_body<PP, ZZ, 2>(g, it.t, it.w, 0, g.C, vb);             \
+  else if (cgt == 4) spread_body<PP, ZZ, 4>(g, it.t, it.w, 0, g.C, vb);        \
+  else spread_body<PP, ZZ, kSpreadCGM>(g, it.t, it.w, 0, g.C, vb);
 #define PSWF_SPREAD_P(PP)                                                     \
   case PP:                                                                     \
-    if (nbz == 4) spread_body<PP, 4>(g, it.t, it.w, 0, g.C, vb);               \
-    else if (nbz == 2) spread_body<PP, 2>(g, it.t, it.w, 0, g.C, vb);          \
-    else spread_body<PP, 1>(g, it.t, it.w, 0, g.C, vb);                        \
+    if (nbz == 4) { PSWF_SPREAD_PZ(PP, 4) }                                   \
+    else if (nbz == 2) { PSWF_SPREAD_PZ(PP, 2) }                              \
+    else { PSWF_SPREAD_PZ(PP, 1) }                                            \
     break;
       switch (g.P) {
         PSWF_SPREAD_P(2)
@@ -2117,6 +2134,7 @@ __global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather
         PSWF_SPREAD_P(8)
       }
 #undef PSWF_SPREAD_P
+#undef PSWF_SPREAD_PZ
       break;
     }
     case kBsZfwd: zfwd_body(g, it.t, it.az, it.w, it.nlines, vb); break;
