@@ -155,9 +155,13 @@ pswflr_status pswflr_backward(pswflr_plan plan, pswflr_stream stream, void *work
 
 /* Many structures in one call (MLIP training batches, serving mixes).  Each
  * entry has its own plan (box, grid and channels may differ) and its own
- * device pointers; semantics per entry are those of pswflr_execute.  All
- * stages of all entries are issued as one persistent launch per stage
- * group; results for an entry do not depend on the other entries. */
+ * device pointers; semantics per entry are those of pswflr_execute.  Each
+ * stage is one launch covering every entry (a device table maps a block to
+ * its entry); entries with more than 12 channels are evaluated one call at
+ * a time instead.  Results for an entry do not depend on the other entries.
+ * The workspace (pswflr_batch_workspace gives its size) holds a header and
+ * one per-entry workspace; it is owned by the caller and must not be used by
+ * another call until this one has completed on the stream. */
 typedef struct {
   int64_t n_atoms;
   const float *pos;
