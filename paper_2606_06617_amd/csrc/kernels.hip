@@ -1149,8 +1149,12 @@ __device__ __forceinline__ float2 kernel_eval(const float *fc, const float *gc, 
   float y = kap * kKerSeg;
   int s = min(int(y), kKerSeg - 1);
   float tau = 2.0f * (y - s) - 1.0f;
-  const float *a = fc + s * (kKerDeg + 1);
-  const float *b = gc + s * (kKerDeg + 1);
+  // both coefficient sets of the segment as 16-byte loads (tables 16-byte
+  // aligned), all in flight before the Horner chains
+  static_assert(kKerDeg + 1 == 12, "kernel segments are read as three float4");
+  float a[12], b[12];
+  win_coef(fc, s, a);
+  win_coef(gc, s, b);
   float fv = a[kKerDeg], gv = b[kKerDeg];
 #pragma unroll
   for (int d = kKerDeg - 1; d >= 0; --d) {
@@ -1272,7 +1276,7 @@ __device__ __forceinline__ void xmul_body(const Geo &g, const Tables &t, const F
   const int kb = g.kb, ld = kb + 1, Mx = g.M[0];
   float2 *buf = reinterpret_cast<float2 *>(smem);
   float2 *tw = buf + Mx * ld;
-  float *fc = reinterpret_cast<float *>(tw + Mx);
+  float *fc = reinterpret_cast<float *>(tw + Mx + ((Mx * ld + Mx) & 1));  // 16-byte aligned
   float *gc = fc + kKerCoef;
   __shared__ double red[7][PSWF_THREADS / 64];
   const int tid = threadIdx.x;
@@ -1911,7 +1915,7 @@ size_t zpass_lds_bytes(const Geo &g) {
 }
 size_t ypass_lds_bytes(const Geo &g) { return (size_t(g.M[1]) * (g.kb + 1) + g.M[1]) * 8; }
 size_t xpass_lds_bytes(const Geo &g) {
-  return (size_t(g.M[0]) * (g.kb + 1) + g.M[0]) * 8 + 2 * kKerCoef * 4;
+  return (size_t(g.M[0]) * (g.kb + 1) + g.M[0] + 1) * 8 + 2 * kKerCoef * 4;
 }
 
 // Dynamic LDS above 64 KiB needs an opt-in per kernel; request it only when
