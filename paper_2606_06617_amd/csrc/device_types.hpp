@@ -80,6 +80,10 @@ struct Geo {
   int zlines;             // lines per z-pass block (power of two)
   int kb;                 // columns per y/x-pass block (power of two)
   int kb_log2;
+  // generic y passes: blocks of kby columns made of ypl planes (c, x) of
+  // kzq k_z columns each (kzq a power of two >= KZ when planes are packed,
+  // else kzq = kby and ypl = 1); the 256-point register path uses kb
+  int kby, kby_log2, kzq, kzq_log2, ypl;
   FastDiv div_nz;         // by Nz
   FastDiv div_kz;         // by KZ
   FastDiv div_gez;        // by the gather halo's z extent B_z + P - 1

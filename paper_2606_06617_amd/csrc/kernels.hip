@@ -1098,31 +1098,38 @@ __device__ __forceinline__ void yfwd_reg(const Geo &g, const Tables &t, const Wo
 // keeps only |f_y| <= FY.
 __device__ __forceinline__ void yfwd_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int bx, int by) {
   extern __shared__ float smem[];
-  const int kb = g.kb, ld = kb + 1, My = g.M[1];
+  const int kb = g.kby, ld = kb + 1, My = g.M[1];
   float2 *buf = reinterpret_cast<float2 *>(smem);
   float2 *tw = buf + My * ld;
   const int tid = threadIdx.x;
-  const int kz0 = bx * kb;
-  const int64_t plane = by;  // c * Mx + x
-  const int ncol = min(kb, g.KZ - kz0);
+  const int kz0 = bx * g.kzq;
+  const int64_t plane0 = int64_t(by) * g.ypl;  // planes c * Mx + x
+  const int64_t nplane = int64_t(g.C) * g.M[0];
+  // column j: plane plane0 + (j >> kzq_log2), k_z = kz0 + (j & (kzq - 1))
+  auto col_ok = [&](int j) {
+    return kz0 + (j & (g.kzq - 1)) < g.KZ && plane0 + (j >> g.kzq_log2) < nplane;
+  };
+  auto col_off = [&](int j, int64_t rows) {
+    return (plane0 + (j >> g.kzq_log2)) * rows * g.KZP + kz0 + (j & (g.kzq - 1));
+  };
   for (int e = tid; e < My; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_y)[e];
-  const float2 *src = reinterpret_cast<const float2 *>(w.s1) + plane * My * g.KZP;
+  const float2 *src = reinterpret_cast<const float2 *>(w.s1);
   staged16(
       My * kb,
       [&](int e) {
-        const int y = e >> g.kb_log2, col = e & (kb - 1);
-        return col < ncol ? src[int64_t(y) * g.KZP + kz0 + col] : make_float2(0.f, 0.f);
+        const int y = e >> g.kby_log2, col = e & (kb - 1);
+        return col_ok(col) ? src[col_off(col, My) + int64_t(y) * g.KZP] : make_float2(0.f, 0.f);
       },
-      [&](int e, float2 v) { buf[(e >> g.kb_log2) * ld + (e & (kb - 1))] = v; });
+      [&](int e, float2 v) { buf[(e >> g.kby_log2) * ld + (e & (kb - 1))] = v; });
   __syncthreads();
-  lds_fft<-1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
+  lds_fft<-1, 16>(buf, ax, g.kby_log2 - 2, ld, tw, tid);
   __syncthreads();
-  float2 *dst = reinterpret_cast<float2 *>(w.s2) + plane * g.NY * g.KZP;
+  float2 *dst = reinterpret_cast<float2 *>(w.s2);
   for (int e = tid; e < g.NY * kb; e += PSWF_THREADS) {
-    const int iy = e >> g.kb_log2, col = e & (kb - 1);
-    if (col >= ncol) continue;
+    const int iy = e >> g.kby_log2, col = e & (kb - 1);
+    if (!col_ok(col)) continue;
     const int my = iy <= g.FY ? iy : My - g.NY + iy;
-    dst[int64_t(iy) * g.KZP + kz0 + col] = buf[my * ld + col];
+    dst[col_off(col, g.NY) + int64_t(iy) * g.KZP] = buf[my * ld + col];
   }
 }
 
@@ -1411,39 +1418,45 @@ __device__ __forceinline__ void yinv_reg(const Geo &g, const Tables &t, const Wo
 // inverse y: kept rows (zero elsewhere and for columns the x pass skipped)
 __device__ __forceinline__ void yinv_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int bx, int by) {
   extern __shared__ float smem[];
-  const int kb = g.kb, ld = kb + 1, My = g.M[1];
+  const int kb = g.kby, ld = kb + 1, My = g.M[1];
   float2 *buf = reinterpret_cast<float2 *>(smem);
   float2 *tw = buf + My * ld;
   const int tid = threadIdx.x;
-  const int kz0 = bx * kb;
-  const int64_t plane = by;
-  const int ncol = min(kb, g.KZ - kz0);
+  const int kz0 = bx * g.kzq;
+  const int64_t plane0 = int64_t(by) * g.ypl;
+  const int64_t nplane = int64_t(g.C) * g.M[0];
+  auto col_ok = [&](int j) {
+    return kz0 + (j & (g.kzq - 1)) < g.KZ && plane0 + (j >> g.kzq_log2) < nplane;
+  };
+  auto col_off = [&](int j, int64_t rows) {
+    return (plane0 + (j >> g.kzq_log2)) * rows * g.KZP + kz0 + (j & (g.kzq - 1));
+  };
   for (int e = tid; e < My; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_y)[e];
   // rows |f_y| > FY are zero; the kept rows are all loaded below
   const int ngap = My - g.NY;
   for (int e = tid; e < ngap * kb; e += PSWF_THREADS)
-    buf[(g.FY + 1 + (e >> g.kb_log2)) * ld + (e & (kb - 1))] = make_float2(0.f, 0.f);
-  const float2 *src = reinterpret_cast<const float2 *>(w.s2) + plane * g.NY * g.KZP;
+    buf[(g.FY + 1 + (e >> g.kby_log2)) * ld + (e & (kb - 1))] = make_float2(0.f, 0.f);
+  const float2 *src = reinterpret_cast<const float2 *>(w.s2);
   // the loads do not wait for the column limits: columns the x pass skipped
   // (k_z >= blim) still hold forward data and are masked after the load
   staged16(
       g.NY * kb,
       [&](int e) {
-        const int iy = e >> g.kb_log2, col = e & (kb - 1);
-        return col < ncol ? src[int64_t(iy) * g.KZP + kz0 + col] : make_float2(0.f, 0.f);
+        const int iy = e >> g.kby_log2, col = e & (kb - 1);
+        return col_ok(col) ? src[col_off(col, g.NY) + int64_t(iy) * g.KZP] : make_float2(0.f, 0.f);
       },
       [&](int e, float2 v) {
-        const int iy = e >> g.kb_log2, col = e & (kb - 1);
+        const int iy = e >> g.kby_log2, col = e & (kb - 1);
         const int my = iy <= g.FY ? iy : My - g.NY + iy;
-        buf[my * ld + col] = kz0 + col < t.blim[iy] ? v : make_float2(0.f, 0.f);
+        buf[my * ld + col] = kz0 + (col & (g.kzq - 1)) < t.blim[iy] ? v : make_float2(0.f, 0.f);
       });
   __syncthreads();
-  lds_fft<1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
+  lds_fft<1, 16>(buf, ax, g.kby_log2 - 2, ld, tw, tid);
   __syncthreads();
-  float2 *dst = reinterpret_cast<float2 *>(w.s1) + plane * My * g.KZP;
+  float2 *dst = reinterpret_cast<float2 *>(w.s1);
   for (int e = tid; e < My * kb; e += PSWF_THREADS) {
-    const int y = e >> g.kb_log2, col = e & (kb - 1);
-    if (col < ncol) dst[int64_t(y) * g.KZP + kz0 + col] = buf[y * ld + col];
+    const int y = e >> g.kby_log2, col = e & (kb - 1);
+    if (col_ok(col)) dst[col_off(col, My) + int64_t(y) * g.KZP] = buf[y * ld + col];
   }
 }
 
@@ -1913,7 +1926,10 @@ size_t zpass_lds_bytes(const Geo &g) {
   if (zreg_ok(g)) return (size_t(32) * kZregLine + 2 * g.Nz + 1) * 8;
   return (size_t(g.Nz) * (g.zlines + 1) + 2 * g.Nz + 1) * 8;
 }
-size_t ypass_lds_bytes(const Geo &g) { return (size_t(g.M[1]) * (g.kb + 1) + g.M[1]) * 8; }
+size_t ypass_lds_bytes(const Geo &g) {
+  const int kb = std::max(g.kb, g.kby);
+  return (size_t(g.M[1]) * (kb + 1) + g.M[1]) * 8;
+}
 size_t xpass_lds_bytes(const Geo &g) {
   return (size_t(g.M[0]) * (g.kb + 1) + g.M[0] + 1) * 8 + 2 * kKerCoef * 4;
 }
@@ -2023,7 +2039,9 @@ hipError_t launch_zfwd(const Geo &g, const Tables &t, const FftAxis &az, const W
 }
 
 hipError_t launch_yfwd(const Geo &g, const Tables &t, const FftAxis &ay, const Work &w, hipStream_t st) {
-  hipLaunchKernelGGL(yreg_ok(g) ? k_yfwd<true> : k_yfwd<false>, dim3(nblocks(g.KZ, g.kb), g.C * g.M[0]), dim3(PSWF_THREADS), ypass_lds_bytes(g),
+  const dim3 grid = yreg_ok(g) ? dim3(nblocks(g.KZ, g.kb), g.C * g.M[0])
+                               : dim3(nblocks(g.KZ, g.kzq), nblocks(int64_t(g.C) * g.M[0], g.ypl));
+  hipLaunchKernelGGL(yreg_ok(g) ? k_yfwd<true> : k_yfwd<false>, grid, dim3(PSWF_THREADS), ypass_lds_bytes(g),
                      st, g, t, ay, w);
   LAUNCH_CHECK();
   return hipSuccess;
@@ -2039,7 +2057,9 @@ hipError_t launch_xmul(const Geo &g, const Tables &t, const FftAxis &ax, const W
 }
 
 hipError_t launch_yinv(const Geo &g, const Tables &t, const FftAxis &ay, const Work &w, hipStream_t st) {
-  hipLaunchKernelGGL(yreg_ok(g) ? k_yinv<true> : k_yinv<false>, dim3(nblocks(g.KZ, g.kb), g.C * g.M[0]), dim3(PSWF_THREADS), ypass_lds_bytes(g),
+  const dim3 grid = yreg_ok(g) ? dim3(nblocks(g.KZ, g.kb), g.C * g.M[0])
+                               : dim3(nblocks(g.KZ, g.kzq), nblocks(int64_t(g.C) * g.M[0], g.ypl));
+  hipLaunchKernelGGL(yreg_ok(g) ? k_yinv<true> : k_yinv<false>, grid, dim3(PSWF_THREADS), ypass_lds_bytes(g),
                      st, g, t, ay, w);
   LAUNCH_CHECK();
   return hipSuccess;
@@ -2143,14 +2163,14 @@ __global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather
     }
     case kBsZfwd: zfwd_body(g, it.t, it.az, it.w, it.nlines, vb); break;
     case kBsYfwd: {
-      const int gx = (g.KZ + g.kb - 1) / g.kb;
+      const int gx = (g.KZ + g.kzq - 1) / g.kzq;
       yfwd_body(g, it.t, it.ay, it.w, vb % gx, vb / gx);
       break;
     }
     case kBsXmul: xmul_body(g, it.t, it.ax, it.w, mode, nullptr, vb % g.nxblk, vb / g.nxblk); break;
     case kBsFinalize: finalize_body(g, it.t, it.w, it.energy, it.virial); break;
     case kBsYinv: {
-      const int gx = (g.KZ + g.kb - 1) / g.kb;
+      const int gx = (g.KZ + g.kzq - 1) / g.kzq;
       yinv_body(g, it.t, it.ay, it.w, vb % gx, vb / gx);
       break;
     }
@@ -2190,9 +2210,9 @@ int batch_stage_blocks(const BatchItem &it, int stage, bool adjoint) {
     case kBsQsum: return it.qblocks * g.C;
     case kBsSpread: return g.ncell;
     case kBsZfwd: return int(nblocks(it.nlines, g.zlines));
-    case kBsYfwd: return int(nblocks(g.KZ, g.kb)) * g.C * g.M[0];
+    case kBsYfwd: return int(nblocks(g.KZ, g.kzq)) * int(nblocks(int64_t(g.C) * g.M[0], g.ypl));
     case kBsXmul: return g.nxblk * g.C;
-    case kBsYinv: return adjoint ? int(nblocks(g.KZ, g.kb)) * g.C * g.M[0] : 0;
+    case kBsYinv: return adjoint ? int(nblocks(g.KZ, g.kzq)) * int(nblocks(int64_t(g.C) * g.M[0], g.ypl)) : 0;
     case kBsZinv: return adjoint ? int(nblocks(it.nlines, g.zlines)) : 0;
     case kBsGather: return (adjoint && N > 0) ? g.ncell : 0;
   }

@@ -261,6 +261,25 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
     const int al = std::max(g.kb, 8);
     g.KZP = (g.KZ + al - 1) / al * al;
   }
+  // generic y passes: when a plane has few k_z columns, a block takes
+  // several planes so it still holds up to 4096 elements
+  g.kby = std::max(1, std::min(64, floor_pow2(4096 / M[1])));
+  {
+    int q = 1;
+    while (q < g.KZ) q <<= 1;
+    if (q <= g.kby / 2) {
+      g.kzq = q;
+      g.ypl = g.kby / q;
+    } else {
+      g.kby = g.kb;
+      g.kzq = g.kb;
+      g.ypl = 1;
+    }
+  }
+  g.kby_log2 = 0;
+  while ((1 << g.kby_log2) < g.kby) ++g.kby_log2;
+  g.kzq_log2 = 0;
+  while ((1 << g.kzq_log2) < g.kzq) ++g.kzq_log2;
   g.zlines = std::max(1, floor_pow2(4096 / g.Nz));
   g.div_nz = make_fastdiv(g.Nz);
   g.div_kz = make_fastdiv(g.KZ);
