@@ -84,6 +84,9 @@ struct Geo {
   // kzq k_z columns each (kzq a power of two >= KZ when planes are packed,
   // else kzq = kby and ypl = 1); the 256-point register path uses kb
   int kby, kby_log2, kzq, kzq_log2, ypl;
+  // generic fused x pass: blocks of kbx columns, made of whole runs of k_z
+  // columns of one k_y row each (several rows per block on small grids)
+  int kbx, kbx_log2;
   FastDiv div_nz;         // by Nz
   FastDiv div_kz;         // by KZ
   FastDiv div_gez;        // by the gather halo's z extent B_z + P - 1
@@ -103,7 +106,8 @@ struct Tables {
   const float *kf;        // [C][kKerCoef]
   const float *kg;        // [C][kKerCoef]
   const KChan *kch;       // [C]
-  const int *xblk;        // [nxblk][4]: iy, kz0, ncols, 0
+  const int *xblk;        // runs [nrun][4]: iy, kz0, ncols, first column in the block
+  const int *xgrp;        // [nxblk + 1]: first run of each x-pass block
   const int *blim;        // [NY] z columns processed by the x pass per iy
   const double *self_coef;  // [C] E_self = self_coef * sum q^2
   const double *zero_V;     // [C] E_0 = zero_V / V * Q_net^2

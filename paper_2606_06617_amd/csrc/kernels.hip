@@ -1191,7 +1191,8 @@ __device__ __forceinline__ void xmul_reg(const Geo &g, const Tables &t, const Wo
   __shared__ double red[7][PSWF_THREADS / 64];
   const int tid = threadIdx.x, col = tid & 15, j = tid >> 4;
   const int blk = bx, c = by;
-  const int iy = t.xblk[4 * blk], kz0 = t.xblk[4 * blk + 1], ncol = t.xblk[4 * blk + 2];
+  const int run = t.xgrp[blk];  // one run per block on this path
+  const int iy = t.xblk[4 * run], kz0 = t.xblk[4 * run + 1], ncol = t.xblk[4 * run + 2];
   const bool on = col < ncol;
   const int64_t xstride = int64_t(g.NY) * g.KZP;
   float2 *col0 = reinterpret_cast<float2 *>(w.s2) + int64_t(c) * 256 * xstride + int64_t(iy) * g.KZP + kz0 + col;
@@ -1280,62 +1281,73 @@ __device__ __forceinline__ void xmul_reg(const Geo &g, const Tables &t, const Wo
 // grad[c] folded into the kernel.
 __device__ __forceinline__ void xmul_body(const Geo &g, const Tables &t, const FftAxis &ax, const Work &w, int mode, const double *__restrict__ grad, int bx, int by) {
   extern __shared__ float smem[];
-  const int kb = g.kb, ld = kb + 1, Mx = g.M[0];
+  const int kb = g.kbx, ld = kb + 1, Mx = g.M[0];
   float2 *buf = reinterpret_cast<float2 *>(smem);
   float2 *tw = buf + Mx * ld;
   float *fc = reinterpret_cast<float *>(tw + Mx + ((Mx * ld + Mx) & 1));  // 16-byte aligned
   float *gc = fc + kKerCoef;
   __shared__ double red[7][PSWF_THREADS / 64];
+  __shared__ int ciy[64], ckz[64];  // k_y row and k_z of each column of the block
   const int tid = threadIdx.x;
   const int blk = bx, c = by;
-  const int iy = t.xblk[4 * blk], kz0 = t.xblk[4 * blk + 1], ncol = t.xblk[4 * blk + 2];
+  const int r0 = t.xgrp[blk], r1 = t.xgrp[blk + 1];
+  const int ncol = t.xblk[4 * (r1 - 1) + 3] + t.xblk[4 * (r1 - 1) + 2];
+  for (int r = r0 + tid; r < r1; r += PSWF_THREADS) {
+    const int iy = t.xblk[4 * r], kz0 = t.xblk[4 * r + 1], n = t.xblk[4 * r + 2], o = t.xblk[4 * r + 3];
+    for (int j = 0; j < n; ++j) {
+      ciy[o + j] = iy;
+      ckz[o + j] = kz0 + j;
+    }
+  }
   const KChan kc = t.kch[c];
   for (int e = tid; e < Mx; e += PSWF_THREADS) tw[e] = reinterpret_cast<const float2 *>(t.tw_x)[e];
   for (int e = tid; e < kKerCoef; e += PSWF_THREADS) {
     fc[e] = t.kf[c * kKerCoef + e];
     gc[e] = t.kg[c * kKerCoef + e];
   }
+  __syncthreads();
   const int64_t xstride = int64_t(g.NY) * g.KZP;
-  float2 *col0 = reinterpret_cast<float2 *>(w.s2) + int64_t(c) * Mx * xstride + int64_t(iy) * g.KZP + kz0;
+  float2 *chan0 = reinterpret_cast<float2 *>(w.s2) + int64_t(c) * Mx * xstride;
   staged16(
       Mx * kb,
       [&](int e) {
-        const int x = e >> g.kb_log2, col = e & (kb - 1);
-        return col < ncol ? col0[x * xstride + col] : make_float2(0.f, 0.f);
+        const int x = e >> g.kbx_log2, col = e & (kb - 1);
+        return col < ncol ? chan0[x * xstride + int64_t(ciy[col]) * g.KZP + ckz[col]] : make_float2(0.f, 0.f);
       },
-      [&](int e, float2 v) { buf[(e >> g.kb_log2) * ld + (e & (kb - 1))] = v; });
+      [&](int e, float2 v) { buf[(e >> g.kbx_log2) * ld + (e & (kb - 1))] = v; });
   __syncthreads();
-  lds_fft<-1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
+  lds_fft<-1, 16>(buf, ax, g.kbx_log2 - 2, ld, tw, tid);
   __syncthreads();
 
-  const int fy = iy <= g.FY ? iy : iy - g.NY;
-  const float ky = fy * g.kunit[1];
-  const float dy = t.Dy[iy];
   const float scale = (mode == 2 ? float(grad[c]) : 1.0f) * g.invV;
   float acc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int e = tid; e < Mx * kb; e += PSWF_THREADS) {
-    const int mx = e >> g.kb_log2, col = e & (kb - 1);
-    const int kz = kz0 + col;
-    const int fx = mx <= Mx / 2 ? mx : mx - Mx;
-    const float kx = fx * g.kunit[0], kzv = kz * g.kunit[2];
-    const float k2 = kx * kx + ky * ky + kzv * kzv;
+    const int mx = e >> g.kbx_log2, col = e & (kb - 1);
     float2 v = buf[mx * ld + col];
     float mult = 0.0f;
-    if (col < ncol && k2 > 0.0f && k2 <= g.kc2 && 2 * abs(fx) != Mx) {
-      const float k = sqrtf(k2);
-      const float2 ph = kernel_eval(fc, gc, kc, k * g.kinv);
-      const float D = t.Dx[mx] * dy * t.Dz[kz];
-      const float wz = (kz == 0) ? 1.0f : 2.0f;
-      const float s2 = (v.x * v.x + v.y * v.y) * D * wz;
-      acc[0] += ph.x * s2;
-      const float vd = ph.y * s2;
-      acc[1] += vd * kx * kx;
-      acc[2] += vd * ky * ky;
-      acc[3] += vd * kzv * kzv;
-      acc[4] += vd * kx * ky;
-      acc[5] += vd * kx * kzv;
-      acc[6] += vd * ky * kzv;
-      mult = ph.x * D * scale;
+    if (col < ncol) {
+      const int iy = ciy[col], kz = ckz[col];
+      const int fy = iy <= g.FY ? iy : iy - g.NY;
+      const float ky = fy * g.kunit[1];
+      const int fx = mx <= Mx / 2 ? mx : mx - Mx;
+      const float kx = fx * g.kunit[0], kzv = kz * g.kunit[2];
+      const float k2 = kx * kx + ky * ky + kzv * kzv;
+      if (k2 > 0.0f && k2 <= g.kc2 && 2 * abs(fx) != Mx) {
+        const float k = sqrtf(k2);
+        const float2 ph = kernel_eval(fc, gc, kc, k * g.kinv);
+        const float D = t.Dx[mx] * t.Dy[iy] * t.Dz[kz];
+        const float wz = (kz == 0) ? 1.0f : 2.0f;
+        const float s2 = (v.x * v.x + v.y * v.y) * D * wz;
+        acc[0] += ph.x * s2;
+        const float vd = ph.y * s2;
+        acc[1] += vd * kx * kx;
+        acc[2] += vd * ky * ky;
+        acc[3] += vd * kzv * kzv;
+        acc[4] += vd * kx * ky;
+        acc[5] += vd * kx * kzv;
+        acc[6] += vd * ky * kzv;
+        mult = ph.x * D * scale;
+      }
     }
     buf[mx * ld + col] = cscale(v, mult);
   }
@@ -1349,16 +1361,16 @@ __device__ __forceinline__ void xmul_body(const Geo &g, const Tables &t, const F
   }
   __syncthreads();
   if (tid < 7) {
-    double s = 0.0;
-    for (int k = 0; k < PSWF_THREADS / 64; ++k) s += red[tid][k];
-    w.epart[(int64_t(c) * g.nxblk + blk) * 8 + tid] = s;
+    double sum = 0.0;
+    for (int k = 0; k < PSWF_THREADS / 64; ++k) sum += red[tid][k];
+    w.epart[(int64_t(c) * g.nxblk + blk) * 8 + tid] = sum;
   }
   if (mode == 0) return;
-  lds_fft<1, 16>(buf, ax, g.kb_log2 - 2, ld, tw, tid);
+  lds_fft<1, 16>(buf, ax, g.kbx_log2 - 2, ld, tw, tid);
   __syncthreads();
   for (int e = tid; e < Mx * kb; e += PSWF_THREADS) {
-    const int x = e >> g.kb_log2, col = e & (kb - 1);
-    if (col < ncol) col0[x * xstride + col] = buf[x * ld + col];
+    const int x = e >> g.kbx_log2, col = e & (kb - 1);
+    if (col < ncol) chan0[x * xstride + int64_t(ciy[col]) * g.KZP + ckz[col]] = buf[x * ld + col];
   }
 }
 
@@ -1930,8 +1942,10 @@ size_t ypass_lds_bytes(const Geo &g) {
   const int kb = std::max(g.kb, g.kby);
   return (size_t(g.M[1]) * (kb + 1) + g.M[1]) * 8;
 }
+bool x_register_path(const Geo &g) { return xreg_ok(g); }
 size_t xpass_lds_bytes(const Geo &g) {
-  return (size_t(g.M[0]) * (g.kb + 1) + g.M[0] + 1) * 8 + 2 * kKerCoef * 4;
+  const int kb = std::max(g.kb, g.kbx);
+  return (size_t(g.M[0]) * (kb + 1) + g.M[0] + 1) * 8 + 2 * kKerCoef * 4;
 }
 
 // Dynamic LDS above 64 KiB needs an opt-in per kernel; request it only when

@@ -19,6 +19,7 @@ size_t ypass_lds_bytes(const Geo &g);
 size_t xpass_lds_bytes(const Geo &g);
 int qsum_blocks(const Geo &g);
 int spread_max_channels();   // channels per spreading launch
+bool x_register_path(const Geo &g);  // the fused x pass runs the 256-point register FFT
 bool spread_tile_ok(int bx, int by, int bz);  // tile fits the spreading kernel's blocks and LDS
 int spread_candidate_cells(const int *nc, const int *b, int P);  // cells a tile screens
 int spread_max_cells();

@@ -292,21 +292,35 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   if (!(ok1 && ok2 && ok3)) return fail(PSWFLR_ERR_UNSUPPORTED, "transform length not supported");
   if (g.Nz > 4096 || M[0] > 4096 || M[1] > 4096) return fail(PSWFLR_ERR_UNSUPPORTED, "transform too long");
 
-  // x-pass blocks: for each kept k_y, the k_z prefix inside the ball
-  std::vector<int> xblk, blim(g.NY, 0);
+  // x-pass runs: for each kept k_y, the k_z prefix inside the ball in runs
+  // of at most one block width; blocks take whole runs (the register path:
+  // one run each; the generic path packs short rows of small grids)
+  const bool xreg = x_register_path(g);
+  g.kbx = xreg ? g.kb : std::max(g.kb, std::min(64, floor_pow2(4096 / M[0])));
+  g.kbx_log2 = 0;
+  while ((1 << g.kbx_log2) < g.kbx) ++g.kbx_log2;
+  const int xstep = xreg ? g.kb : g.kbx;
+  std::vector<int> xblk, xgrp, blim(g.NY, 0);
+  int fill = g.kbx;  // columns used in the open block
   for (int iy = 0; iy < g.NY; ++iy) {
     const int fy = iy <= g.FY ? iy : iy - g.NY;
     const double ky = 2 * kPi * fy / p.box[1];
     const double r2 = kc * kc - ky * ky;
     if (r2 < 0) continue;
     const int kzl = std::min(g.KZ - 1, int(std::floor(std::sqrt(r2) * p.box[2] / (2 * kPi))));
-    for (int kz0 = 0; kz0 <= kzl; kz0 += g.kb) {
-      const int ncol = std::min(g.kb, g.KZ - kz0);
-      xblk.insert(xblk.end(), {iy, kz0, ncol, 0});
+    for (int kz0 = 0; kz0 <= kzl; kz0 += xstep) {
+      const int ncol = std::min(xstep, g.KZ - kz0);
+      if (xreg || fill + ncol > g.kbx) {
+        xgrp.push_back(int(xblk.size() / 4));
+        fill = 0;
+      }
+      xblk.insert(xblk.end(), {iy, kz0, ncol, fill});
+      fill += ncol;
       blim[iy] = kz0 + ncol;
     }
   }
-  g.nxblk = int(xblk.size() / 4);
+  g.nxblk = int(xgrp.size());
+  xgrp.push_back(int(xblk.size() / 4));
 
   // ---- tables (host FP64 -> device FP32) ----
   auto wpoly = make_window_poly(cs, kWinSeg, kWinDeg, 1e-9);
@@ -369,6 +383,7 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
          o_kf = put(kf.data(), kf.size() * 4), o_kg = put(kg.data(), kg.size() * 4),
          o_kch = put(kch.data(), kch.size() * sizeof(KChan)),
          o_xb = put(xblk.data(), std::max<size_t>(1, xblk.size()) * 4 * (xblk.empty() ? 0 : 1)),
+         o_xg = put(xgrp.data(), xgrp.size() * 4),
          o_bl = put(blim.data(), blim.size() * 4), o_self = put(selfc.data(), selfc.size() * 8),
          o_zero = put(zerov.data(), zerov.size() * 8);
   blob.resize(align256(blob.size()) + 256);
@@ -390,6 +405,7 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   t.kg = reinterpret_cast<const float *>(b + o_kg);
   t.kch = reinterpret_cast<const KChan *>(b + o_kch);
   t.xblk = reinterpret_cast<const int *>(b + o_xb);
+  t.xgrp = reinterpret_cast<const int *>(b + o_xg);
   t.blim = reinterpret_cast<const int *>(b + o_bl);
   t.self_coef = reinterpret_cast<const double *>(b + o_self);
   t.zero_V = reinterpret_cast<const double *>(b + o_zero);
