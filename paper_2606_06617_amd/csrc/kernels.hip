@@ -2150,31 +2150,7 @@ __global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather
     case kBsOrder: order_body(g, it.w, vb); break;
     case kBsQsum: qsum_body(g, it.w, it.q, kQChunk, vb % it.qblocks, vb / it.qblocks); break;
     case kBsQreduce: qreduce_body(g, it.w, it.qblocks); break;
-    case kBsSpread: {
-      const int nbz = spread_nbz(g.B[2]), cgt = spread_cg_template(g.C);
-#define PSWF_SPREAD_PZ(PP, ZZ)                                                 \
-  if (cgt == 2) spread_body<PP, ZZ, 2>(g, it.t, it.w, 0, g.C, vb);             \
-  else if (cgt == 4) spread_body<PP, ZZ, 4>(g, it.t, it.w, 0, g.C, vb);        \
-  else spread_body<PP, ZZ, kSpreadCGM>(g, it.t, it.w, 0, g.C, vb);
-#define PSWF_SPREAD_P(PP)                                                     \
-  case PP:                                                                     \
-    if (nbz == 4) { PSWF_SPREAD_PZ(PP, 4) }                                   \
-    else if (nbz == 2) { PSWF_SPREAD_PZ(PP, 2) }                              \
-    else { PSWF_SPREAD_PZ(PP, 1) }                                            \
-    break;
-      switch (g.P) {
-        PSWF_SPREAD_P(2)
-        PSWF_SPREAD_P(3)
-        PSWF_SPREAD_P(4)
-        PSWF_SPREAD_P(5)
-        PSWF_SPREAD_P(6)
-        PSWF_SPREAD_P(7)
-        PSWF_SPREAD_P(8)
-      }
-#undef PSWF_SPREAD_P
-#undef PSWF_SPREAD_PZ
-      break;
-    }
+    case kBsSpread: break;  // one launch per kernel variant: k_batch_spread
     case kBsZfwd: zfwd_body(g, it.t, it.az, it.w, it.nlines, vb); break;
     case kBsYfwd: {
       const int gx = (g.KZ + g.kzq - 1) / g.kzq;
@@ -2244,6 +2220,74 @@ size_t batch_stage_lds(const BatchItem &it, int stage) {
   return 0;
 }
 
+// Spreading of a batch: one launch per kernel variant (support, z blocks,
+// channel accumulators) present in the batch, each over every block; a
+// block whose structure has another variant returns at once.  One kernel
+// holding every variant would be large and spill scalar registers.
+template <int P, int NBZ, int CG>
+__global__ __launch_bounds__(kSpreadThreads, 4) void k_batch_spread(const BatchItem *__restrict__ items,
+                                                                     const int *__restrict__ prefix, int n) {
+  const int b = blockIdx.x;
+  const int s = find_item(prefix, n, b);
+  const BatchItem &it = items[s];
+  const Geo &g = it.g;
+  if (g.P != P || spread_nbz(g.B[2]) != NBZ || spread_cg_template(g.C) != CG) return;
+  spread_body<P, NBZ, CG>(g, it.t, it.w, 0, g.C, b - prefix[s]);
+}
+
+template <int P, int NBZ, int CG>
+static hipError_t bspread_launch(const BatchItem *d_items, const int *d_prefix, int n, int total_blocks, size_t lds,
+                                 hipStream_t st) {
+  hipError_t e = lds_request(reinterpret_cast<const void *>(&k_batch_spread<P, NBZ, CG>), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_batch_spread<P, NBZ, CG>), dim3(total_blocks), dim3(kSpreadThreads), lds, st, d_items,
+                     d_prefix, n);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+template <int P, int NBZ>
+static hipError_t bspread_pz(int cgt, const BatchItem *d_items, const int *d_prefix, int n, int total_blocks,
+                             size_t lds, hipStream_t st) {
+  switch (cgt) {
+    case 2: return bspread_launch<P, NBZ, 2>(d_items, d_prefix, n, total_blocks, lds, st);
+    case 4: return bspread_launch<P, NBZ, 4>(d_items, d_prefix, n, total_blocks, lds, st);
+    default: return bspread_launch<P, NBZ, kSpreadCGM>(d_items, d_prefix, n, total_blocks, lds, st);
+  }
+}
+
+template <int P>
+static hipError_t bspread_p(int nbz, int cgt, const BatchItem *d_items, const int *d_prefix, int n,
+                            int total_blocks, size_t lds, hipStream_t st) {
+  switch (nbz) {
+    case 1: return bspread_pz<P, 1>(cgt, d_items, d_prefix, n, total_blocks, lds, st);
+    case 2: return bspread_pz<P, 2>(cgt, d_items, d_prefix, n, total_blocks, lds, st);
+    case 4: return bspread_pz<P, 4>(cgt, d_items, d_prefix, n, total_blocks, lds, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+int batch_spread_variant(const Geo &g) {
+  return g.P * 100 + spread_nbz(g.B[2]) * 10 + (spread_cg_template(g.C) == kSpreadCGM ? 0 : spread_cg_template(g.C));
+}
+
+hipError_t launch_batch_spread(const BatchItem *d_items, const int *d_prefix, int n, int total_blocks, size_t lds,
+                               int variant, hipStream_t st) {
+  if (total_blocks <= 0) return hipSuccess;
+  const int P = variant / 100, nbz = (variant / 10) % 10, cgv = variant % 10;
+  const int cgt = cgv == 0 ? kSpreadCGM : cgv;
+  switch (P) {
+    case 2: return bspread_p<2>(nbz, cgt, d_items, d_prefix, n, total_blocks, lds, st);
+    case 3: return bspread_p<3>(nbz, cgt, d_items, d_prefix, n, total_blocks, lds, st);
+    case 4: return bspread_p<4>(nbz, cgt, d_items, d_prefix, n, total_blocks, lds, st);
+    case 5: return bspread_p<5>(nbz, cgt, d_items, d_prefix, n, total_blocks, lds, st);
+    case 6: return bspread_p<6>(nbz, cgt, d_items, d_prefix, n, total_blocks, lds, st);
+    case 7: return bspread_p<7>(nbz, cgt, d_items, d_prefix, n, total_blocks, lds, st);
+    case 8: return bspread_p<8>(nbz, cgt, d_items, d_prefix, n, total_blocks, lds, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int STAGE>
 static hipError_t launch_stage_t(const BatchItem *d_items, const int *d_prefix, int n, int total_blocks, size_t lds,
                                  int mode, hipStream_t st) {
@@ -2268,7 +2312,7 @@ hipError_t launch_batch_stage(const BatchItem *d_items, const int *d_prefix, int
     case kBsOrder: return launch_stage_t<kBsOrder>(d_items, d_prefix, n, total_blocks, lds, mode, st);
     case kBsQsum: return launch_stage_t<kBsQsum>(d_items, d_prefix, n, total_blocks, lds, mode, st);
     case kBsQreduce: return launch_stage_t<kBsQreduce>(d_items, d_prefix, n, total_blocks, lds, mode, st);
-    case kBsSpread: return launch_stage_t<kBsSpread>(d_items, d_prefix, n, total_blocks, lds, mode, st);
+    case kBsSpread: return hipErrorInvalidValue;  // launch_batch_spread
     case kBsZfwd: return launch_stage_t<kBsZfwd>(d_items, d_prefix, n, total_blocks, lds, mode, st);
     case kBsYfwd: return launch_stage_t<kBsYfwd>(d_items, d_prefix, n, total_blocks, lds, mode, st);
     case kBsXmul: return launch_stage_t<kBsXmul>(d_items, d_prefix, n, total_blocks, lds, mode, st);

@@ -45,5 +45,9 @@ int batch_stage_blocks(const BatchItem &it, int stage, bool adjoint);
 size_t batch_stage_lds(const BatchItem &it, int stage);
 hipError_t launch_batch_stage(const BatchItem *d_items, const int *d_prefix, int n, int stage, int total_blocks,
                               size_t lds, int mode, hipStream_t st);
+// the batch's spreading, one launch per kernel variant (batch_spread_variant)
+int batch_spread_variant(const Geo &g);
+hipError_t launch_batch_spread(const BatchItem *d_items, const int *d_prefix, int n, int total_blocks, size_t lds,
+                               int variant, hipStream_t st);
 
 }  // namespace pswf

@@ -782,6 +782,12 @@ pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const ps
     prefix[stg * (n + 1) + n] = acc;
     total[stg] = acc;
   }
+  std::vector<int> spread_variants;  // kernel variants of the spreading stage present in the batch
+  for (int i = 0; i < n; ++i) {
+    const int v = batch_spread_variant(items[i].g);
+    if (std::find(spread_variants.begin(), spread_variants.end(), v) == spread_variants.end())
+      spread_variants.push_back(v);
+  }
   hipError_t e = hipMemcpyAsync(ws, blob, hdr, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipLaunchHostFunc(st, free_host_blob, blob);
   if (e != hipSuccess) {
@@ -794,7 +800,12 @@ pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const ps
   StageRunner run{plans[0], st};
   for (int stg = 0; stg < kNumBatchStages; ++stg) {
     e = run(stage_profile_id(stg), [&] {
-      return launch_batch_stage(d_items, d_prefix + stg * (n + 1), n, stg, total[stg], lds[stg], 1, st);
+      if (stg != kBsSpread)
+        return launch_batch_stage(d_items, d_prefix + stg * (n + 1), n, stg, total[stg], lds[stg], 1, st);
+      hipError_t r = hipSuccess;
+      for (int v : spread_variants)
+        if (r == hipSuccess) r = launch_batch_spread(d_items, d_prefix + stg * (n + 1), n, total[stg], lds[stg], v, st);
+      return r;
     });
     if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
   }
