@@ -124,23 +124,44 @@ def execute_batch(plans, inputs, forces=True, virial=True, potential=False, work
     _lib.check(L.pswflr_batch_workspace(n, handles, natoms, ctypes.byref(need)))
     dev = inputs[0][0].device if n else torch.device("cuda")
     ws = workspace if workspace is not None else torch.empty(max(1, need.value), dtype=torch.uint8, device=dev)
+    if n == 0:
+        _lib.check(L.pswflr_execute_batch(0, handles, (_lib.IO * 1)(), _stream(stream), _ptr(ws), ws.numel()))
+        return [], ws
+    # outputs live in a few flat tensors (one allocation each, not one per
+    # structure); the per-structure dicts hold views of them
+    Ns = [int(x[0].shape[0]) for x in inputs]
+    Cs = [plan.C for plan in plans]
+    e_all = torch.empty(3 * sum(Cs), dtype=torch.float64, device=dev)
+    f_all = torch.empty((sum(Ns), 3), dtype=torch.float32, device=dev) if forces else None
+    v_all = torch.empty((n, 6), dtype=torch.float64, device=dev) if virial else None
+    p_all = torch.empty(sum(c * m for c, m in zip(Cs, Ns)), dtype=torch.float32, device=dev) if potential else None
+    e_views = torch.split(e_all, [3 * c for c in Cs])
+    f_views = torch.split(f_all, Ns) if forces else [None] * n
+    v_views = v_all.unbind(0) if virial else [None] * n
+    p_views = ([t.view(c, m) for t, c, m in zip(torch.split(p_all, [c * m for c, m in zip(Cs, Ns)]), Cs, Ns)]
+               if potential else [None] * n)
+    e_ptr = e_all.data_ptr()
+    f_ptr = f_all.data_ptr() if forces else 0
+    v_ptr = v_all.data_ptr() if virial else 0
+    p_ptr = p_all.data_ptr() if potential else 0
     ios = (_lib.IO * n)()
     outs = []
+    eo = fo = po = 0
     for i, (plan, (pos, q)) in enumerate(zip(plans, inputs)):
         _check_inputs(pos, q, plan.C, plan.max_atoms)
-        N = pos.shape[0]
-        o = {"energy": torch.empty(3 * plan.C, dtype=torch.float64, device=dev),
-             "forces": torch.empty((N, 3), dtype=torch.float32, device=dev) if forces else None,
-             "virial": torch.empty(6, dtype=torch.float64, device=dev) if virial else None,
-             "potential": torch.empty((plan.C, N), dtype=torch.float32, device=dev) if potential else None}
-        ios[i].n_atoms = N
-        ios[i].pos = pos.data_ptr()
-        ios[i].q = q.data_ptr()
-        ios[i].energy = o["energy"].data_ptr()
-        ios[i].forces = o["forces"].data_ptr() if forces else None
-        ios[i].virial = o["virial"].data_ptr() if virial else None
-        ios[i].potential = o["potential"].data_ptr() if potential else None
-        outs.append(o)
+        N, C = Ns[i], Cs[i]
+        io = ios[i]
+        io.n_atoms = N
+        io.pos = pos.data_ptr()
+        io.q = q.data_ptr()
+        io.energy = e_ptr + 8 * eo
+        io.forces = f_ptr + 12 * fo if forces else None
+        io.virial = v_ptr + 48 * i if virial else None
+        io.potential = p_ptr + 4 * po if potential else None
+        eo += 3 * C
+        fo += N
+        po += C * N
+        outs.append({"energy": e_views[i], "forces": f_views[i], "virial": v_views[i], "potential": p_views[i]})
     _lib.check(L.pswflr_execute_batch(n, handles, ios, _stream(stream), _ptr(ws), ws.numel()))
     return outs, ws
 
