@@ -693,7 +693,44 @@ int stage_profile_id(int bs) {
   }
 }
 
-void free_host_blob(void *p) { delete[] static_cast<char *>(p); }
+// Pinned staging for batch headers, one per host thread and reused across
+// calls: the upload is then a plain DMA with no host callback on the stream.
+// An event recorded after each upload keeps the next call from overwriting
+// the buffer before the copy has run.  Kept for the life of the process.
+struct HeaderStage {
+  char *buf = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  int device = -1;
+};
+thread_local HeaderStage g_header;
+
+hipError_t header_buffer(size_t bytes, char **out) {
+  HeaderStage &h = g_header;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (h.ev) {
+    e = hipEventSynchronize(h.ev);  // the previous upload from this buffer has run
+    if (e != hipSuccess) return e;
+  }
+  if (h.device != dev) {
+    h.ev = nullptr;  // an event of another device is left as is
+    e = hipEventCreateWithFlags(&h.ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    h.device = dev;
+  }
+  if (h.cap < bytes) {
+    if (h.buf) (void)hipHostFree(h.buf);
+    h.buf = nullptr;
+    h.cap = 0;
+    e = hipHostMalloc(reinterpret_cast<void **>(&h.buf), bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    h.cap = bytes;
+  }
+  *out = h.buf;
+  return hipSuccess;
+}
 
 }  // namespace
 
@@ -744,7 +781,9 @@ pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const ps
     return PSWFLR_OK;
   }
   // host image of the header: items, then per-stage prefixes
-  char *blob = new char[hdr]();
+  char *blob = nullptr;
+  if (header_buffer(hdr, &blob) != hipSuccess) return fail(PSWFLR_ERR_DEVICE, "batch header staging failed");
+  std::memset(blob, 0, hdr);
   BatchItem *items = reinterpret_cast<BatchItem *>(blob);
   int *prefix = reinterpret_cast<int *>(blob + align256(size_t(n) * sizeof(BatchItem)));
   std::vector<bool> adj(n);
@@ -789,12 +828,9 @@ pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const ps
       spread_variants.push_back(v);
   }
   hipError_t e = hipMemcpyAsync(ws, blob, hdr, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipLaunchHostFunc(st, free_host_blob, blob);
-  if (e != hipSuccess) {
-    (void)hipStreamSynchronize(st);
-    delete[] blob;
+  if (e == hipSuccess) e = hipEventRecord(g_header.ev, st);
+  if (e != hipSuccess)
     return fail(PSWFLR_ERR_DEVICE, std::string("batch header upload failed: ") + hipGetErrorString(e));
-  }
   const BatchItem *d_items = reinterpret_cast<const BatchItem *>(ws);
   const int *d_prefix = reinterpret_cast<const int *>(ws + align256(size_t(n) * sizeof(BatchItem)));
   StageRunner run{plans[0], st};
