@@ -119,8 +119,11 @@ pswflr_status pswflr_plan_create(const pswflr_params *params, int64_t max_atoms,
 /* Copy the resolved parameters and sizes into *out. */
 pswflr_status pswflr_plan_info(pswflr_plan plan, pswflr_info *out);
 
-/* Release the plan's device table.  The caller must ensure no enqueued work
- * still uses the plan. */
+/* Release the plan.  Its device table goes back to a per-process pool (no
+ * device-wide wait) and is handed to a later plan only after the event
+ * recorded at the end of this plan's last call has completed; a plan used
+ * on several streams at once must have those streams synchronised by the
+ * caller first. */
 pswflr_status pswflr_plan_destroy(pswflr_plan plan);
 
 /* One evaluation (the whole hot path) on `stream`.

@@ -589,8 +589,11 @@ double choose_c_spread(int P, double eta, double c_moll) {
       cache[key] = v[j];
     }
   }
+  // rounded to 0.05 (well inside the flat minimum): boxes of nearby eta then
+  // share one window bandwidth, so the window polynomial built for it is
+  // reused from its cache instead of refitted per box
   const double f = u - double(i0);
-  return std::round(((1.0 - f) * v[0] + f * v[1]) * 1e3) / 1e3;
+  return std::round(((1.0 - f) * v[0] + f * v[1]) * 20.0) / 20.0;
 }
 
 bool is_smooth235(int m) {

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <map>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -30,6 +31,70 @@ namespace {
 
 const double kPi = 3.14159265358979323846264338327950288;
 thread_local std::string g_last_error;
+
+// Plan tables come from a per-process pool of device blocks: a destroyed
+// plan's block is kept for the next plan instead of being freed, because
+// hipFree waits for the whole device and would stall every stream in
+// flight (a serving loop retires plans while other requests run).  The
+// pool holds at most what the peak number of live plans used.
+std::mutex g_table_mu;
+// A released block carries the event recorded after its plan's last call;
+// it is handed out again only once that event has completed.  Events are one
+// per stream, kept for the life of the process and re-recorded by every
+// call on that stream: a later record only makes the wait longer, never
+// shorter, since work on one stream completes in order.
+std::mutex g_event_mu;
+std::map<void *, hipEvent_t> g_stream_events;
+
+hipError_t stream_event(hipStream_t st, hipEvent_t *out) {
+  std::lock_guard<std::mutex> lock(g_event_mu);
+  auto it = g_stream_events.find(static_cast<void *>(st));
+  if (it != g_stream_events.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  hipEvent_t ev = nullptr;
+  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
+  g_stream_events.emplace(static_cast<void *>(st), ev);
+  *out = ev;
+  return hipSuccess;
+}
+
+struct PooledTable {
+  int device;
+  void *block;
+  hipEvent_t done;
+};
+std::multimap<size_t, PooledTable> g_table_pool;  // capacity -> block
+
+hipError_t table_alloc(size_t bytes, int device, void **out, size_t *cap) {
+  PooledTable got{-1, nullptr, nullptr};
+  {
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    for (auto it = g_table_pool.lower_bound(bytes); it != g_table_pool.end() && it->first <= 4 * bytes + 65536; ++it) {
+      if (it->second.device != device) continue;
+      got = it->second;
+      *cap = it->first;
+      g_table_pool.erase(it);
+      break;
+    }
+  }
+  if (got.block) {
+    // the last call of the plan that held it has run
+    const hipError_t e = got.done ? hipEventSynchronize(got.done) : hipSuccess;
+    *out = got.block;
+    return e;
+  }
+  *cap = bytes;
+  return hipMalloc(out, bytes);
+}
+
+void table_release(void *p, size_t cap, int device, hipEvent_t done) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lock(g_table_mu);
+  g_table_pool.emplace(cap, PooledTable{device, p, done});
+}
 
 pswflr_status fail(pswflr_status s, const std::string &msg) {
   g_last_error = msg;
@@ -87,6 +152,8 @@ struct pswflr_plan_s {
   FftAxis az, ay, ax;
   Tables tab{};
   void *dtab = nullptr;
+  size_t dtab_bytes = 0;  // capacity of the block dtab points to
+  hipEvent_t last_use = nullptr;  // the stream event recorded after its last call (not owned)
   int device = 0;
   // workspace layout for max_atoms
   int64_t max_atoms = 0;
@@ -388,9 +455,13 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
          o_zero = put(zerov.data(), zerov.size() * 8);
   blob.resize(align256(blob.size()) + 256);
   if (hipGetDevice(&pl.device) != hipSuccess) return fail(PSWFLR_ERR_DEVICE, "hipGetDevice failed");
-  if (hipMalloc(&pl.dtab, blob.size()) != hipSuccess) return fail(PSWFLR_ERR_OOM, "table allocation failed");
+  if (table_alloc(blob.size(), pl.device, &pl.dtab, &pl.dtab_bytes) != hipSuccess) {
+    pl.dtab = nullptr;
+    return fail(PSWFLR_ERR_OOM, "table allocation failed");
+  }
   if (hipMemcpy(pl.dtab, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess)
     return fail(PSWFLR_ERR_DEVICE, "table upload failed");
+
   char *b = static_cast<char *>(pl.dtab);
   Tables &t = pl.tab;
   t.tw_z = reinterpret_cast<const float *>(b + o_twz);
@@ -521,12 +592,12 @@ pswflr_status pswflr_plan_create(const pswflr_params *params, int64_t max_atoms,
     pl = new pswflr_plan_s();
     pswflr_status s = build_plan(*params, max_atoms, *pl);
     if (s != PSWFLR_OK) {
-      if (pl->dtab) (void)hipFree(pl->dtab);
+      table_release(pl->dtab, pl->dtab_bytes, pl->device, pl->last_use);
       delete pl;
       return s;
     }
   } catch (const std::exception &e) {
-    if (pl && pl->dtab) (void)hipFree(pl->dtab);
+    if (pl) table_release(pl->dtab, pl->dtab_bytes, pl->device, pl->last_use);
     delete pl;
     return fail(PSWFLR_ERR_INTERNAL, e.what());
   }
@@ -542,7 +613,7 @@ pswflr_status pswflr_plan_info(pswflr_plan plan, pswflr_info *out) {
 
 pswflr_status pswflr_plan_destroy(pswflr_plan plan) {
   if (!plan) return PSWFLR_OK;
-  if (plan->dtab) (void)hipFree(plan->dtab);
+  table_release(plan->dtab, plan->dtab_bytes, plan->device, plan->last_use);
   delete plan;
   return PSWFLR_OK;
 }
@@ -607,6 +678,18 @@ hipError_t run_adjoint(pswflr_plan_s *pl, hipStream_t st, const Geo &g, const Wo
 
 }  // namespace
 
+namespace {
+// record the end of a call on `st` for the plans it used
+hipError_t mark_use(hipStream_t st, const pswflr_plan *plans, int n) {
+  hipEvent_t ev = nullptr;
+  hipError_t e = stream_event(st, &ev);
+  if (e == hipSuccess) e = hipEventRecord(ev, st);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < n; ++i) plans[i]->last_use = ev;
+  return hipSuccess;
+}
+}  // namespace
+
 extern "C" {
 
 pswflr_status pswflr_execute(pswflr_plan plan, pswflr_stream stream, void *workspace, size_t ws_bytes,
@@ -622,6 +705,7 @@ pswflr_status pswflr_execute(pswflr_plan plan, pswflr_stream stream, void *works
   const bool adjoint = forces || potential;
   hipError_t e = run_forward(plan, st, g, w, pos, q, adjoint ? 1 : 0, energy, virial);
   if (e == hipSuccess && adjoint) e = run_adjoint(plan, st, g, w, forces, potential, 1, nullptr);
+  if (e == hipSuccess) e = mark_use(st, &plan, 1);
   if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return PSWFLR_OK;
 }
@@ -638,6 +722,7 @@ pswflr_status pswflr_backward(pswflr_plan plan, pswflr_stream stream, void *work
   g.N = n_atoms;
   Work w = carve(*plan, workspace, n_atoms);
   hipError_t e = run_adjoint(plan, st, g, w, grad_pos, grad_q, 2, grad_energy);
+  if (e == hipSuccess) e = mark_use(st, &plan, 1);
   if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return PSWFLR_OK;
 }
@@ -845,6 +930,8 @@ pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const ps
     });
     if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
   }
+  if ((e = mark_use(st, plans, n)) != hipSuccess)
+    return fail(PSWFLR_ERR_DEVICE, std::string("event record failed: ") + hipGetErrorString(e));
   return PSWFLR_OK;
 }
 
