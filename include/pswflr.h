@@ -120,10 +120,10 @@ pswflr_status pswflr_plan_create(const pswflr_params *params, int64_t max_atoms,
 pswflr_status pswflr_plan_info(pswflr_plan plan, pswflr_info *out);
 
 /* Release the plan.  Its device table goes back to a per-process pool (no
- * device-wide wait) and is handed to a later plan only after the event
+ * device-wide wait) and is handed to a later plan only once the event
  * recorded at the end of this plan's last call has completed; a plan used
  * on several streams at once must have those streams synchronised by the
- * caller first. */
+ * caller first.  Never blocks. */
 pswflr_status pswflr_plan_destroy(pswflr_plan plan);
 
 /* One evaluation (the whole hot path) on `stream`.

@@ -39,7 +39,8 @@ thread_local std::string g_last_error;
 // pool holds at most what the peak number of live plans used.
 std::mutex g_table_mu;
 // A released block carries the event recorded after its plan's last call;
-// it is handed out again only once that event has completed.  Events are one
+// it is handed out again only once that event has completed (otherwise a
+// new block is allocated: no call ever waits here).  Events are one
 // per stream, kept for the life of the process and re-recorded by every
 // call on that stream: a later record only makes the wait longer, never
 // shorter, since work on one stream completes in order.
@@ -74,6 +75,9 @@ hipError_t table_alloc(size_t bytes, int device, void **out, size_t *cap) {
     std::lock_guard<std::mutex> lock(g_table_mu);
     for (auto it = g_table_pool.lower_bound(bytes); it != g_table_pool.end() && it->first <= 4 * bytes + 65536; ++it) {
       if (it->second.device != device) continue;
+      // only a block whose last use has completed: never wait here (the
+      // stream's event may stand for newer work queued behind it)
+      if (it->second.done && hipEventQuery(it->second.done) != hipSuccess) continue;
       got = it->second;
       *cap = it->first;
       g_table_pool.erase(it);
@@ -81,10 +85,8 @@ hipError_t table_alloc(size_t bytes, int device, void **out, size_t *cap) {
     }
   }
   if (got.block) {
-    // the last call of the plan that held it has run
-    const hipError_t e = got.done ? hipEventSynchronize(got.done) : hipSuccess;
     *out = got.block;
-    return e;
+    return hipSuccess;
   }
   *cap = bytes;
   return hipMalloc(out, bytes);

@@ -20,6 +20,7 @@ admission logic is exercised on the CPU with a simulated executor
 import collections
 import concurrent.futures
 import dataclasses
+import gc
 import time
 from typing import Any, Optional
 
@@ -62,6 +63,21 @@ class HipExecutor:
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
         self.r_c, self.c, self.tol, self.support = r_c, c, tol, support
+        # per-slot pinned staging, grown geometrically and reused: a slot
+        # takes a new request only after the previous one's copies are done,
+        # and no request pays a pinned allocation
+        self._pinned = [dict() for _ in range(slots)]
+
+    def _stage(self, slot, name, shape, dtype):
+        n = 1
+        for d in shape:
+            n *= d
+        buf = self._pinned[slot].get(name)
+        if buf is None or buf.numel() < n:
+            size = max(n, 2 * buf.numel() if buf is not None else 0, 1)
+            buf = self.torch.empty(size, dtype=dtype, pin_memory=True)
+            self._pinned[slot][name] = buf
+        return buf[:n].view(*shape)
 
     @property
     def slots(self):
@@ -85,14 +101,16 @@ class HipExecutor:
         st = self.streams[slot]
         N, C = req.n_atoms, len(req.ps)
         with torch.cuda.stream(st):
-            pos_h = torch.from_numpy(req.pos).pin_memory()
-            q_h = torch.from_numpy(req.q).pin_memory()
+            pos_h = self._stage(slot, "pos", (N, 3), torch.float32)
+            q_h = self._stage(slot, "q", (C, N), torch.float32)
+            pos_h.copy_(torch.from_numpy(req.pos))
+            q_h.copy_(torch.from_numpy(req.q))
             pos = pos_h.to(self.device, non_blocking=True)
             q = q_h.to(self.device, non_blocking=True)
             out = plan.execute(pos, q, forces=True, virial=True, stream=st)
-            e_h = torch.empty(3 * C, dtype=torch.float64, pin_memory=True)
-            f_h = torch.empty((N, 3), dtype=torch.float32, pin_memory=True)
-            w_h = torch.empty(6, dtype=torch.float64, pin_memory=True)
+            e_h = self._stage(slot, "energy", (3 * C,), torch.float64)
+            f_h = self._stage(slot, "forces", (N, 3), torch.float32)
+            w_h = self._stage(slot, "virial", (6,), torch.float64)
             e_h.copy_(out["energy"], non_blocking=True)
             f_h.copy_(out["forces"], non_blocking=True)
             w_h.copy_(out["virial"], non_blocking=True)
@@ -206,18 +224,27 @@ class Server:
         """Replay requests at their t_arrival offsets; return them when all
         have completed."""
         order = sorted(reqs, key=lambda r: r.t_arrival)
-        self.t0 = self.clock()
-        i = 0
-        while i < len(order) or self.busy():
-            now = self.now()
-            while i < len(order) and (not realtime or order[i].t_arrival <= now):
-                if not realtime:
-                    order[i].t_arrival = now
-                self.submit(order[i])
-                i += 1
-            self.poll()
-            if poll_sleep:
-                time.sleep(poll_sleep)
+        # the cyclic garbage collector can pause the loop for tens of ms in
+        # the middle of a trace; it runs before and after instead
+        gc_on = gc.isenabled()
+        gc.collect()
+        gc.disable()
+        try:
+            self.t0 = self.clock()
+            i = 0
+            while i < len(order) or self.busy():
+                now = self.now()
+                while i < len(order) and (not realtime or order[i].t_arrival <= now):
+                    if not realtime:
+                        order[i].t_arrival = now
+                    self.submit(order[i])
+                    i += 1
+                self.poll()
+                if poll_sleep:
+                    time.sleep(poll_sleep)
+        finally:
+            if gc_on:
+                gc.enable()
         return order
 
     def close(self):
