@@ -87,6 +87,7 @@ struct Geo {
   // generic fused x pass: blocks of kbx columns, made of whole runs of k_z
   // columns of one k_y row each (several rows per block on small grids)
   int kbx, kbx_log2;
+  int srec;               // floats per staged atom record: 4 + C rounded up to 4
   FastDiv div_nz;         // by Nz
   FastDiv div_kz;         // by KZ
   FastDiv div_gez;        // by the gather halo's z extent B_z + P - 1
@@ -118,8 +119,9 @@ struct Work {
   float *grid;            // [C][Mx][My][Mz]
   float *s1;              // [C][Mx][My][KZP] complex
   float *s2;              // [C][Mx][NY][KZP] complex
-  float *rec_a, *rec_b;   // [N][4]: delta_x, delta_y, delta_z, packed n0 bits
-  float *q_a, *q_b;       // [C][N] in cell order
+  float *rec_a;           // [N][4] in cell order: delta_x, delta_y, delta_z, packed n0 bits
+  float *q_a;             // [C][N] in cell order
+  float *q_b;             // the sort's staging: [N][srec] records in caller order
   int *perm_a, *perm_b;   // cell order -> caller order
   int *cell_of, *slot;    // [N]
   int *cell_count;        // [ncell]

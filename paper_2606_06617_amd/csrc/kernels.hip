@@ -344,14 +344,15 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zero_int(int *p, int n) { zero
 
 __device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const float *__restrict__ pos,
                                          const float *__restrict__ q, int bx) {
-  // charges staged atom-major, [N][C], so that the reorder reads one
-  // contiguous row per atom instead of C scattered words; consecutive
-  // threads write consecutive words of the block's rows
+  // atoms staged in caller order as records of g.srec floats: window
+  // offsets and packed start, then the C charges (padded to a multiple of
+  // four), so the reorder reads one aligned record per atom; consecutive
+  // threads write consecutive charge words of the block's records
   const int64_t b0 = int64_t(bx) * PSWF_THREADS;
   const int nrow = g.N - b0 < PSWF_THREADS ? int(g.N - b0) : PSWF_THREADS;
   for (int f = threadIdx.x; f < nrow * g.C; f += PSWF_THREADS) {
     const int a = f / g.C, ch = f - a * g.C;
-    w.q_b[b0 * g.C + f] = q[int64_t(ch) * g.N + b0 + a];
+    w.q_b[(b0 + a) * g.srec + 4 + ch] = q[int64_t(ch) * g.N + b0 + a];
   }
   const int64_t i = b0 + threadIdx.x;
   if (i >= g.N) return;
@@ -379,7 +380,7 @@ __device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const floa
   w.cell_of[i] = c;
   w.slot[i] = atomicAdd(&w.cell_count[c], 1);
   float4 r = make_float4(dl[0], dl[1], dl[2], __uint_as_float(packed));
-  reinterpret_cast<float4 *>(w.rec_b)[i] = r;  // staged in caller order
+  *reinterpret_cast<float4 *>(w.q_b + i * g.srec) = r;
 }
 
 __global__ __launch_bounds__(PSWF_THREADS) void k_bin(Geo g, Work w, const float *__restrict__ pos,
@@ -442,10 +443,16 @@ __device__ __forceinline__ void order_body(const Geo &g, const Work &w, int bx) 
     int rank = 0;
     for (int m = 0; m < n; ++m) rank += (in_lds ? keys[m] : w.perm_b[s + m]) < key;
     const int dst = s + rank;
-    reinterpret_cast<float4 *>(w.rec_a)[dst] = reinterpret_cast<const float4 *>(w.rec_b)[key];
+    const float4 *rec = reinterpret_cast<const float4 *>(w.q_b + int64_t(key) * g.srec);
+    reinterpret_cast<float4 *>(w.rec_a)[dst] = rec[0];
     w.perm_a[dst] = key;
-    const float *qr = w.q_b + int64_t(key) * g.C;
-    for (int c = 0; c < g.C; ++c) w.q_a[int64_t(c) * g.N + dst] = qr[c];
+    for (int c4 = 0; 4 * c4 < g.C; ++c4) {
+      const float4 v = rec[1 + c4];
+      const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (4 * c4 + j < g.C) w.q_a[int64_t(4 * c4 + j) * g.N + dst] = vv[j];
+    }
   }
 }
 

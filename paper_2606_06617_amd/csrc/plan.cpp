@@ -159,7 +159,7 @@ struct pswflr_plan_s {
   int device = 0;
   // workspace layout for max_atoms
   int64_t max_atoms = 0;
-  size_t off_grid = 0, off_s1 = 0, off_s2 = 0, off_rec_a = 0, off_rec_b = 0, off_q_a = 0, off_q_b = 0,
+  size_t off_grid = 0, off_s1 = 0, off_s2 = 0, off_rec_a = 0, off_q_a = 0, off_q_b = 0,
          off_perm_a = 0, off_perm_b = 0, off_cell_of = 0, off_slot = 0, off_count = 0, off_start = 0,
          off_epart = 0, off_qpart = 0, off_qsum = 0, ws_bytes = 0;
   // optional per-stage event timing (measurement only)
@@ -349,6 +349,7 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   while ((1 << g.kby_log2) < g.kby) ++g.kby_log2;
   g.kzq_log2 = 0;
   while ((1 << g.kzq_log2) < g.kzq) ++g.kzq_log2;
+  g.srec = 4 + (C + 3) / 4 * 4;
   g.zlines = std::max(1, floor_pow2(4096 / g.Nz));
   g.div_nz = make_fastdiv(g.Nz);
   g.div_kz = make_fastdiv(g.KZ);
@@ -498,9 +499,8 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   pl.off_s1 = take(s1_b);
   pl.off_s2 = s2_b <= grid_b ? pl.off_grid : take(s2_b);  // grid is dead while S2 lives
   pl.off_rec_a = take(size_t(Nm) * 16);
-  pl.off_rec_b = take(size_t(Nm) * 16);
   pl.off_q_a = take(size_t(Nm) * C * 4);
-  pl.off_q_b = take(size_t(Nm) * C * 4);
+  pl.off_q_b = take(size_t(Nm) * g.srec * 4);
   pl.off_perm_a = take(size_t(Nm) * 4);
   pl.off_perm_b = take(size_t(Nm) * 4);
   pl.off_cell_of = take(size_t(Nm) * 4);
@@ -549,7 +549,6 @@ Work carve(const pswflr_plan_s &pl, void *ws, int64_t N) {
   w.s1 = reinterpret_cast<float *>(b + pl.off_s1);
   w.s2 = reinterpret_cast<float *>(b + pl.off_s2);
   w.rec_a = reinterpret_cast<float *>(b + pl.off_rec_a);
-  w.rec_b = reinterpret_cast<float *>(b + pl.off_rec_b);
   w.q_a = reinterpret_cast<float *>(b + pl.off_q_a);
   w.q_b = reinterpret_cast<float *>(b + pl.off_q_b);
   w.perm_a = reinterpret_cast<int *>(b + pl.off_perm_a);
