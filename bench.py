@@ -155,7 +155,9 @@ def serving_leg(nreq=400, seed=6, fractions=(0.5, 0.8, 0.95), slots=4):
     warm = Server(HipExecutor(slots=1))
     warm.run_trace([reqs[i] for i in range(min(8, nreq))], realtime=False)
     warm.close()
-    solo = Server(HipExecutor(slots=1))
+    ex1 = HipExecutor(slots=1)
+    ex1.reserve(max(r.n_atoms for r in reqs), max(len(r.ps) for r in reqs))
+    solo = Server(ex1)
     t0 = time.perf_counter()
     done = solo.run_trace(reqs, realtime=False)
     span = time.perf_counter() - t0
@@ -168,7 +170,9 @@ def serving_leg(nreq=400, seed=6, fractions=(0.5, 0.8, 0.95), slots=4):
         gaps = rng.exponential(1.0 / (f * capacity), size=nreq)
         for r, t in zip(reqs, np.cumsum(gaps)):
             r.t_arrival, r.t_done, r.t_admit, r.t_ready, r.error = float(t), None, None, None, None
-        srv = Server(HipExecutor(slots=slots))
+        ex = HipExecutor(slots=slots)
+        ex.reserve(max(r.n_atoms for r in reqs), max(len(r.ps) for r in reqs))
+        srv = Server(ex)
         res = srv.run_trace(reqs, realtime=True)
         srv.close()
         st = latency_stats(res)

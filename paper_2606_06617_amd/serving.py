@@ -68,6 +68,17 @@ class HipExecutor:
         # and no request pays a pinned allocation
         self._pinned = [dict() for _ in range(slots)]
 
+    def reserve(self, n_atoms, n_channels):
+        """Allocate every slot's pinned staging for requests of up to
+        n_atoms atoms and n_channels channels ahead of serving."""
+        torch = self.torch
+        for slot in range(self.slots):
+            self._stage(slot, "pos", (n_atoms, 3), torch.float32)
+            self._stage(slot, "q", (n_channels, n_atoms), torch.float32)
+            self._stage(slot, "energy", (3 * n_channels,), torch.float64)
+            self._stage(slot, "forces", (n_atoms, 3), torch.float32)
+            self._stage(slot, "virial", (6,), torch.float64)
+
     def _stage(self, slot, name, shape, dtype):
         n = 1
         for d in shape:
