@@ -15,7 +15,7 @@ import os
 import threading
 import time
 
-KERNEL_VERSION = 11
+KERNEL_VERSION = 12
 _LOCK = threading.Lock()
 
 

@@ -1744,6 +1744,10 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
     }
     const int base = o[0] * plane + o[1] * SZ + o[2];
     float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+    // a wave whose atoms all lie past the end of the tile (the short last
+    // pass of a tile with more than kGatherAtoms atoms) only moves halo
+    // data and meets the barriers
+    const bool wave_busy = (wv * 64) / kGatherLanes < na;
 
     for (int c = 0; c < g.C; ++c) {
       // this wave's part of channel c has landed; after the barrier all of
@@ -1756,6 +1760,7 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
         gather_dma_halo(w.grid, chan, c + 1, goff, (c & 1) ? tile0 : tile1, wv);
         qv = w.q_a[int64_t(c + 1) * g.N + a];
       }
+      if (!wave_busy) continue;
       float vphi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
 #pragma unroll 1
       for (int j = 0; j < R; ++j) {
