@@ -17,6 +17,9 @@ on; bench.py reports the traffic only while the source is unchanged.
 
   python -m paper_2606_06617_amd.profiling stats <kernel_stats.csv> --out F --cmd "..."
   python -m paper_2606_06617_amd.profiling traffic <fetch.csv> <write.csv> --copy-bytes B --out F --cmd "..."
+
+B is what the copy moves in total, read plus written (2 x --calib-copy-mib
+MiB, the calib_copy_bytes bench.py prints).
 """
 import argparse
 import collections
@@ -134,7 +137,9 @@ def main():
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
-    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--copy-bytes", type=int, required=True,
+                   help="bytes the calibration copy moves, read plus written (bench.py's calib_copy_bytes: "
+                        "2 x --calib-copy-mib MiB)")
     t.add_argument("--out", required=True)
     t.add_argument("--cmd", required=True)
     a = ap.parse_args()
