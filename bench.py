@@ -235,8 +235,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the sharded design is "
-              "described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (each structure, or each "
+              "channel group of one structure, runs whole on one device); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import ctypes

@@ -16,7 +16,7 @@ Forces (Fig. 1 caption: obtained by differentiation) use the exact adjoint:
 phi_grid = dE/dg = (1/V) IDFT(K F) with K = Phi_p h^6 / What^2, gathered
 with W for potentials and with grad W for forces.
 
-Readings used (all listed in the design doc):
+Readings of the paper used here:
  * the spreading window has its own bandwidth c_s (the paper reuses the
    symbol c for both the mollifier and the window);
  * grid nodes sit at n h, n = 0..M-1; each atom touches the P nodes with
