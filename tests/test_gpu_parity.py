@@ -89,7 +89,7 @@ def test_random_box_vs_mesh_algorithm():
     _compare(g, r, 2e-6, 2e-5, 2e-5, 2e-5)
 
 
-@pytest.mark.parametrize("P", [4, 5, 6, 7, 8])
+@pytest.mark.parametrize("P", [2, 3, 4, 5, 6, 7, 8])
 def test_every_support_vs_mesh_algorithm(P):
     w = wl.random_box(300, ps=(1,), seed=30 + P)
     grid = (20, 24, 18)
