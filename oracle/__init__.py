@@ -16,6 +16,9 @@ kernels     mollifiers G_p (Eqs. G1, G6, G), Fourier kernels Phi_p (Eq. PhiH),
             details").
 reciprocal  direct structure-factor sum of the truncated Fourier energy
             (Eq. Fourier) with potentials, forces and virial.
+cellsum     the same Fourier sum for a general (triclinic) cell H, structure
+            factors from separable phase tables in fractional coordinates,
+            potentials and forces for a sample of atoms (large structures).
 realspace   real-space complement (1 - G_p)/r^p summed over images.
 ewald       textbook Ewald for p = 1 (independent cross-check only; Eq.
             screening).
