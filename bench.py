@@ -255,7 +255,7 @@ def main():
     q = torch.from_numpy(w["q"]).to(dev)
     plan = Plan(w["box"], w["ps"], r_c=R_C, c=C_MOL, grid=w["grid"], support=w["support"], max_atoms=N)
     ws = plan.new_workspace(dev)
-    out = {"energy": torch.empty(3 * C, dtype=torch.float64, device=dev),
+    out = {"energy": torch.empty(3 * C + 1, dtype=torch.float64, device=dev),
            "forces": torch.empty((N, 3), dtype=torch.float32, device=dev),
            "virial": torch.empty(6, dtype=torch.float64, device=dev)}
     L = _lib.lib()

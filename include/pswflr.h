@@ -15,9 +15,9 @@
  * the PSWF-mollified kernel G_p(r)/r^p (Eq. PhiH), k_c = c / r_c (Methods,
  * "Parameter selection").  The zero-frequency term E_0 (Eqs. Correction,
  * Correction3r) and the self term E_self (Methods, "Implementation
- * details") are returned separately per channel; the long-range energy
- * of the MLIP decomposition is E_lr = sum_c (E_k + E_0), and the complete
- * split of Eq. realLR is E_real + E_lr - sum_c E_self.
+ * details") are returned separately per channel, followed by the long-range
+ * energy of the MLIP decomposition, E_lr = sum_c (E_k + E_0) (Eq. Fourier);
+ * the complete split of Eq. realLR is E_real + E_lr - sum_c E_self.
  *
  * Conventions
  *  - Units: lengths in the caller's unit (Angstrom in the paper); energies in
@@ -34,7 +34,11 @@
  *  - Errors: argument errors are detected on the host before any launch and
  *    returned as a status; no exception crosses the ABI.  Launch failures are
  *    returned as PSWFLR_ERR_DEVICE.  pswflr_last_error() gives the message of
- *    the last failure on the calling thread.
+ *    the last failure on the calling thread.  Values on the device are not
+ *    inspected unless the plan has PSWFLR_FLAG_CHECK_INPUTS; without it a
+ *    non-finite position makes E_lr, every E_k and the virial NaN (the atom
+ *    itself is placed at the origin so that every kernel stays in bounds)
+ *    and non-finite charges propagate into the sums.
  */
 #ifndef PSWFLR_H
 #define PSWFLR_H
@@ -49,6 +53,14 @@ extern "C" {
 #define PSWFLR_MAX_CHANNELS 64
 #define PSWFLR_MAX_SUPPORT 8
 #define PSWFLR_MAX_GRID 1024
+
+/* Plan flags (pswflr_params.flags).
+ * PSWFLR_FLAG_CHECK_INPUTS: every execute call first checks on the device
+ * that all positions and charges are finite and waits for the answer; a
+ * non-finite value returns PSWFLR_ERR_INVALID_ARG and nothing else runs.
+ * The wait makes the call synchronous: meant for debugging and for callers
+ * that take inputs from untrusted sources. */
+#define PSWFLR_FLAG_CHECK_INPUTS 1u
 
 typedef struct pswflr_plan_s *pswflr_plan; /* opaque, immutable after create */
 typedef void *pswflr_stream;               /* a hipStream_t */
@@ -82,11 +94,14 @@ typedef struct {
   int32_t tile[3];                   /* binning/spreading tile edges; 0: the
                                         planner's choice.  Each must divide
                                         the grid edge (autotuner knob)       */
-  uint32_t flags;                    /* reserved, 0                           */
+  uint32_t flags;                    /* PSWFLR_FLAG_* bits, 0 for none        */
 } pswflr_params;
 
-/* Resolved plan: what the automatic choices became, and the workspace the
- * caller must provide for up to max_atoms atoms. */
+/* Resolved plan (Methods, "Parameter selection"): what the automatic
+ * choices became (c = ln(3 / tol) splits the tolerance in thirds between
+ * the band limit, the spreading window and the rest; h <= eta pi / k_c;
+ * the smallest P whose aliasing estimate meets tol / 3), and the workspace
+ * the caller must provide for up to max_atoms atoms. */
 typedef struct {
   double c, r_c, k_c, c_spread, eta;
   double h[3];
@@ -116,20 +131,25 @@ typedef struct {
 pswflr_status pswflr_plan_create(const pswflr_params *params, int64_t max_atoms,
                                  pswflr_plan *out);
 
-/* Copy the resolved parameters and sizes into *out. */
+/* Copy the resolved parameters and sizes (Methods, "Parameter selection")
+ * into *out, a caller-owned struct.  Errors: INVALID_ARG (NULL). */
 pswflr_status pswflr_plan_info(pswflr_plan plan, pswflr_info *out);
 
-/* Release the plan.  Its device table goes back to a per-process pool (no
+/* Release the plan (the tables of Methods, "Parameter selection").  Its
+ * device table goes back to a per-process pool (no
  * device-wide wait) and is handed to a later plan only once the event
  * recorded at the end of this plan's last call has completed; a plan used
  * on several streams at once must have those streams synchronised by the
  * caller first.  Never blocks. */
 pswflr_status pswflr_plan_destroy(pswflr_plan plan);
 
-/* One evaluation (the whole hot path) on `stream`.
+/* One evaluation (the whole hot path: the four steps after Eq. EthetaLR in
+ * Methods, "Accelerating atom-grid spreading with PSWFs", and their adjoint
+ * for forces, Fig. 1 caption) on `stream`.
  *   pos       [N][3] float, positions (wrapped into the cell)
  *   q         [C][N] float, latent variables per channel (SoA)
- *   energy    [3C] double (required): per channel E_k, E_0, E_self
+ *   energy    [3C + 1] double (required): per channel E_k, E_0, E_self,
+ *             then E_lr = sum_c (E_k + E_0) summed in channel order
  *   forces    [N][3] float or NULL: F_i = -d(sum_c E_k + E_0)/dr_i
  *   virial    [6] double or NULL: W = -dE/d(strain) of sum_c (E_k + E_0),
  *             order xx, yy, zz, xy, xz, yz
@@ -148,15 +168,20 @@ pswflr_status pswflr_execute(pswflr_plan plan, pswflr_stream stream, void *works
 /* Adjoint of an energy-only pswflr_execute (same plan, workspace, positions
  * and charges, no other call on that workspace in between): given
  * grad_energy [C] (device double, dL/dE_c where E_c = E_k + E_0 of channel
- * c), writes dL/dq [C][N] and dL/dr [N][3] (either may be NULL).
- * This is the hand-written backward of the differentiable energy: the
- * scaled inverse transforms and the gather. */
+ * c), writes dL/dq [C][N] and dL/dr [N][3] (either may be NULL; device
+ * float, caller-owned).  This is the hand-written backward of the
+ * differentiable energy (Fig. 1 caption: forces and charge gradients by
+ * differentiation of Eq. Fourier): the spectrum scaled by Phi_p / What^2
+ * (Eq. EthetaLR), the inverse transforms and the gather with the window
+ * and its gradient.  Errors: INVALID_ARG, WORKSPACE, DEVICE. */
 pswflr_status pswflr_backward(pswflr_plan plan, pswflr_stream stream, void *workspace,
                               size_t ws_bytes, int64_t n_atoms, const float *pos,
                               const float *q, const double *grad_energy,
                               float *grad_q, float *grad_pos);
 
-/* Many structures in one call (MLIP training batches, serving mixes).  Each
+/* Many structures in one call (MLIP training batches, serving mixes; the
+ * paper evaluates configurations of many sizes and boxes, Methods,
+ * "Performance comparison in differentiable long-range evaluations").  Each
  * entry has its own plan (box, grid and channels may differ) and its own
  * device pointers; semantics per entry are those of pswflr_execute.  Each
  * stage is one launch covering every entry (a device table maps a block to
@@ -175,6 +200,8 @@ typedef struct {
   float *potential;
 } pswflr_io;
 
+/* Bytes of workspace pswflr_execute_batch needs for these plans and atom
+ * counts (host arrays of n entries).  Errors: INVALID_ARG. */
 pswflr_status pswflr_batch_workspace(int32_t n, const pswflr_plan *plans,
                                      const int64_t *n_atoms, size_t *bytes);
 pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans,
@@ -205,8 +232,11 @@ enum {
 pswflr_status pswflr_profile_enable(pswflr_plan plan, int enable);
 pswflr_status pswflr_profile_read(pswflr_plan plan, double *ms_total, int64_t *launches);
 
+/* Static text naming a status (not a passage of the paper: error
+ * reporting of this interface). */
 const char *pswflr_status_string(pswflr_status status);
-/* Copies the last error message of the calling thread (NUL-terminated). */
+/* Copies the last error message of the calling thread (NUL-terminated,
+ * truncated to len bytes) into the caller's buffer. */
 void pswflr_last_error(char *buf, size_t len);
 
 #ifdef __cplusplus

@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpswflr.so")
 
 MAX_CHANNELS = 64
+FLAG_CHECK_INPUTS = 1
 
 OK = 0
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "workspace", 4: "device error",
@@ -117,7 +118,7 @@ def check(status):
         raise PswflrError(status, buf.value.decode(errors="replace"))
 
 
-def make_params(box, ps, r_c, c=0.0, tol=1e-5, grid=None, support=0, c_spread=0.0, tile=None):
+def make_params(box, ps, r_c, c=0.0, tol=1e-5, grid=None, support=0, c_spread=0.0, tile=None, flags=0):
     prm = Params()
     ps = list(ps)
     if not 1 <= len(ps) <= MAX_CHANNELS:
@@ -135,5 +136,5 @@ def make_params(box, ps, r_c, c=0.0, tol=1e-5, grid=None, support=0, c_spread=0.
     prm.c_spread = float(c_spread or 0.0)
     for a in range(3):
         prm.tile[a] = int(tile[a]) if tile is not None else 0
-    prm.flags = 0
+    prm.flags = int(flags)
     return prm

@@ -1,6 +1,7 @@
 """Python API over the C ABI: plans, one-structure evaluation, the autograd
 adjoint.  PyTorch provides device memory and the current stream only.
 """
+import contextlib
 import ctypes
 
 import torch
@@ -23,13 +24,16 @@ class Plan:
     box: 3 orthorhombic edges; ps: exponent per channel (1..6); r_c: the
     short-range cutoff (k_c = c / r_c); c: mollifier bandwidth (0: from tol);
     grid: (Mx, My, Mz) or None (from tol); support: window points per axis
-    P (0: from tol); c_spread: window bandwidth (0: automatic).
+    P (0: from tol); c_spread: window bandwidth (0: automatic); check_inputs:
+    every call first verifies on the device that positions and charges are
+    finite and raises otherwise (synchronous).
     """
 
     def __init__(self, box, ps, r_c=5.0, c=12.024, tol=1e-5, grid=None, support=0, c_spread=0.0,
-                 max_atoms=1, tile=None):
+                 max_atoms=1, tile=None, check_inputs=False):
         L = _lib.lib()
-        self.params = _lib.make_params(box, ps, r_c, c, tol, grid, support, c_spread, tile)
+        self.params = _lib.make_params(box, ps, r_c, c, tol, grid, support, c_spread, tile,
+                                       flags=_lib.FLAG_CHECK_INPUTS if check_inputs else 0)
         h = ctypes.c_void_p()
         _lib.check(L.pswflr_plan_create(ctypes.byref(self.params), int(max_atoms), ctypes.byref(h)))
         self.handle = h
@@ -73,25 +77,31 @@ class Plan:
 
     def execute(self, pos, q, forces=True, virial=True, potential=False, workspace=None, stream=None,
                 out=None):
-        """Evaluate energy [3C] (E_k, E_0, E_self per channel), forces [N,3],
-        virial [6] and potentials [C,N] on the current stream.
+        """Evaluate energy [3C + 1] (E_k, E_0, E_self per channel, then
+        E_lr = sum_c (E_k + E_0)), forces [N,3], virial [6] and potentials
+        [C,N] on `stream` (default: the current stream).  Tensors allocated
+        here are allocated on that stream, so the caching allocator does not
+        hand them to other work before the call has run.
 
         pos: float32 [N,3] CUDA tensor; q: float32 [C,N] CUDA tensor.
         """
         _check_inputs(pos, q, self.C, self.max_atoms)
         N = pos.shape[0]
         dev = pos.device
-        ws = workspace if workspace is not None else self.new_workspace(dev)
         o = out or {}
-        energy = o.get("energy")
-        if energy is None:
-            energy = torch.empty(3 * self.C, dtype=torch.float64, device=dev)
-        F = (o.get("forces") if o.get("forces") is not None else
-             torch.empty((N, 3), dtype=torch.float32, device=dev)) if forces else None
-        W = (o.get("virial") if o.get("virial") is not None else
-             torch.empty(6, dtype=torch.float64, device=dev)) if virial else None
-        phi = (o.get("potential") if o.get("potential") is not None else
-               torch.empty((self.C, N), dtype=torch.float32, device=dev)) if potential else None
+        with (torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()):
+            ws = workspace if workspace is not None else self.new_workspace(dev)
+            energy = o.get("energy")
+            if energy is None:
+                energy = torch.empty(3 * self.C + 1, dtype=torch.float64, device=dev)
+            F = (o.get("forces") if o.get("forces") is not None else
+                 torch.empty((N, 3), dtype=torch.float32, device=dev)) if forces else None
+            W = (o.get("virial") if o.get("virial") is not None else
+                 torch.empty(6, dtype=torch.float64, device=dev)) if virial else None
+            phi = (o.get("potential") if o.get("potential") is not None else
+                   torch.empty((self.C, N), dtype=torch.float32, device=dev)) if potential else None
+        if energy.numel() < 3 * self.C + 1:
+            raise ValueError("energy output needs 3C + 1 entries")
         st = _lib.lib().pswflr_execute(self.handle, _stream(stream), _ptr(ws), ws.numel(), N, _ptr(pos),
                                        _ptr(q), _ptr(energy), _ptr(F), _ptr(W), _ptr(phi))
         _lib.check(st)
@@ -101,9 +111,10 @@ class Plan:
         """Adjoint of an energy-only execute on the same workspace."""
         N = pos.shape[0]
         dev = pos.device
-        gq = torch.empty((self.C, N), dtype=torch.float32, device=dev) if want_q else None
-        gp = torch.empty((N, 3), dtype=torch.float32, device=dev) if want_pos else None
-        g = grad_energy.to(device=dev, dtype=torch.float64).contiguous()
+        with (torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()):
+            gq = torch.empty((self.C, N), dtype=torch.float32, device=dev) if want_q else None
+            gp = torch.empty((N, 3), dtype=torch.float32, device=dev) if want_pos else None
+            g = grad_energy.to(device=dev, dtype=torch.float64).contiguous()
         st = _lib.lib().pswflr_backward(self.handle, _stream(stream), _ptr(workspace), workspace.numel(), N,
                                         _ptr(pos), _ptr(q), _ptr(g), _ptr(gq), _ptr(gp))
         _lib.check(st)
@@ -131,11 +142,11 @@ def execute_batch(plans, inputs, forces=True, virial=True, potential=False, work
     # structure); the per-structure dicts hold views of them
     Ns = [int(x[0].shape[0]) for x in inputs]
     Cs = [plan.C for plan in plans]
-    e_all = torch.empty(3 * sum(Cs), dtype=torch.float64, device=dev)
+    e_all = torch.empty(sum(3 * c + 1 for c in Cs), dtype=torch.float64, device=dev)
     f_all = torch.empty((sum(Ns), 3), dtype=torch.float32, device=dev) if forces else None
     v_all = torch.empty((n, 6), dtype=torch.float64, device=dev) if virial else None
     p_all = torch.empty(sum(c * m for c, m in zip(Cs, Ns)), dtype=torch.float32, device=dev) if potential else None
-    e_views = torch.split(e_all, [3 * c for c in Cs])
+    e_views = torch.split(e_all, [3 * c + 1 for c in Cs])
     f_views = torch.split(f_all, Ns) if forces else [None] * n
     v_views = v_all.unbind(0) if virial else [None] * n
     p_views = ([t.view(c, m) for t, c, m in zip(torch.split(p_all, [c * m for c, m in zip(Cs, Ns)]), Cs, Ns)]
@@ -158,7 +169,7 @@ def execute_batch(plans, inputs, forces=True, virial=True, potential=False, work
         io.forces = f_ptr + 12 * fo if forces else None
         io.virial = v_ptr + 48 * i if virial else None
         io.potential = p_ptr + 4 * po if potential else None
-        eo += 3 * C
+        eo += 3 * C + 1
         fo += N
         po += C * N
         outs.append({"energy": e_views[i], "forces": f_views[i], "virial": v_views[i], "potential": p_views[i]})
@@ -190,7 +201,8 @@ def energy_forces(pos, q, box, ps, r_c=5.0, c=12.024, tol=1e-5, grid=None, suppo
 
 
 class PSWFLRFunction(torch.autograd.Function):
-    """E_lr = sum_c (E_k + E_0) as a differentiable function of (pos, q).
+    """E_lr = sum_c (E_k + E_0) (the library's last energy entry) as a
+    differentiable function of (pos, q).
 
     Forward runs only the forward transforms (the energy needs no inverse
     FFT) and keeps the spectrum in the plan's workspace; backward runs the
@@ -203,11 +215,10 @@ class PSWFLRFunction(torch.autograd.Function):
         ws = plan.new_workspace(pos.device)
         out = plan.execute(pos.detach(), q.detach(), forces=False, virial=False, potential=False,
                            workspace=ws)
-        e = out["energy"].view(-1, 3)
         ctx.plan = plan
         ctx.ws = ws
         ctx.save_for_backward(pos.detach(), q.detach())
-        return (e[:, 0] + e[:, 1]).sum()
+        return out["energy"][3 * plan.C]
 
     @staticmethod
     def backward(ctx, grad_out):

@@ -3,7 +3,15 @@
 // can include it.
 #pragma once
 
+#include <cmath>
 #include <cstdint>
+
+// functions the kernels share with host-side unit probes (built with g++)
+#ifdef __HIPCC__
+#define PSWF_HD __host__ __device__
+#else
+#define PSWF_HD
+#endif
 
 namespace pswf {
 
@@ -33,6 +41,41 @@ inline FastDiv make_fastdiv(int d) {
   return f;
 }
 
+// Window start of one position component.  The grid coordinate
+// u = x M / L is formed as an unevaluated FP32 sum hi + lo: M / L = sh + sl
+// is carried in two floats and the product's rounding error is recovered
+// exactly by an FMA, so u is good to ~1e-14 relative (a plain FP32 product
+// would lose ~3e-5 grid units at M = 256).  The window covers the P nodes
+// n0 .. n0 + P - 1 with n0 = ceil(u - P/2); delta = n0 - (u - P/2) is in
+// [0, 1) and n0 is returned wrapped into [0, M).  Positions a few boxes
+// outside the cell keep their unwrapped coordinate (only the integer start
+// is wrapped, exactly); beyond 2^22 grid units the whole multiple of M is
+// removed from the coordinate first.
+PSWF_HD inline void window_start(float x, float sh, float sl, int M, int P, int *n0, float *delta) {
+  const float Mf = float(M);
+  float p = x * sh;
+  const float lo = std::fma(x, sh, -p) + x * sl;
+  if (std::fabs(p) >= 4194304.0f) p = std::fma(-std::floor(p / Mf), Mf, p);
+  // s = u - P/2 = shi + slo by an error-free two-sum
+  const float half = 0.5f * float(P);
+  const float shi = p - half;
+  const float bv = shi - p;
+  const float slo = ((p - (shi - bv)) + (-half - bv)) + lo;
+  float nf = std::ceil(shi);
+  float d = (nf - shi) - slo;
+  if (d < 0.0f) {
+    nf += 1.0f;
+    d += 1.0f;
+  } else if (d >= 1.0f) {
+    nf -= 1.0f;
+    d -= 1.0f;
+  }
+  *delta = d < 0.0f ? 0.0f : (d > 0.99999994f ? 0.99999994f : d);
+  int n = int(nf) % M;
+  if (n < 0) n += M;
+  *n0 = n;
+}
+
 // Stockham factorisation of one transform length.
 struct FftAxis {
   int n = 1;
@@ -52,8 +95,9 @@ struct KChan {
   float pad[2];
 };
 
-// One problem geometry.  Doubles where positions are turned into grid
-// coordinates (FP32 would lose ~3e-5 grid units at M = 256).
+// One problem geometry.  Positions become grid coordinates in FP32
+// double-word arithmetic: M / L is carried as an unevaluated sum of two
+// floats (a single FP32 product would lose ~3e-5 grid units at M = 256).
 struct Geo {
   int C;                  // channels
   int64_t N;              // atoms
@@ -66,8 +110,8 @@ struct Geo {
   int B[3];               // tile edge per axis
   int nc[3];              // tiles per axis
   int ncell;
-  double L[3];            // box
-  double Minv_L[3];       // M / L
+  double L[3];            // box (host side)
+  float sM_hi[3], sM_lo[3];  // M / L = sM_hi + sM_lo (FP32 double word)
   float kunit[3];         // 2 pi / L
   float kc2;              // k_c^2
   float kinv;             // r_c / c  (kappa = k * kinv)
@@ -129,6 +173,8 @@ struct Work {
   double *epart;          // [C][nxblk][8]
   double *qpart;          // [nqblk][C][2]
   double *qsum;           // [C][2]: Q_net, Q_self
+  int *status;            // [2] input status: [0] bit 0 = a non-finite position met by
+                          // the binning; [1] result of the optional input check
 };
 
 // One structure of a batched call: everything a stage body needs.

@@ -335,12 +335,13 @@ __device__ __forceinline__ int unpack_n0(unsigned v, int a) { return int((v >> (
 // ---------------------------------------------------------------------------
 // Binning: each atom is assigned to the tile holding the first node of its
 // window, n0 = ceil(x/h - P/2) (mod M); delta = n0 - (x/h - P/2) in [0, 1).
-__device__ __forceinline__ void zero_int_body(int *p, int n, int bx) {
+__device__ __forceinline__ void zero_body(const Geo &g, const Work &w, int bx) {
   int i = bx * PSWF_THREADS + threadIdx.x;
-  if (i < n) p[i] = 0;
+  if (i < g.ncell) w.cell_count[i] = 0;
+  if (i == 0) w.status[0] = 0;
 }
 
-__global__ __launch_bounds__(PSWF_THREADS) void k_zero_int(int *p, int n) { zero_int_body(p, n, blockIdx.x); }
+__global__ __launch_bounds__(PSWF_THREADS) void k_zero(Geo g, Work w) { zero_body(g, w, blockIdx.x); }
 
 __device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const float *__restrict__ pos,
                                          const float *__restrict__ q, int bx) {
@@ -359,23 +360,22 @@ __device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const floa
   unsigned packed = 0;
   float dl[3];
   int cell[3];
+  bool bad = false;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double x = double(pos[3 * i + a]);
-    if (!isfinite(x)) x = 0.0;
-    const double L = g.L[a];
-    x -= L * floor(x / L);
-    if (x >= L || x < 0.0) x = 0.0;
-    const double s = x * g.Minv_L[a] - 0.5 * g.P;
-    double n0d = ceil(s);
-    float delta = float(n0d - s);
-    if (delta >= 1.0f) delta = 0.99999994f;
-    int n0 = int(n0d) % g.M[a];
-    if (n0 < 0) n0 += g.M[a];
+    float x = pos[3 * i + a];
+    if (!isfinite(x)) {  // reported through the status word; placed at 0
+      bad = true;
+      x = 0.0f;
+    }
+    int n0;
+    float delta;
+    window_start(x, g.sM_hi[a], g.sM_lo[a], g.M[a], g.P, &n0, &delta);
     dl[a] = delta;
     packed |= unsigned(n0) << (10 * a);
     cell[a] = n0 / g.B[a];
   }
+  if (bad) atomicOr(w.status, 1);
   const int c = (cell[0] * g.nc[1] + cell[1]) * g.nc[2] + cell[2];
   w.cell_of[i] = c;
   w.slot[i] = atomicAdd(&w.cell_count[c], 1);
@@ -426,6 +426,85 @@ __device__ __forceinline__ void scatter_body(const Geo &g, const Work &w, int bx
 
 __global__ __launch_bounds__(PSWF_THREADS) void k_scatter(Geo g, Work w) { scatter_body(g, w, blockIdx.x); }
 
+// move atom `key` (caller index) to cell-order position dst: its record,
+// its charges and the permutation entry
+__device__ __forceinline__ void order_move(const Geo &g, const Work &w, int key, int dst) {
+  const float4 *rec = reinterpret_cast<const float4 *>(w.q_b + int64_t(key) * g.srec);
+  reinterpret_cast<float4 *>(w.rec_a)[dst] = rec[0];
+  w.perm_a[dst] = key;
+  for (int c4 = 0; 4 * c4 < g.C; ++c4) {
+    const float4 v = rec[1 + c4];
+    const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (4 * c4 + j < g.C) w.q_a[int64_t(4 * c4 + j) * g.N + dst] = vv[j];
+  }
+}
+
+// Crowded cell (more keys than fit the LDS rank): stable least-significant-
+// digit radix sort of its caller indices, 8 bits per pass, between the
+// cell's ranges of perm_b and perm_a.  A pass takes the keys 256 at a time;
+// inside a wave, lanes with equal digits are found by ballots over the 8
+// digit bits and ranked by lane, waves in order, so every pass is stable and
+// the cost is linear in the cell's size.  Returns the buffer holding the
+// sorted keys.
+__device__ int *order_radix(const Geo &g, const Work &w, int s, int n) {
+  __shared__ int hist[256];
+  __shared__ int wcnt[PSWF_THREADS / 64][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int *src = w.perm_b + s, *dst = w.perm_a + s;
+  const int bits = g.N > 1 ? 32 - __clz(int(g.N - 1)) : 1;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int shift = 0; shift < bits; shift += 8) {
+    for (int d = tid; d < 256; d += PSWF_THREADS) hist[d] = 0;
+    __syncthreads();
+    for (int k = tid; k < n; k += PSWF_THREADS) atomicAdd(&hist[(src[k] >> shift) & 255], 1);
+    __syncthreads();
+    if (tid == 0) {  // exclusive prefix: the first slot of every digit
+      int acc = 0;
+      for (int d = 0; d < 256; ++d) {
+        const int v = hist[d];
+        hist[d] = acc;
+        acc += v;
+      }
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < n; k0 += PSWF_THREADS) {
+      for (int e = tid; e < (PSWF_THREADS / 64) * 256; e += PSWF_THREADS) (&wcnt[0][0])[e] = 0;
+      __syncthreads();
+      const int k = k0 + tid;
+      const bool valid = k < n;
+      const int key = valid ? src[k] : 0;
+      const int d = (key >> shift) & 255;
+      unsigned long long eq = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const unsigned long long on = __ballot(valid && ((d >> b) & 1));
+        eq &= ((d >> b) & 1) ? on : ~on;
+      }
+      const int rank = __popcll(eq & below);
+      if (valid && rank == 0) wcnt[wave][d] = __popcll(eq);
+      __syncthreads();
+      if (valid) {
+        int off = hist[d] + rank;
+        for (int wq = 0; wq < wave; ++wq) off += wcnt[wq][d];
+        dst[off] = key;
+      }
+      __syncthreads();
+      for (int dd = tid; dd < 256; dd += PSWF_THREADS) {
+        int t = 0;
+        for (int wq = 0; wq < PSWF_THREADS / 64; ++wq) t += wcnt[wq][dd];
+        hist[dd] += t;
+      }
+      __syncthreads();
+    }
+    int *tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  return src;
+}
+
 // deterministic order inside each cell: ascending caller index
 __device__ __forceinline__ void order_body(const Geo &g, const Work &w, int bx) {
   __shared__ int keys[2048];
@@ -433,26 +512,18 @@ __device__ __forceinline__ void order_body(const Geo &g, const Work &w, int bx) 
   const int s = w.cell_start[cell], e = w.cell_start[cell + 1];
   const int n = e - s;
   if (n <= 0) return;
-  const bool in_lds = n <= 2048;
-  if (in_lds) {
-    for (int k = threadIdx.x; k < n; k += PSWF_THREADS) keys[k] = w.perm_b[s + k];
-    __syncthreads();
+  if (n > 2048) {
+    const int *sorted = order_radix(g, w, s, n);
+    for (int k = threadIdx.x; k < n; k += PSWF_THREADS) order_move(g, w, sorted[k], s + k);
+    return;
   }
+  for (int k = threadIdx.x; k < n; k += PSWF_THREADS) keys[k] = w.perm_b[s + k];
+  __syncthreads();
   for (int k = threadIdx.x; k < n; k += PSWF_THREADS) {
-    const int key = in_lds ? keys[k] : w.perm_b[s + k];
+    const int key = keys[k];
     int rank = 0;
-    for (int m = 0; m < n; ++m) rank += (in_lds ? keys[m] : w.perm_b[s + m]) < key;
-    const int dst = s + rank;
-    const float4 *rec = reinterpret_cast<const float4 *>(w.q_b + int64_t(key) * g.srec);
-    reinterpret_cast<float4 *>(w.rec_a)[dst] = rec[0];
-    w.perm_a[dst] = key;
-    for (int c4 = 0; 4 * c4 < g.C; ++c4) {
-      const float4 v = rec[1 + c4];
-      const float vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (4 * c4 + j < g.C) w.q_a[int64_t(4 * c4 + j) * g.N + dst] = vv[j];
-    }
+    for (int m = 0; m < n; ++m) rank += keys[m] < key;
+    order_move(g, w, key, s + rank);
   }
 }
 
@@ -1854,13 +1925,19 @@ __global__ __launch_bounds__(kGatherThreads, 4) void k_gather(Geo g, Tables t, W
   gather_body<P>(g, t, w, fout, pout, mode, grad, tile_grouped(xcd_contiguous(blockIdx.x, gridDim.x), g.nc));
 }
 
-// Final FP64 reduction: energy [3C] (E_k, E_0, E_self) and virial [6].
+// Final FP64 reduction: energy [3C + 1] (E_k, E_0, E_self per channel, then
+// E_lr = sum_c (E_k + E_0) in channel order) and virial [6].  A non-finite
+// input position (status word set by the binning) makes E_lr, every E_k and
+// the virial NaN.
 __device__ __forceinline__ void finalize_body(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial) {
   // one wave per channel at a time (channels c = wave, wave + 4, ...): lane
   // sums over the x-pass blocks, then a fixed-order wave reduction; the
-  // channels' virial terms are added in channel order by one thread
-  __shared__ double vch[kMaxChannels][6];
+  // channels' energy and virial terms are added in channel order by one
+  // thread each
+  __shared__ double vch[kMaxChannels][7];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool bad = w.status[0] != 0;
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
   for (int c = wave; c < g.C; c += PSWF_THREADS / 64) {
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int b = lane; b < g.nxblk; b += 64)
@@ -1871,7 +1948,7 @@ __device__ __forceinline__ void finalize_body(const Geo &g, const Tables &t, con
       for (int off = 32; off > 0; off >>= 1) acc[i] += __shfl_down(acc[i], off, 64);
     if (lane == 0) {
       const double inv2V = 0.5 / g.V;
-      const double Ek = acc[0] * inv2V;
+      const double Ek = bad ? nan : acc[0] * inv2V;
       const double Q = w.qsum[2 * c], Q2 = w.qsum[2 * c + 1];
       const double E0 = t.zero_V[c] / g.V * Q * Q;
       energy[3 * c] = Ek;
@@ -1881,22 +1958,43 @@ __device__ __forceinline__ void finalize_body(const Geo &g, const Tables &t, con
       vch[c][0] = Ek + E0 + acc[1] * inv2V;
       vch[c][1] = Ek + E0 + acc[2] * inv2V;
       vch[c][2] = Ek + E0 + acc[3] * inv2V;
-      vch[c][3] = acc[4] * inv2V;
-      vch[c][4] = acc[5] * inv2V;
-      vch[c][5] = acc[6] * inv2V;
+      vch[c][3] = bad ? nan : acc[4] * inv2V;
+      vch[c][4] = bad ? nan : acc[5] * inv2V;
+      vch[c][5] = bad ? nan : acc[6] * inv2V;
+      vch[c][6] = Ek + E0;
     }
   }
   __syncthreads();
-  if (virial && tid < 6) {
+  if (tid < 7 && (virial || tid == 6)) {
     double v = 0.0;
     for (int c = 0; c < g.C; ++c) v += vch[c][tid];
-    virial[tid] = v;
+    if (tid < 6) virial[tid] = v;
+    else energy[3 * g.C] = g.C > 0 ? v : 0.0;
   }
 }
 
 __global__ __launch_bounds__(PSWF_THREADS) void k_finalize(Geo g, Tables t, Work w, double *energy, double *virial) {
   finalize_body(g, t, w, energy, virial);
 }
+// Input validation (plans created with PSWFLR_FLAG_CHECK_INPUTS): bit 0 of
+// word[0] is set when a position is not finite, bit 1 when a charge is not.
+__global__ __launch_bounds__(PSWF_THREADS) void k_clear_word(int *word) {
+  if (threadIdx.x == 0) word[0] = 0;
+}
+
+__global__ __launch_bounds__(PSWF_THREADS) void k_check_inputs(const float *__restrict__ pos, const float *__restrict__ q,
+                                                               int64_t npos, int64_t nq, int *word) {
+  int bits = 0;
+  for (int64_t i = int64_t(blockIdx.x) * PSWF_THREADS + threadIdx.x; i < npos + nq;
+       i += int64_t(gridDim.x) * PSWF_THREADS) {
+    const float v = i < npos ? pos[i] : q[i - npos];
+    if (!isfinite(v)) bits |= i < npos ? 1 : 2;
+  }
+  if (__ballot(bits != 0)) {
+    if (bits) atomicOr(word, bits);
+  }
+}
+
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -1986,8 +2084,7 @@ static hipError_t lds_request(const void *fn, size_t bytes) {
 
 hipError_t enqueue_sort(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st) {
   // cell offsets are produced even for N = 0 (the spread reads them)
-  hipLaunchKernelGGL(k_zero_int, dim3(nblocks(g.ncell, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st,
-                     w.cell_count, g.ncell);
+  hipLaunchKernelGGL(k_zero, dim3(nblocks(g.ncell, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, w);
   LAUNCH_CHECK();
   if (g.N > 0) {
     hipLaunchKernelGGL(k_bin, dim3(nblocks(g.N, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, w, pos, q);
@@ -2125,6 +2222,18 @@ hipError_t launch_gather(const Geo &g, const Tables &t, const Work &w, float *fo
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_check_inputs(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(PSWF_THREADS), 0, st, w.status + 1);
+  LAUNCH_CHECK();
+  const int64_t n = 3 * g.N + int64_t(g.C) * g.N;
+  if (n == 0) return hipSuccess;
+  const unsigned nb = unsigned(std::min<int64_t>(2048, (n + PSWF_THREADS - 1) / PSWF_THREADS));
+  hipLaunchKernelGGL(k_check_inputs, dim3(nb), dim3(PSWF_THREADS), 0, st, pos, q, 3 * g.N, int64_t(g.C) * g.N,
+                     w.status + 1);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
 hipError_t launch_finalize(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial,
                            hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(PSWF_THREADS), 0, st, g, t, w, energy, virial);
@@ -2155,7 +2264,7 @@ __global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather
   const int vb = b - prefix[s];
   const Geo &g = it.g;
   switch (STAGE) {
-    case kBsZero: zero_int_body(it.w.cell_count, g.ncell, vb); break;
+    case kBsZero: zero_body(g, it.w, vb); break;
     case kBsBin: bin_body(g, it.w, it.pos, it.q, vb); break;
     case kBsScan: scan_body(it.w, g.ncell, g.N); break;
     case kBsScatter: scatter_body(g, it.w, vb); break;

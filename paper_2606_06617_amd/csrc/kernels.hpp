@@ -36,6 +36,9 @@ hipError_t launch_yinv(const Geo &g, const Tables &t, const FftAxis &ay, const W
 hipError_t launch_zinv(const Geo &g, const Tables &t, const FftAxis &az, const Work &w, hipStream_t st);
 hipError_t launch_gather(const Geo &g, const Tables &t, const Work &w, float *forces, float *pot, int mode,
                          const double *grad, hipStream_t st);
+// input validation: word w.status[1] gets bit 0 for a non-finite position,
+// bit 1 for a non-finite charge
+hipError_t launch_check_inputs(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st);
 hipError_t launch_finalize(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial,
                            hipStream_t st);
 

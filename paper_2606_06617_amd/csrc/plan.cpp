@@ -161,7 +161,7 @@ struct pswflr_plan_s {
   int64_t max_atoms = 0;
   size_t off_grid = 0, off_s1 = 0, off_s2 = 0, off_rec_a = 0, off_q_a = 0, off_q_b = 0,
          off_perm_a = 0, off_perm_b = 0, off_cell_of = 0, off_slot = 0, off_count = 0, off_start = 0,
-         off_epart = 0, off_qpart = 0, off_qsum = 0, ws_bytes = 0;
+         off_epart = 0, off_qpart = 0, off_qsum = 0, off_status = 0, ws_bytes = 0;
   // optional per-stage event timing (measurement only)
   bool prof = false;
   std::mutex prof_mu;
@@ -186,6 +186,7 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
     return fail(PSWFLR_ERR_INVALID_ARG, "tol must be in (0, 0.1] when c, grid or support are automatic");
   if (p.support != 0 && (p.support < 2 || p.support > 8))
     return fail(PSWFLR_ERR_INVALID_ARG, "support P must be in 2..8");
+  if (p.flags & ~uint32_t(PSWFLR_FLAG_CHECK_INPUTS)) return fail(PSWFLR_ERR_INVALID_ARG, "unknown flag bits");
 
   // bandwidth c ~ log(1/eps_band) with eps_band = tol / 3
   const double c = p.c > 0.0 ? p.c : std::log(3.0 / p.tol);
@@ -239,7 +240,9 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   for (int a = 0; a < 3; ++a) {
     g.M[a] = M[a];
     g.L[a] = p.box[a];
-    g.Minv_L[a] = double(M[a]) / p.box[a];
+    const double sM = double(M[a]) / p.box[a];
+    g.sM_hi[a] = float(sM);
+    g.sM_lo[a] = float(sM - double(g.sM_hi[a]));
     g.kunit[a] = float(2.0 * kPi / p.box[a]);
     g.dwin[a] = float(2.0 / (P * h[a]));
   }
@@ -510,6 +513,7 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   pl.off_epart = take(size_t(C) * std::max(1, g.nxblk) * 8 * 8);
   pl.off_qpart = take(size_t((Nm + kQChunk - 1) / kQChunk + 1) * C * 2 * 8);
   pl.off_qsum = take(size_t(C) * 2 * 8);
+  pl.off_status = take(2 * sizeof(int));
   pl.ws_bytes = o;
   pl.max_atoms = max_atoms;
 
@@ -560,6 +564,7 @@ Work carve(const pswflr_plan_s &pl, void *ws, int64_t N) {
   w.epart = reinterpret_cast<double *>(b + pl.off_epart);
   w.qpart = reinterpret_cast<double *>(b + pl.off_qpart);
   w.qsum = reinterpret_cast<double *>(b + pl.off_qsum);
+  w.status = reinterpret_cast<int *>(b + pl.off_status);
   (void)N;
   return w;
 }
@@ -571,6 +576,21 @@ pswflr_status check_call(pswflr_plan pl, void *ws, size_t ws_bytes, int64_t n, c
   if (!ws || ws_bytes < pl->ws_bytes) return fail(PSWFLR_ERR_WORKSPACE, "workspace missing or too small");
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(PSWFLR_ERR_WORKSPACE, "workspace not 256-byte aligned");
   if (n > 0 && (!pos || !q)) return fail(PSWFLR_ERR_INVALID_ARG, "pos and q must be non-NULL");
+  return PSWFLR_OK;
+}
+
+// Optional input validation (PSWFLR_FLAG_CHECK_INPUTS): a check kernel,
+// then the result word is read back, which waits for the stream.
+pswflr_status check_inputs(const pswflr_plan_s &pl, hipStream_t st, const Geo &g, const Work &w, const float *pos,
+                           const float *q) {
+  if (!(pl.prm.flags & PSWFLR_FLAG_CHECK_INPUTS)) return PSWFLR_OK;
+  hipError_t e = launch_check_inputs(g, w, pos, q, st);
+  int word = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&word, w.status + 1, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("input check failed: ") + hipGetErrorString(e));
+  if (word & 1) return fail(PSWFLR_ERR_INVALID_ARG, "a position is not finite");
+  if (word & 2) return fail(PSWFLR_ERR_INVALID_ARG, "a charge is not finite");
   return PSWFLR_OK;
 }
 
@@ -703,6 +723,7 @@ pswflr_status pswflr_execute(pswflr_plan plan, pswflr_stream stream, void *works
   Geo g = plan->geo;
   g.N = n_atoms;
   Work w = carve(*plan, workspace, n_atoms);
+  if ((s = check_inputs(*plan, st, g, w, pos, q)) != PSWFLR_OK) return s;
   const bool adjoint = forces || potential;
   hipError_t e = run_forward(plan, st, g, w, pos, q, adjoint ? 1 : 0, energy, virial);
   if (e == hipSuccess && adjoint) e = run_adjoint(plan, st, g, w, forces, potential, 1, nullptr);
@@ -854,6 +875,17 @@ pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const ps
   hipStream_t st = static_cast<hipStream_t>(stream);
   char *ws = static_cast<char *>(workspace);
   const size_t hdr = batch_header_bytes(n);
+  {
+    size_t off = hdr;
+    for (int i = 0; i < n; ++i) {
+      Geo gi = plans[i]->geo;
+      gi.N = io[i].n_atoms;
+      if ((s = check_inputs(*plans[i], st, gi, carve(*plans[i], ws + off, io[i].n_atoms), io[i].pos, io[i].q)) !=
+          PSWFLR_OK)
+        return s;
+      off += align256(plans[i]->ws_bytes);
+    }
+  }
   bool fused = true;
   for (int i = 0; i < n; ++i) fused = fused && plans[i]->geo.C <= spread_max_channels();
   if (!fused) {  // channel groups beyond one spreading launch: one call per structure

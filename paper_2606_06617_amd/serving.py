@@ -75,7 +75,7 @@ class HipExecutor:
         for slot in range(self.slots):
             self._stage(slot, "pos", (n_atoms, 3), torch.float32)
             self._stage(slot, "q", (n_channels, n_atoms), torch.float32)
-            self._stage(slot, "energy", (3 * n_channels,), torch.float64)
+            self._stage(slot, "energy", (3 * n_channels + 1,), torch.float64)
             self._stage(slot, "forces", (n_atoms, 3), torch.float32)
             self._stage(slot, "virial", (6,), torch.float64)
 
@@ -104,7 +104,7 @@ class HipExecutor:
         plan = Plan(req.box, req.ps, r_c=self.r_c, c=self.c, tol=self.tol, support=self.support,
                     max_atoms=max(1, req.n_atoms))
         N, C = req.n_atoms, len(req.ps)
-        foot = plan.workspace_bytes + N * 12 * 2 + C * N * 4 + 3 * C * 8 + 48
+        foot = plan.workspace_bytes + N * 12 * 2 + C * N * 4 + (3 * C + 1) * 8 + 48
         return plan, foot
 
     def launch(self, req, plan, slot):
@@ -119,7 +119,7 @@ class HipExecutor:
             pos = pos_h.to(self.device, non_blocking=True)
             q = q_h.to(self.device, non_blocking=True)
             out = plan.execute(pos, q, forces=True, virial=True, stream=st)
-            e_h = self._stage(slot, "energy", (3 * C,), torch.float64)
+            e_h = self._stage(slot, "energy", (3 * C + 1,), torch.float64)
             f_h = self._stage(slot, "forces", (N, 3), torch.float32)
             w_h = self._stage(slot, "virial", (6,), torch.float64)
             e_h.copy_(out["energy"], non_blocking=True)

@@ -105,7 +105,7 @@ def water(nmol=1000, L=31.0, seed=2):
 
 def _neutral_charges(rng, nchan, n, sigma=0.5):
     q = rng.normal(0.0, sigma, size=(nchan, n))
-    return q - q.mean(axis=1, keepdims=True)
+    return q - q.mean(axis=1, keepdims=True) if n > 0 else q
 
 
 def ionic(n=1_000_000, nlatent=4, ps=(1, 3, 6), grid=256, support=8, seed=3):

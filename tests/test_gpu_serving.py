@@ -3,10 +3,13 @@ arrive while others are in flight; each result must equal the same request
 evaluated alone (bit for bit: kernels touch only their own structure and
 reduce in a fixed order), the HBM budget is respected and requests overlap.
 Also the batched launch path against its per-structure autotuned plans."""
+import math
+
 import numpy as np
 import pytest
 import torch
 
+from oracle import cellsum
 from paper_2606_06617_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -33,6 +36,18 @@ def test_mixed_stream_results_equal_alone():
         assert np.array_equal(r.energy, ref["energy"].cpu().numpy())
         assert np.array_equal(r.forces, ref["forces"].cpu().numpy())
         assert np.array_equal(r.virial, ref["virial"].cpu().numpy())
+    # served results against the plain direct sum at c = ln(3 / tol) (Methods,
+    # "Parameter selection"), at the method's bars
+    c = math.log(3.0 / 1e-5)
+    for r in out[:12]:
+        ref = cellsum.evaluate(r.pos.astype(np.float64), r.q.astype(np.float64), np.diag(r.box), r.ps, c, 5.0)
+        e = r.energy[:-1].reshape(-1, 3)
+        assert np.all(np.abs(e[:, 0] + e[:, 1] - ref["Ek"] - ref["E0"]) <= 1e-5 * np.abs(ref["Ek"] + ref["E0"]))
+        ef = np.sqrt(np.mean((r.forces - ref["F"]) ** 2)) / np.sqrt(np.mean(ref["F"] ** 2))
+        assert ef <= 1e-4, (r.rid, r.n_atoms, ef)
+        Wg = np.array([[r.virial[0], r.virial[3], r.virial[4]], [r.virial[3], r.virial[1], r.virial[5]],
+                       [r.virial[4], r.virial[5], r.virial[2]]])
+        assert np.abs(Wg - ref["W"]).max() <= 1e-4 * np.abs(ref["W"]).max()
 
 
 def test_budget_defers_admission():
