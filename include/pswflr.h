@@ -165,6 +165,28 @@ pswflr_status pswflr_execute(pswflr_plan plan, pswflr_stream stream, void *works
                              const float *q, double *energy, float *forces,
                              double *virial, float *potential);
 
+/* pswflr_execute without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments and results as
+ * pswflr_execute minus the workspace: the library's own scratch array of
+ * 64 MiB per device (reserved when the library is loaded, held until the
+ * process ends) takes its place.  Nothing is allocated: no hipMalloc,
+ * hipFree, event or pinned buffer, no timing events even while profiling
+ * is on.  Limits and rules:
+ *  - the plan's workspace (pswflr_info.workspace_bytes, set by its
+ *    max_atoms) must fit the 64 MiB, else PSWFLR_ERR_WORKSPACE;
+ *  - plans with PSWFLR_FLAG_CHECK_INPUTS are refused (INVALID_ARG): the
+ *    check waits on the host;
+ *  - every call on one device shares that device's scratch, which keeps
+ *    the last call's contents: calls that overlap on one device (two
+ *    streams, or two threads) race and give wrong results; serialise them;
+ *  - the call does not record the plan's last-use event: synchronise the
+ *    stream before destroying the plan.
+ * Errors: INVALID_ARG, WORKSPACE, DEVICE. */
+pswflr_status pswflr_execute_noalloc(pswflr_plan plan, pswflr_stream stream, int64_t n_atoms,
+                                     const float *pos, const float *q, double *energy,
+                                     float *forces, double *virial, float *potential);
+
 /* Adjoint of an energy-only pswflr_execute (same plan, workspace, positions
  * and charges, no other call on that workspace in between): given
  * grad_energy [C] (device double, dL/dE_c where E_c = E_k + E_0 of channel

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "device_types.hpp"
 #include "kernels.hpp"
@@ -2231,6 +2232,31 @@ hipError_t launch_check_inputs(const Geo &g, const Work &w, const float *pos, co
   hipLaunchKernelGGL(k_check_inputs, dim3(nb), dim3(PSWF_THREADS), 0, st, pos, q, 3 * g.N, int64_t(g.C) * g.N,
                      w.status + 1);
   LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// Scratch for callers that cannot allocate (pswflr_execute_noalloc): one
+// workspace-sized array per device, held until the process ends.  Host code
+// never passes the array's name to a kernel (in host code it names a host
+// stand-in, not device memory); it uses the device address looked up once
+// per device with that device current, kept below.
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+hipError_t noalloc_scratch(void **out) {
+  static std::mutex mu;
+  static void *addr[kNoallocMaxDevices] = {nullptr};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kNoallocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
   return hipSuccess;
 }
 

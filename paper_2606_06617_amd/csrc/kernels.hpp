@@ -10,6 +10,12 @@
 namespace pswf {
 
 constexpr int kQChunk = 8192;   // atoms per block of the charge sums
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;  // workspace of pswflr_execute_noalloc
+constexpr int kNoallocMaxDevices = 64;
+
+// device address of this device's no-allocation scratch array (looked up
+// once per device, with the device current)
+hipError_t noalloc_scratch(void **out);
 
 size_t spread_lds_bytes(const Geo &g, int ncg);
 size_t gather_lds_bytes(const Geo &g, int ncg);

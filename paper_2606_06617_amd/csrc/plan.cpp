@@ -648,9 +648,10 @@ namespace {
 struct StageRunner {
   pswflr_plan_s *pl;
   hipStream_t st;
+  bool timing = true;  // false: never create timing events (allocation-free calls)
   template <class F>
   hipError_t operator()(int stage, F &&f) {
-    if (!pl->prof) return f();
+    if (!pl->prof || !timing) return f();
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return hipErrorOutOfMemory;
     (void)hipEventRecord(a, st);
@@ -663,8 +664,8 @@ struct StageRunner {
 };
 
 hipError_t run_forward(pswflr_plan_s *pl, hipStream_t st, const Geo &g, const Work &w, const float *pos,
-                       const float *q, int xmode, double *energy, double *virial) {
-  StageRunner run{pl, st};
+                       const float *q, int xmode, double *energy, double *virial, bool timing = true) {
+  StageRunner run{pl, st, timing};
   const Tables &t = pl->tab;
   hipError_t e;
   if ((e = run(PSWFLR_STAGE_SORT, [&] { return enqueue_sort(g, w, pos, q, st); })) != hipSuccess) return e;
@@ -683,8 +684,8 @@ hipError_t run_forward(pswflr_plan_s *pl, hipStream_t st, const Geo &g, const Wo
 }
 
 hipError_t run_adjoint(pswflr_plan_s *pl, hipStream_t st, const Geo &g, const Work &w, float *forces,
-                       float *pot, int mode, const double *grad) {
-  StageRunner run{pl, st};
+                       float *pot, int mode, const double *grad, bool timing = true) {
+  StageRunner run{pl, st, timing};
   const Tables &t = pl->tab;
   hipError_t e;
   if (mode == 2) {
@@ -728,6 +729,33 @@ pswflr_status pswflr_execute(pswflr_plan plan, pswflr_stream stream, void *works
   hipError_t e = run_forward(plan, st, g, w, pos, q, adjoint ? 1 : 0, energy, virial);
   if (e == hipSuccess && adjoint) e = run_adjoint(plan, st, g, w, forces, potential, 1, nullptr);
   if (e == hipSuccess) e = mark_use(st, &plan, 1);
+  if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return PSWFLR_OK;
+}
+
+pswflr_status pswflr_execute_noalloc(pswflr_plan plan, pswflr_stream stream, int64_t n_atoms, const float *pos,
+                                     const float *q, double *energy, float *forces, double *virial,
+                                     float *potential) {
+  if (!plan) return fail(PSWFLR_ERR_INVALID_ARG, "plan is NULL");
+  if (plan->ws_bytes > kNoallocScratchBytes)
+    return fail(PSWFLR_ERR_WORKSPACE, "the plan's workspace (" + std::to_string(plan->ws_bytes) +
+                                          " B for its max_atoms) exceeds the no-allocation scratch of " +
+                                          std::to_string(kNoallocScratchBytes) + " B");
+  if (plan->prm.flags & PSWFLR_FLAG_CHECK_INPUTS)
+    return fail(PSWFLR_ERR_INVALID_ARG, "the input check waits on the host; use pswflr_execute");
+  void *scratch = nullptr;
+  hipError_t e = noalloc_scratch(&scratch);
+  if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("scratch lookup failed: ") + hipGetErrorString(e));
+  pswflr_status s = check_call(plan, scratch, kNoallocScratchBytes, n_atoms, pos, q);
+  if (s != PSWFLR_OK) return s;
+  if (!energy) return fail(PSWFLR_ERR_INVALID_ARG, "energy output is required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Geo g = plan->geo;
+  g.N = n_atoms;
+  Work w = carve(*plan, scratch, n_atoms);
+  const bool adjoint = forces || potential;
+  e = run_forward(plan, st, g, w, pos, q, adjoint ? 1 : 0, energy, virial, false);
+  if (e == hipSuccess && adjoint) e = run_adjoint(plan, st, g, w, forces, potential, 1, nullptr, false);
   if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return PSWFLR_OK;
 }
