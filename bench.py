@@ -183,41 +183,53 @@ def serving_leg(nreq=400, seed=6, fractions=(0.5, 0.8, 0.95), slots=4):
     return out
 
 
-def cpu_baseline(w, n_sample=128):
-    """The FP64 oracle (direct structure-factor sum over the same k-ball with
-    energy, forces and virial) timed single-threaded on a bounded sample:
-    one channel of each distinct exponent, first with no atoms (the fixed
-    cost of enumerating the k-ball and evaluating the kernels) and then with
-    the first n_sample atoms (the per-atom cost).  The oracle's cost is
-    linear in atoms and channels, so the full-frame time is
-    (C / C_s) (t_0 + N (t_n - t_0) / n), and value = N / that."""
+def _oracle_channel_timing(args):
+    """One worker of the CPU baseline: the FP64 direct sum (E, F, W) of one
+    channel on 0 and on n atoms, single-threaded; returns both times."""
+    pos, q, box, p = args
     from threadpoolctl import threadpool_limits
 
     from oracle import reciprocal
-
-    chans = []
-    for i, p in enumerate(w["ps"]):
-        if p not in [w["ps"][j] for j in chans]:
-            chans.append(i)
-    ps = [w["ps"][i] for i in chans]
-
-    def run(n):
-        pos = w["pos"][:n].astype(np.float64)
-        q = w["q"][chans, :n].astype(np.float64)
-        t0 = time.perf_counter()
-        reciprocal.evaluate(pos, q, w["box"], ps, C_MOL, R_C)
-        return time.perf_counter() - t0
-
     with threadpool_limits(limits=1):
-        t0 = run(0)
-        tn = run(n_sample)
+        t0 = time.perf_counter()
+        reciprocal.evaluate(pos[:0], q[:, :0], box, [p], C_MOL, R_C)
+        t1 = time.perf_counter()
+        reciprocal.evaluate(pos, q, box, [p], C_MOL, R_C)
+        t2 = time.perf_counter()
+    return t1 - t0, t2 - t1
+
+
+def cpu_baseline(w, n_sample=128):
+    """The FP64 oracle (the direct structure-factor sum over the k-ball with
+    energy, forces and virial) timed on the host's cores: channels are
+    independent evaluations, so one worker process per channel (up to the
+    cores this process may run on, os.sched_getaffinity), each timing its
+    channel with no atoms (the fixed cost of the k-ball) and with the first
+    n_sample atoms.  The oracle's cost is linear in atoms, so a channel of
+    the full frame takes t_0 + N (t_n - t_0) / n; the frame takes the
+    slowest worker's channel time for every round of workers the channels
+    need, and value = N / that."""
+    import multiprocessing as mp
+
     N, C = w["pos"].shape[0], len(w["ps"])
-    full = (C / len(chans)) * (t0 + N * (tn - t0) / n_sample)
-    return {"value": N / full, "unit": "atoms/s", "cores": 1, "kind": "oracle",
-            "sample": ("channels %s (one per exponent p=%s) with 0 and the first %d atoms, full k-ball "
-                       "|k|<=c/r_c, E+F+W, FP64 numpy on 1 thread: t_0=%.2f s, t_n=%.2f s; "
-                       "extrapolated to %d atoms x %d channels = %.3g s"
-                       % (chans, ps, n_sample, t0, tn, N, C, full))}
+    ncores = len(os.sched_getaffinity(0))
+    workers = max(1, min(C, ncores))
+    pos = np.ascontiguousarray(w["pos"][:n_sample].astype(np.float64))
+    tasks = [(pos, w["q"][c:c + 1, :n_sample].astype(np.float64), np.asarray(w["box"]), w["ps"][c])
+             for c in range(workers)]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        times = pool.map(_oracle_channel_timing, tasks)
+    per_chan = max(t0 + N * (tn - t0) / n_sample for t0, tn in times)
+    rounds = -(-C // workers)
+    full = rounds * per_chan
+    return {"value": N / full, "unit": "atoms/s", "cores": workers, "kind": "oracle",
+            "sample": ("FP64 direct sum over the k-ball |k|<=c/r_c, E+F+W, one single-threaded worker per channel "
+                       "(%d workers on %d available cores, channels %d..%d, p=%s), each timed on 0 and the first %d "
+                       "atoms (t_0 %.2f-%.2f s, t_n %.2f-%.2f s); extrapolated linearly to %d atoms: %.3g s per "
+                       "channel, %d round(s) for %d channels = %.3g s"
+                       % (workers, ncores, 0, workers - 1, sorted(set(w["ps"][:workers])), n_sample,
+                          min(t[0] for t in times), max(t[0] for t in times), min(t[1] for t in times),
+                          max(t[1] for t in times), N, per_chan, rounds, C, full))}
 
 
 def main():
