@@ -610,10 +610,12 @@ constexpr int kSpreadCap = 256;     // candidates staged per flush
 constexpr int kSpreadScreenPer = 1; // atoms screened per thread per round
 constexpr int kSpreadList = kSpreadCap + kSpreadScreenPer * 512;  // screened-candidate list
 constexpr int kSpreadMaxCells = 64; // candidate cells of a tile
-constexpr int kSpreadCGM = 12;      // channels per launch (most)
-// accumulator counts the spread is instantiated for: 2, 4 or 12
+constexpr int kSpreadCGM = 16;      // channels per launch (most)
+// accumulator counts the spread is instantiated for: 2 or 4 channels on the
+// vector ALUs, up to 16 on the matrix cores
 __host__ __device__ constexpr int spread_cg4(int cg) { return (cg + 3) / 4 * 4; }
 __host__ __device__ constexpr int spread_cg_template(int ncg) { return ncg <= 2 ? 2 : (ncg <= 4 ? 4 : kSpreadCGM); }
+__host__ __device__ constexpr bool spread_mfma(int cg) { return cg == kSpreadCGM; }
 constexpr int kSpreadNBW = 4;       // 4x4x4 blocks per wave
 constexpr int kSpreadMaxS = 64;     // padded tile edges Sx + Sy + Sz
 constexpr int kSpreadBias = 8;      // packed window offsets are stored + bias
@@ -674,6 +676,21 @@ __device__ __forceinline__ void spread_load(const float *cw, int S, int kk, int 
   }
 }
 
+typedef float spread_f4 __attribute__((ext_vector_type(4)));
+// Accumulators of a lane.  Vector-ALU variants: one per point of each of
+// the wave's four blocks and per channel.  Matrix-core variant: per block
+// and x slice of it, the lane's part of a 16 x 16 product tile (16 points of
+// the 4 x 4 (y, z) slice by 16 channels): rows 4 (lane / 16) .. + 3, i.e.
+// y = lane / 16 and z = 0..3, of channel lane % 16.
+template <int CG>
+struct SpreadAcc {
+  float v[kSpreadNBW][CG];
+};
+template <>
+struct SpreadAcc<kSpreadCGM> {
+  spread_f4 v[kSpreadNBW][4];
+};
+
 __device__ __forceinline__ int spread_take(unsigned long long &u) {
   const int bit = __builtin_ctzll(u);
   u &= u - 1ull;
@@ -710,14 +727,15 @@ template <int P, int NBZ, int CG>
 __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg0, int ncg, int ncand, const int *sz,
                                              float *cq, float *cw, const int *cd, const float *cf, const int *ci,
                                              const float *wcf, const int (&bo)[3], bool wval,
-                                             float (&acc)[kSpreadNBW][CG]) {
+                                             SpreadAcc<CG> &accs) {
   constexpr int CPW = kSpreadNBW / NBZ;
+  constexpr bool MF = spread_mfma(CG);
   const int tid = threadIdx.x, lane = tid & 63;
   const int S = sz[0] + sz[1] + sz[2];
   const int soff[3] = {0, sz[0], sz[0] + sz[1]};
   // (1) per candidate and axis, the window weights over the padded tile
-  // edge (zero outside the window); z position zz is stored at
-  // (zz % 4) NBZ + zz / 4.  The window positions of one candidate are
+  // edge (zero outside the window); for the vector-ALU variants z position
+  // zz is stored at (zz % 4) NBZ + zz / 4.  The window positions of one candidate are
   // distinct (P <= M), so they are plain stores after a zero fill whose
   // start rotates with the candidate (no bank conflicts between lanes).
   for (int t = tid; t < 3 * kSpreadCap; t += kSpreadThreads) {
@@ -745,7 +763,7 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
       int x = d + l;
       if (x < 0) x += Ma;
       if (x >= Ma) x -= Ma;
-      if (x < Ba) dst[a == 2 ? (x & 3) * NBZ + (x >> 2) : x] = win_eval(wcf, (2.0f * (l + r)) / P - 1.0f);
+      if (x < Ba) dst[(a == 2 && !MF) ? (x & 3) * NBZ + (x >> 2) : x] = win_eval(wcf, (2.0f * (l + r)) / P - 1.0f);
     }
     if (a == 0) {
 #pragma unroll
@@ -782,10 +800,43 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
       m[j] = __ballot(valid && inx && iny[j / NBZ] && inz[j % NBZ]);
       u |= m[j];
     }
+    if (!u) continue;
+    if constexpr (MF) {
+      // matrix cores: per block, the hits in groups of four; one 16x16x4
+      // product per x slice: (16 points of the slice) x (4 hits) weights
+      // times (4 hits) x (16 channels) charges.  Lane l supplies the weight
+      // of point l % 16 for hit l / 16 and the charge of channel l % 16 of
+      // hit l / 16; a group short of four hits repeats its first hit with
+      // zero charges.
+      const int i16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+      for (int j = 0; j < kSpreadNBW; ++j) {
+        unsigned long long uj = m[j];
+        const int yo = soff[1] + bo[1] + 4 * (j / NBZ) + (i16 >> 2);
+        const int zo = soff[2] + 4 * (j % NBZ) + (i16 & 3);
+        while (uj) {
+          const int b0 = spread_take(uj);
+          const int b1 = uj ? spread_take(uj) : 64;
+          const int b2 = uj ? spread_take(uj) : 64;
+          const int b3 = uj ? spread_take(uj) : 64;
+          const int mine = kq == 0 ? b0 : (kq == 1 ? b1 : (kq == 2 ? b2 : b3));
+          const bool ok = mine < 64;
+          const int kk = k0 + (ok ? mine : b0);
+          const float *row = cw + kk * S;
+          const float4 wx4 = *reinterpret_cast<const float4 *>(row + bo[0]);
+          const float wyz = row[yo] * row[zo];
+          const float qv = ok ? cq[kk * kSpreadCGM + i16] : 0.0f;
+          accs.v[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx4.x * wyz, qv, accs.v[j][0], 0, 0, 0);
+          accs.v[j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx4.y * wyz, qv, accs.v[j][1], 0, 0, 0);
+          accs.v[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx4.z * wyz, qv, accs.v[j][2], 0, 0, 0);
+          accs.v[j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx4.w * wyz, qv, accs.v[j][3], 0, 0, 0);
+        }
+      }
+    } else {
+    auto &acc = accs.v;
     // software-pipelined walk over the hits, unrolled by two with two
     // register sets: the LDS reads of the next hit are in flight while the
     // current one is accumulated
-    if (!u) continue;
     float qreg[spread_cg4(CG)];
     {
       const int kq = min(k, ncand - 1);
@@ -815,6 +866,7 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
       spread_load<NBZ>(cw, S, k0 + ba, xa, ya, za, ca);
       spread_accumulate<NBZ, CG>(cb, bb, qreg, m, acc);
       if (!ha) break;
+    }
     }
   }
   __syncthreads();
@@ -852,11 +904,18 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   const int col0 = wave * CPW;
   const bool wval = col0 < ncol;
   const int bo[3] = {wval ? (col0 / nby) * 4 : 0, wval ? (col0 % nby) * 4 : 0, 0};
-  float acc[kSpreadNBW][CG];
+  constexpr bool MF = spread_mfma(CG);
+  SpreadAcc<CG> acc;
 #pragma unroll
-  for (int j = 0; j < kSpreadNBW; ++j)
+  for (int j = 0; j < kSpreadNBW; ++j) {
+    if constexpr (MF) {
 #pragma unroll
-    for (int c = 0; c < CG; ++c) acc[j][c] = 0.0f;
+      for (int sl = 0; sl < 4; ++sl) acc.v[j][sl] = spread_f4{0.0f, 0.0f, 0.0f, 0.0f};
+    } else {
+#pragma unroll
+      for (int c = 0; c < CG; ++c) acc.v[j][c] = 0.0f;
+    }
+  }
 
   // candidate cells: this tile's cell and the ones before it along each
   // axis that can hold a window start reaching into the tile.  Their atom
@@ -1007,14 +1066,35 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   for (int c0 = 0; c0 < ncg; c0 += cpp) {
     const int nc = min(cpp, ncg - c0);
     if (wval) {
+      if constexpr (MF) {
+        // lane: channel lane % 16, row y = lane / 16 of the slice, z = 0..3
+        const int ch = (lane & 15) - c0, y0 = lane >> 4;
+        if (ch >= 0 && ch < nc) {
 #pragma unroll
-      for (int j = 0; j < kSpreadNBW; ++j) {
-        const int x = bo[0] + lx, y = bo[1] + 4 * (j / NBZ) + ly, z = 4 * (j % NBZ) + lz;
-        if (x < Bx && y < By && z < Bz) {
-          float *dst = stage + (x * By + y) * Bz + z;
+          for (int j = 0; j < kSpreadNBW; ++j) {
+            const int y = bo[1] + 4 * (j / NBZ) + y0, z0 = 4 * (j % NBZ);
 #pragma unroll
-          for (int cc = 0; cc < CG; ++cc)
-            if (cc >= c0 && cc < c0 + nc) dst[(cc - c0) * nt] = acc[j][cc];
+            for (int sl = 0; sl < 4; ++sl) {
+              const int x = bo[0] + sl;
+              if (x < Bx && y < By) {
+                float *dst = stage + ch * nt + (x * By + y) * Bz + z0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                  if (z0 + r < Bz) dst[r] = acc.v[j][sl][r];
+              }
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < kSpreadNBW; ++j) {
+          const int x = bo[0] + lx, y = bo[1] + 4 * (j / NBZ) + ly, z = 4 * (j % NBZ) + lz;
+          if (x < Bx && y < By && z < Bz) {
+            float *dst = stage + (x * By + y) * Bz + z;
+#pragma unroll
+            for (int cc = 0; cc < CG; ++cc)
+              if (cc >= c0 && cc < c0 + nc) dst[(cc - c0) * nt] = acc.v[j][cc];
+          }
         }
       }
     }
