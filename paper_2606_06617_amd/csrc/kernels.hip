@@ -625,9 +625,13 @@ constexpr int kSpreadOutMax = (kSpreadMaxPts + kSpreadThreads - 1) / kSpreadThre
 // LDS floats of the candidate staging area (charges and weights) for padded
 // edges summing to S; the screened-candidate list, the candidate-cell table
 // and the window coefficients follow it
-__host__ __device__ __forceinline__ int spread_stage_floats(int S) { return kSpreadCap * (kSpreadCGM + S); }
+// (one row past the staged candidates holds zeros: the padding of the
+// matrix-core hit groups points there)
+constexpr int kSpreadHitList = 68;  // per wave and block: 64 hits padded to whole groups of four
+__host__ __device__ __forceinline__ int spread_stage_floats(int S) { return (kSpreadCap + 1) * (kSpreadCGM + S); }
 __host__ __device__ __forceinline__ int spread_lds_floats(int S) {
-  return spread_stage_floats(S) + 5 * kSpreadList + 2 * kSpreadMaxCells + 1 + 3 + kWinSeg * (kWinDeg + 1);
+  return spread_stage_floats(S) + 5 * kSpreadList + 2 * kSpreadMaxCells + 1 + 3 + kWinSeg * (kWinDeg + 1) +
+         2 * kSpreadCap + (kSpreadThreads / 64) * kSpreadNBW * kSpreadHitList / 2;
 }
 __host__ __device__ __forceinline__ int spread_pad4(int b) { return (b + 3) & ~3; }
 // blocks along z of a tile edge (1, 2 or 4 supported); 0 if unsupported
@@ -726,8 +730,8 @@ __device__ __forceinline__ void spread_accumulate(const SpreadCand<NBZ> &cnd, in
 template <int P, int NBZ, int CG>
 __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg0, int ncg, int ncand, const int *sz,
                                              float *cq, float *cw, const int *cd, const float *cf, const int *ci,
-                                             const float *wcf, const int (&bo)[3], bool wval,
-                                             SpreadAcc<CG> &accs) {
+                                             const float *wcf, const int (&bo)[3], bool wval, unsigned short *cbits,
+                                             unsigned short *hl, SpreadAcc<CG> &accs) {
   constexpr int CPW = kSpreadNBW / NBZ;
   constexpr bool MF = spread_mfma(CG);
   const int tid = threadIdx.x, lane = tid & 63;
@@ -758,13 +762,18 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
       if (++xx == sa) xx = 0;
     }
     const int Ma = g.M[a], Ba = g.B[a];
+    unsigned bits = 0;  // 4-point blocks of this axis the window reaches
 #pragma unroll
     for (int l = 0; l < P; ++l) {
       int x = d + l;
       if (x < 0) x += Ma;
       if (x >= Ma) x -= Ma;
-      if (x < Ba) dst[(a == 2 && !MF) ? (x & 3) * NBZ + (x >> 2) : x] = win_eval(wcf, (2.0f * (l + r)) / P - 1.0f);
+      if (x < Ba) {
+        dst[(a == 2 && !MF) ? (x & 3) * NBZ + (x >> 2) : x] = win_eval(wcf, (2.0f * (l + r)) / P - 1.0f);
+        bits |= 1u << (x >> 2);
+      }
     }
+    cbits[4 * k + a] = static_cast<unsigned short>(bits);
     if (a == 0) {
 #pragma unroll
       for (int c = 0; c < spread_cg4(CG); c += 4)
@@ -777,6 +786,63 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
   // (2) accumulate: 64 candidates per ballot, scalar walk over the hits
   const int lx = lane >> 4, ly = (lane >> 2) & 3, lz = lane & 3;
   const int xa = (bo[0] + lx) * 4, ya = (soff[1] + bo[1] + ly) * 4, za = (soff[2] + lz * NBZ) * 4;
+  if constexpr (MF) {
+    // Matrix cores.  Per 64 candidates, each of the wave's blocks gets the
+    // list of candidates whose window meets it (from the per-axis block bits
+    // of the staging), padded to whole groups of four with the zero row; the
+    // groups of all four blocks are walked as one sequence.  A group is one
+    // 16x16x4 product per x slice of its block: (16 points of the slice) x
+    // (4 hits) weights times (4 hits) x (16 channels) charges; lane l
+    // supplies the weight of point l % 16 for hit l / 16 and the charge of
+    // channel l % 16 of hit l / 16.  The next group's index and operands are
+    // read while the current group's products run.
+    const int i16 = lane & 15, kq = lane >> 4;
+    unsigned short *hw = hl + __builtin_amdgcn_readfirstlane(tid >> 6) * (kSpreadNBW * kSpreadHitList);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int bxi = bo[0] >> 2, byi = bo[1] >> 2;
+    for (int k0 = 0; k0 < ncand; k0 += 64) {
+      const int k = k0 + lane;
+      const bool valid = wval && k < ncand;
+      const uint2 bv = valid ? *reinterpret_cast<const uint2 *>(cbits + 4 * k) : make_uint2(0u, 0u);
+      const bool inx = (bv.x >> bxi) & 1u;
+      int ng[kSpreadNBW], tot = 0;
+#pragma unroll
+      for (int j = 0; j < kSpreadNBW; ++j) {
+        const bool hit = inx && ((bv.x >> (16 + byi + j / NBZ)) & 1u) && ((bv.y >> (j % NBZ)) & 1u);
+        const unsigned long long mj = __ballot(hit);
+        const int n = __popcll(mj);
+        if (hit) hw[4 * tot + __popcll(mj & below)] = static_cast<unsigned short>(k);
+        const int pad = (4 - (n & 3)) & 3;
+        if (lane < pad) hw[4 * tot + n + lane] = static_cast<unsigned short>(kSpreadCap);
+        ng[j] = (n + 3) >> 2;
+        tot += ng[j];
+      }
+      if (tot == 0) continue;
+      // the groups of the four blocks lie one after another in the list;
+      // the index of the next group is read one group ahead, and the
+      // operand reads of a group overlap the previous group's products
+      int t = 0;
+      int idx = hw[kq];
+      int idxn = tot > 1 ? hw[4 + kq] : kSpreadCap;
+#pragma unroll
+      for (int j = 0; j < kSpreadNBW; ++j) {
+        const int yoff = soff[1] + bo[1] + 4 * (j / NBZ) + (i16 >> 2);
+        const int zoff = soff[2] + 4 * (j % NBZ) + (i16 & 3);
+        for (int gq = 0; gq < ng[j]; ++gq, ++t) {
+          const float *row = cw + __umul24(idx, S);
+          const float4 wx4 = *reinterpret_cast<const float4 *>(row + bo[0]);
+          const float wyz = row[yoff] * row[zoff];
+          const float qv = cq[idx * kSpreadCGM + i16];
+          idx = idxn;
+          idxn = t + 2 < tot ? hw[4 * (t + 2) + kq] : kSpreadCap;
+          accs.v[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx4.x * wyz, qv, accs.v[j][0], 0, 0, 0);
+          accs.v[j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx4.y * wyz, qv, accs.v[j][1], 0, 0, 0);
+          accs.v[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx4.z * wyz, qv, accs.v[j][2], 0, 0, 0);
+          accs.v[j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx4.w * wyz, qv, accs.v[j][3], 0, 0, 0);
+        }
+      }
+    }
+  } else {
   for (int k0 = 0; k0 < ncand; k0 += 64) {
     const int k = k0 + lane;
     const bool valid = wval && k < ncand;
@@ -801,38 +867,7 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
       u |= m[j];
     }
     if (!u) continue;
-    if constexpr (MF) {
-      // matrix cores: per block, the hits in groups of four; one 16x16x4
-      // product per x slice: (16 points of the slice) x (4 hits) weights
-      // times (4 hits) x (16 channels) charges.  Lane l supplies the weight
-      // of point l % 16 for hit l / 16 and the charge of channel l % 16 of
-      // hit l / 16; a group short of four hits repeats its first hit with
-      // zero charges.
-      const int i16 = lane & 15, kq = lane >> 4;
-#pragma unroll
-      for (int j = 0; j < kSpreadNBW; ++j) {
-        unsigned long long uj = m[j];
-        const int yo = soff[1] + bo[1] + 4 * (j / NBZ) + (i16 >> 2);
-        const int zo = soff[2] + 4 * (j % NBZ) + (i16 & 3);
-        while (uj) {
-          const int b0 = spread_take(uj);
-          const int b1 = uj ? spread_take(uj) : 64;
-          const int b2 = uj ? spread_take(uj) : 64;
-          const int b3 = uj ? spread_take(uj) : 64;
-          const int mine = kq == 0 ? b0 : (kq == 1 ? b1 : (kq == 2 ? b2 : b3));
-          const bool ok = mine < 64;
-          const int kk = k0 + (ok ? mine : b0);
-          const float *row = cw + kk * S;
-          const float4 wx4 = *reinterpret_cast<const float4 *>(row + bo[0]);
-          const float wyz = row[yo] * row[zo];
-          const float qv = ok ? cq[kk * kSpreadCGM + i16] : 0.0f;
-          accs.v[j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx4.x * wyz, qv, accs.v[j][0], 0, 0, 0);
-          accs.v[j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx4.y * wyz, qv, accs.v[j][1], 0, 0, 0);
-          accs.v[j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx4.z * wyz, qv, accs.v[j][2], 0, 0, 0);
-          accs.v[j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(wx4.w * wyz, qv, accs.v[j][3], 0, 0, 0);
-        }
-      }
-    } else {
+    {
     auto &acc = accs.v;
     // software-pipelined walk over the hits, unrolled by two with two
     // register sets: the LDS reads of the next hit are in flight while the
@@ -869,6 +904,7 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
     }
     }
   }
+  }
   __syncthreads();
 }
 
@@ -879,18 +915,23 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
   const int sz[3] = {spread_pad4(Bx), spread_pad4(By), spread_pad4(Bz)};
   const int S = sz[0] + sz[1] + sz[2];
-  float *cq = smem;                                                 // [cap][CGM]
-  float *cw = cq + kSpreadCap * kSpreadCGM;                         // [cap][S]
-  float *lf = cw + kSpreadCap * S;                                  // [list][3] window offsets delta
+  float *cq = smem;                                                 // [cap + 1][CGM]
+  float *cw = cq + (kSpreadCap + 1) * kSpreadCGM;                   // [cap + 1][S]
+  float *lf = cw + (kSpreadCap + 1) * S;                            // [list][3] window offsets delta
   int *ld = reinterpret_cast<int *>(lf + 3 * kSpreadList);          // [list] packed window starts
   int *li = ld + kSpreadList;                                       // [list] atom index
   int *rb = li + kSpreadList;                                       // [cells] first atom of a candidate cell
   int *rs = rb + kSpreadMaxCells;                                   // [cells + 1] prefix of their sizes
   float *wcf = smem + ((int(reinterpret_cast<float *>(rs + kSpreadMaxCells + 1) - smem) + 3) & ~3);  // window coefficients, 16-byte aligned
+  unsigned short *cbits = reinterpret_cast<unsigned short *>(wcf + kWinSeg * (kWinDeg + 1));  // [cap][4] block bits per axis
+  unsigned short *hl = cbits + 4 * kSpreadCap;                      // [waves][blocks][68] hit lists
   // (the write-out stage below reuses the cq and cw area)
   __shared__ int wcount[kSpreadScreenPer * (kSpreadThreads / 64)];
 
   const int tid = threadIdx.x, lane = tid & 63;
+  // the zero row past the staged candidates (padding of the hit groups)
+  for (int e = tid; e < kSpreadCGM; e += kSpreadThreads) cq[kSpreadCap * kSpreadCGM + e] = 0.0f;
+  for (int e = tid; e < S; e += kSpreadThreads) cw[kSpreadCap * S + e] = 0.0f;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps block bookkeeping scalar
   const int cell = bx;
   const int cz = cell % g.nc[2], cy = (cell / g.nc[2]) % g.nc[1], cx = cell / (g.nc[2] * g.nc[1]);
@@ -1013,7 +1054,8 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
     const bool last = base + kSpreadScreenPer * kSpreadThreads >= total;
     while (nlist - c0 >= kSpreadCap || (last && c0 < nlist)) {
       const int n = min(kSpreadCap, nlist - c0);
-      spread_flush<P, NBZ, CG>(g, w, cg0, ncg, n, sz, cq, cw, ld + c0, lf + 3 * c0, li + c0, wcf, bo, wval, acc);
+      spread_flush<P, NBZ, CG>(g, w, cg0, ncg, n, sz, cq, cw, ld + c0, lf + 3 * c0, li + c0, wcf, bo, wval, cbits, hl,
+                               acc);
       c0 += n;
     }
     // keep the unflushed tail (fewer than kSpreadCap <= threads entries)
