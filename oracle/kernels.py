@@ -149,6 +149,33 @@ def mollifier(p, r, c, r_c):
     return np.where(inside, g, 1.0)
 
 
+def mollifier_deriv(p, r, c, r_c):
+    """dG_p/dr of mollifier(): the rho-derivative of Eqs. G1, G6, G divided
+    by r_c (each term differentiated by the product rule; G_p' = 0 for
+    r >= r_c)."""
+    ps = pswf(c)
+    r = np.asarray(r, dtype=np.float64)
+    rho = r / r_c
+    inside = rho < 1.0
+    x = np.where(inside, rho, 0.0)
+    psi, d1, d2 = ps(x), ps.d1(x), ps.d2(x)
+    if p == 1:
+        g = psi / ps.C0
+    elif p == 2:
+        g = -d1
+    elif p == 3:
+        g = -x * d1 / ps.C0
+    elif p == 4:
+        g = -0.5 * d1 + 0.5 * x * d2
+    elif p == 5:
+        g = (-x * d1 / 3.0 + x * x * d2 / 3.0) / ps.C0
+    elif p == 6:
+        g = -3.0 * d1 / 8.0 + 3.0 * x * d2 / 8.0 - x * x * ps.d3(x) / 8.0
+    else:
+        raise ValueError("p must be in 1..6")
+    return np.where(inside, g / r_c, 0.0)
+
+
 def self_coefficient(p, c, r_c):
     """s_p with E_self^(p) = s_p * sum_i q_i^2 (Methods, self-correction term)."""
     ps = pswf(c)

@@ -58,6 +58,7 @@ class PSWF:
         self.C0 = 0.5 * self.lam
         self._d1 = npleg.legder(coef, 1)
         self._d2 = npleg.legder(coef, 2)
+        self._d3 = npleg.legder(coef, 3)
         self._int = npleg.legint(coef, lbnd=0.0)            # int_0^x psi
         self._int_x = npleg.legint(npleg.legmulx(coef), lbnd=0.0)   # int_0^x u psi
         x3 = npleg.legmulx(npleg.legmulx(npleg.legmulx(coef)))
@@ -73,6 +74,9 @@ class PSWF:
 
     def d2(self, x):
         return npleg.legval(np.asarray(x, dtype=np.float64), self._d2)
+
+    def d3(self, x):
+        return npleg.legval(np.asarray(x, dtype=np.float64), self._d3)
 
     def deriv_at_zero(self, n):
         """n-th derivative of psi_0^c at 0, from the Legendre series."""

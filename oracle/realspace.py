@@ -12,8 +12,18 @@ complete decomposition of Eq. realLR:
 with G_p from Eqs. G1, G6, G and the prime excluding i = j at n = 0.
 1 - G_p vanishes for r >= r_c, so only images within r_c contribute.
 
-Pins: used only inside the total-energy pins (Madelung, splitting
-independence, brute force, Ewald) of tests/test_oracle_invariants.py.
+`evaluate` gives, per channel, E_real and the potentials
+phi_i = dE_real/dq_i = sum_{j,n}' q_j K(r), and in total over channels the
+forces F_i = sum_{j,n}' q_i q_j K'(r) d / r (d = r_j + n L - r_i) and the
+virial W = -1/2 sum_i sum_{j,n}' q_i q_j K'(r) d d^T / r, with
+K(r) = (1 - G_p(r)) / r^p and K'(r) = -G_p'(r) / r^p - p K(r) / r.
+
+Pins: the total-energy pins (Madelung, splitting independence, brute force,
+Ewald) of tests/test_oracle_invariants.py; evaluate's energy against
+real_energy (an independent loop), its forces against central finite
+differences of the energy, its virial against finite differences under
+affine strain, its potentials against the quadratic form E = 1/2 sum q phi
+and against finite differences in q (tests/test_oracle_realspace.py).
 """
 import numpy as np
 
@@ -44,6 +54,45 @@ def real_energy(pos, q, box, p, c, r_c):
                 rr = r[mask]
                 E += 0.5 * np.sum(qq[mask] * (1.0 - kernels.mollifier(p, rr, c, r_c)) / rr ** p)
     return E
+
+
+def evaluate(pos, q, box, ps, c, r_c):
+    """All channels of the real-space complement.  q is [C, N].
+
+    Returns Ereal [C], phi [C, N], F [N, 3] and W [3, 3] (sums over channels)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.atleast_2d(np.asarray(q, dtype=np.float64))
+    box = np.asarray(box, dtype=np.float64)
+    C, n = q.shape
+    nimg = np.ceil(r_c / box).astype(int) + 1
+    d0 = pos[None, :, :] - pos[:, None, :]     # d0[i, j] = r_j - r_i
+    d0 -= box * np.round(d0 / box)
+    E = np.zeros(C)
+    phi = np.zeros((C, n))
+    F = np.zeros((n, 3))
+    W = np.zeros((3, 3))
+    for ix in range(-nimg[0], nimg[0] + 1):
+        for iy in range(-nimg[1], nimg[1] + 1):
+            for iz in range(-nimg[2], nimg[2] + 1):
+                d = d0 + np.array([ix, iy, iz], dtype=np.float64) * box
+                r = np.sqrt(np.sum(d * d, axis=2))
+                mask = (r < r_c) & (r > 0.0)
+                if not np.any(mask):
+                    continue
+                ii, jj = np.nonzero(mask)
+                rr = r[mask]
+                dd = d[mask]
+                for ch in range(C):
+                    p = int(ps[ch])
+                    K = (1.0 - kernels.mollifier(p, rr, c, r_c)) / rr ** p
+                    Kd = -kernels.mollifier_deriv(p, rr, c, r_c) / rr ** p - p * K / rr
+                    np.add.at(phi[ch], ii, q[ch, jj] * K)
+                    s = q[ch, ii] * q[ch, jj] * Kd / rr
+                    np.add.at(F, ii, s[:, None] * dd)
+                    W -= 0.5 * np.einsum("k,ka,kb->ab", s, dd, dd)
+    for ch in range(C):
+        E[ch] = 0.5 * float(np.sum(q[ch] * phi[ch]))
+    return {"Ereal": E, "phi": phi, "F": F, "W": W}
 
 
 def total_energy(pos, q, box, p, c, r_c):
