@@ -165,6 +165,25 @@ pswflr_status pswflr_execute(pswflr_plan plan, pswflr_stream stream, void *works
                              const float *q, double *energy, float *forces,
                              double *virial, float *potential);
 
+/* The real-space complement of the split (Eq. realLR; Methods,
+ * "Implementation details"): for each channel c,
+ *   E_real^(c) = 1/2 sum_n sum'_{i,j} q_i q_j (1 - G_p(r)) / r^p,
+ * r = |r_j - r_i + n L| < r_c over all periodic images n (the prime drops
+ * i = j at n = 0), with G_p the PSWF mollifier of Eqs. G1, G6, G at the
+ * plan's c and r_c.  Together with pswflr_execute this gives the complete
+ * energy of Eq. realLR: E = sum_c (E_real + E_k + E_0 - E_self).
+ *   energy    [C] double (required): E_real per channel
+ *   forces    [N][3] float or NULL: -dE_real/dr_i summed over channels
+ *   virial    [6] double or NULL: -dE_real/d(strain), order as execute
+ *   potential [C][N] float or NULL: dE_real/dq_i^(c)
+ * Same plan, workspace (its real-space part: an execute's results in the
+ * same workspace, spectrum included, are left intact), stream semantics and
+ * errors as pswflr_execute.  Pairs at zero distance are skipped. */
+pswflr_status pswflr_realspace(pswflr_plan plan, pswflr_stream stream, void *workspace,
+                               size_t ws_bytes, int64_t n_atoms, const float *pos,
+                               const float *q, double *energy, float *forces,
+                               double *virial, float *potential);
+
 /* pswflr_execute without a caller workspace, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid allocation).  Same arguments and results as

@@ -107,6 +107,24 @@ class Plan:
         _lib.check(st)
         return {"energy": energy, "forces": F, "virial": W, "potential": phi, "workspace": ws}
 
+    def realspace(self, pos, q, forces=True, virial=True, potential=False, workspace=None, stream=None):
+        """Real-space complement of the split: energy [C] (E_real per
+        channel), forces [N,3], virial [6] and potentials [C,N] of
+        1/2 sum q_i q_j (1 - G_p(r)) / r^p over pairs closer than r_c."""
+        _check_inputs(pos, q, self.C, self.max_atoms)
+        N = pos.shape[0]
+        dev = pos.device
+        with (torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()):
+            ws = workspace if workspace is not None else self.new_workspace(dev)
+            energy = torch.empty(self.C, dtype=torch.float64, device=dev)
+            F = torch.empty((N, 3), dtype=torch.float32, device=dev) if forces else None
+            W = torch.empty(6, dtype=torch.float64, device=dev) if virial else None
+            phi = torch.empty((self.C, N), dtype=torch.float32, device=dev) if potential else None
+        st = _lib.lib().pswflr_realspace(self.handle, _stream(stream), _ptr(ws), ws.numel(), N, _ptr(pos), _ptr(q),
+                                         _ptr(energy), _ptr(F), _ptr(W), _ptr(phi))
+        _lib.check(st)
+        return {"energy": energy, "forces": F, "virial": W, "potential": phi, "workspace": ws}
+
     def backward(self, workspace, pos, q, grad_energy, want_q=True, want_pos=True, stream=None):
         """Adjoint of an energy-only execute on the same workspace."""
         N = pos.shape[0]

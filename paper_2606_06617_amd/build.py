@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["kernels.hip", "plan.cpp", "host_math.cpp"]
+SOURCES = ["kernels.hip", "realspace.hip", "plan.cpp", "host_math.cpp"]
 LIB = os.path.join(HERE, "libpswflr.so")
 
 HIP_FLAGS = [

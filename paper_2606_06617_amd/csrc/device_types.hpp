@@ -177,6 +177,38 @@ struct Work {
                           // the binning; [1] result of the optional input check
 };
 
+// Real-space complement of the split (Eq. realLR): the pair kernel
+// K_p(r) = (1 - G_p(r / r_c)) / r^p for 0 < r < r_c over all periodic
+// images.  Cells of edge >= r_c (or the whole box along an axis shorter
+// than r_c); a cell's neighbours are the offsets -R..R on each axis, each
+// offset one periodic image of the cell it wraps to.
+constexpr int kRsSeg = 16;   // complement polynomial: segments on rho in [0, 1]
+constexpr int kRsDeg = 11;
+constexpr int kRsCoef = kRsSeg * (kRsDeg + 1);
+struct RsGeo {
+  int C;
+  int64_t N;
+  int nc[3];              // cells per axis
+  int R[3];               // neighbour offsets per axis
+  int ncell;
+  float L[3], Llo[3];     // box edges as FP32 double words
+  float cells_per_len[3]; // nc / L
+  float rc, rc2, inv_rc;
+  int srec;               // floats per atom record: position + pad, then C charges (multiple of 4)
+};
+struct RsTables {
+  const float *ucoef;     // [C][kRsCoef] 1 - G_p on rho in [0, 1], per channel
+  const int *pch;         // [C] exponent of each channel
+};
+struct RsWork {
+  float *rec_b;           // [N][srec] caller order (wrapped positions, charges)
+  float *rec_a;           // [N][srec] cell order
+  int *perm_b, *perm_a;   // cell order -> caller order (unordered, ordered)
+  int *cell_of, *slot;    // [N]
+  int *count, *start;     // [ncell], [ncell + 1]
+  double *part;           // [ncell][C + 6]: per-cell energy and virial partials
+};
+
 // One structure of a batched call: everything a stage body needs.
 struct BatchItem {
   Geo g;

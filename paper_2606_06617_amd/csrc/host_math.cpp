@@ -392,6 +392,37 @@ double phi_hat_deriv(const Prolate &ps, int p, double k, double c, double r_c) {
 
 static ChannelKernel build_channel_kernel(int p, double c, double r_c, double eps);
 
+double mollifier_complement(const Prolate &ps, int p, double rho) {
+  if (!(rho < 1.0)) return 0.0;
+  const double x = rho < 0.0 ? 0.0 : rho;
+  const double psi = ps(x), d1 = ps.d1(x), C0 = ps.C0();
+  switch (p) {
+    case 1: return 1.0 - ps.I0(x) / C0;                                  // G1 = I0 / C0
+    case 2: return psi;                                                   // G2 = 1 - psi
+    case 3: return 1.0 - (ps.I0(x) - x * psi) / C0;
+    case 4: return psi - 0.5 * x * d1;
+    case 5: return 1.0 - (ps.I0(x) - x * psi + x * x / 3.0 * d1) / C0;
+    case 6: return psi - 5.0 * x / 8.0 * d1 + x * x / 8.0 * ps.d2(x);   // G6
+  }
+  return 0.0;
+}
+
+PiecewisePoly make_complement_poly(int p, double c, int nseg, int deg, double eps) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, long, int, int, long>, PiecewisePoly> cache;
+  const auto key = std::make_tuple(p, std::lround(c * 1e9), nseg, deg, std::lround(std::log10(eps) * 100));
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  auto ps = prolate_cached(c);
+  PiecewisePoly fit = fit_piecewise([&](double x) { return mollifier_complement(*ps, p, x); }, nseg, deg, eps);
+  std::lock_guard<std::mutex> lock(mu);
+  cache.emplace(key, fit);
+  return fit;
+}
+
 ChannelKernel make_channel_kernel(int p, double c, double r_c, double eps) {
   // box-independent: one fit per (p, c, r_c) serves every structure
   static std::mutex mu;

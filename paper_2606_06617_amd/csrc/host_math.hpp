@@ -81,6 +81,13 @@ struct ChannelKernel {
 };
 ChannelKernel make_channel_kernel(int p, double c, double r_c, double eps);
 
+// Real-space complement 1 - G_p(rho) of the mollifier (Eqs. G1, G6, G;
+// rho = r / r_c, zero for rho >= 1), and its device representation on
+// [0, 1] (the pair kernel is (1 - G_p(r / r_c)) / r^p; its derivative comes
+// from the polynomial's).
+double mollifier_complement(const Prolate &ps, int p, double rho);
+PiecewisePoly make_complement_poly(int p, double c, int nseg, int deg, double eps);
+
 // Exact (FP64) Phi_p(k) and Phi_p'(k) from the closed forms, for checks.
 double phi_hat(const Prolate &ps, int p, double k, double c, double r_c);
 double phi_hat_deriv(const Prolate &ps, int p, double k, double c, double r_c);

@@ -14,12 +14,14 @@
 #include <cstdint>
 #include <mutex>
 
+#include "device_sort.hpp"
 #include "device_types.hpp"
 #include "kernels.hpp"
 
 namespace pswf {
 
 #define PSWF_THREADS 256
+static_assert(PSWF_THREADS == kSortThreads, "the ordering kernels run with the sort's block size");
 
 // ---------------------------------------------------------------------------
 // complex helpers
@@ -391,27 +393,7 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_bin(Geo g, Work w, const float
 
 // exclusive scan of cell counts (single block)
 __device__ __forceinline__ void scan_body(const Work &w, int ncell, int64_t N) {
-  __shared__ int part[1024];
-  __shared__ int carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < ncell; base += 1024) {
-    int i = base + threadIdx.x;
-    int v = i < ncell ? w.cell_count[i] : 0;
-    part[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      int t = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-      __syncthreads();
-      part[threadIdx.x] += t;
-      __syncthreads();
-    }
-    if (i < ncell) w.cell_start[i] = carry + part[threadIdx.x] - v;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry += part[1023];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) w.cell_start[ncell] = int(N);
+  scan_counts(w.cell_count, w.cell_start, ncell, N);
 }
 
 __global__ __launch_bounds__(1024) void k_scan(Work w, int ncell, int64_t N) { scan_body(w, ncell, N); }
@@ -442,70 +424,6 @@ __device__ __forceinline__ void order_move(const Geo &g, const Work &w, int key,
   }
 }
 
-// Crowded cell (more keys than fit the LDS rank): stable least-significant-
-// digit radix sort of its caller indices, 8 bits per pass, between the
-// cell's ranges of perm_b and perm_a.  A pass takes the keys 256 at a time;
-// inside a wave, lanes with equal digits are found by ballots over the 8
-// digit bits and ranked by lane, waves in order, so every pass is stable and
-// the cost is linear in the cell's size.  Returns the buffer holding the
-// sorted keys.
-__device__ int *order_radix(const Geo &g, const Work &w, int s, int n) {
-  __shared__ int hist[256];
-  __shared__ int wcnt[PSWF_THREADS / 64][256];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int *src = w.perm_b + s, *dst = w.perm_a + s;
-  const int bits = g.N > 1 ? 32 - __clz(int(g.N - 1)) : 1;
-  const unsigned long long below = (1ull << lane) - 1ull;
-  for (int shift = 0; shift < bits; shift += 8) {
-    for (int d = tid; d < 256; d += PSWF_THREADS) hist[d] = 0;
-    __syncthreads();
-    for (int k = tid; k < n; k += PSWF_THREADS) atomicAdd(&hist[(src[k] >> shift) & 255], 1);
-    __syncthreads();
-    if (tid == 0) {  // exclusive prefix: the first slot of every digit
-      int acc = 0;
-      for (int d = 0; d < 256; ++d) {
-        const int v = hist[d];
-        hist[d] = acc;
-        acc += v;
-      }
-    }
-    __syncthreads();
-    for (int k0 = 0; k0 < n; k0 += PSWF_THREADS) {
-      for (int e = tid; e < (PSWF_THREADS / 64) * 256; e += PSWF_THREADS) (&wcnt[0][0])[e] = 0;
-      __syncthreads();
-      const int k = k0 + tid;
-      const bool valid = k < n;
-      const int key = valid ? src[k] : 0;
-      const int d = (key >> shift) & 255;
-      unsigned long long eq = __ballot(valid);
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const unsigned long long on = __ballot(valid && ((d >> b) & 1));
-        eq &= ((d >> b) & 1) ? on : ~on;
-      }
-      const int rank = __popcll(eq & below);
-      if (valid && rank == 0) wcnt[wave][d] = __popcll(eq);
-      __syncthreads();
-      if (valid) {
-        int off = hist[d] + rank;
-        for (int wq = 0; wq < wave; ++wq) off += wcnt[wq][d];
-        dst[off] = key;
-      }
-      __syncthreads();
-      for (int dd = tid; dd < 256; dd += PSWF_THREADS) {
-        int t = 0;
-        for (int wq = 0; wq < PSWF_THREADS / 64; ++wq) t += wcnt[wq][dd];
-        hist[dd] += t;
-      }
-      __syncthreads();
-    }
-    int *tmp = src;
-    src = dst;
-    dst = tmp;
-  }
-  return src;
-}
-
 // deterministic order inside each cell: ascending caller index
 __device__ __forceinline__ void order_body(const Geo &g, const Work &w, int bx) {
   __shared__ int keys[2048];
@@ -514,7 +432,7 @@ __device__ __forceinline__ void order_body(const Geo &g, const Work &w, int bx) 
   const int n = e - s;
   if (n <= 0) return;
   if (n > 2048) {
-    const int *sorted = order_radix(g, w, s, n);
+    const int *sorted = order_radix(g.N, w.perm_b + s, w.perm_a + s, n);
     for (int k = threadIdx.x; k < n; k += PSWF_THREADS) order_move(g, w, sorted[k], s + k);
     return;
   }

@@ -48,6 +48,12 @@ hipError_t launch_check_inputs(const Geo &g, const Work &w, const float *pos, co
 hipError_t launch_finalize(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial,
                            hipStream_t st);
 
+// real-space complement: binning, ordering, pair sums and the FP64 reduction
+// (realspace.hip); grp/gch describe channel groups sharing one exponent
+hipError_t launch_realspace(const RsGeo &g, const RsTables &t, const RsWork &w, const int *grp, const int *gch,
+                            int ngrp, int cgmax, const float *pos, const float *q, double *energy, float *forces,
+                            double *virial, float *pot, hipStream_t st);
+
 // batched execution (one launch per stage over every structure)
 int batch_stage_threads(int stage);
 int batch_stage_blocks(const BatchItem &it, int stage, bool adjoint);

@@ -162,6 +162,14 @@ struct pswflr_plan_s {
   size_t off_grid = 0, off_s1 = 0, off_s2 = 0, off_rec_a = 0, off_q_a = 0, off_q_b = 0,
          off_perm_a = 0, off_perm_b = 0, off_cell_of = 0, off_slot = 0, off_count = 0, off_start = 0,
          off_epart = 0, off_qpart = 0, off_qsum = 0, off_status = 0, ws_bytes = 0;
+  // real-space complement: geometry, tables (in the plan's device block) and
+  // workspace regions
+  RsGeo rsg{};
+  RsTables rst{};
+  const int *rs_grp = nullptr, *rs_gch = nullptr;
+  int rs_ngrp = 0, rs_cgmax = 0;
+  size_t off_rs_rec_b = 0, off_rs_rec_a = 0, off_rs_perm_b = 0, off_rs_perm_a = 0, off_rs_cell_of = 0,
+         off_rs_slot = 0, off_rs_count = 0, off_rs_start = 0, off_rs_part = 0;
   // optional per-stage event timing (measurement only)
   bool prof = false;
   std::mutex prof_mu;
@@ -441,6 +449,26 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
     selfc[ch] = k.self_coef;
     zerov[ch] = k.zero_coef_V;
   }
+  // real-space complement 1 - G_p per distinct exponent, channel groups of
+  // one exponent (at most 16 channels each)
+  std::vector<int> rs_pdist, rs_grp, rs_gch;
+  for (int ch = 0; ch < C; ++ch)
+    if (std::find(rs_pdist.begin(), rs_pdist.end(), p.p[ch]) == rs_pdist.end()) rs_pdist.push_back(p.p[ch]);
+  std::vector<float> rs_u(rs_pdist.size() * kRsCoef);
+  int rs_cgmax = 0;
+  for (size_t e = 0; e < rs_pdist.size(); ++e) {
+    const PiecewisePoly up = make_complement_poly(rs_pdist[e], c, kRsSeg, kRsDeg, 1e-9);
+    for (int i = 0; i < kRsCoef; ++i) rs_u[e * kRsCoef + i] = float(up.coef[i]);
+    std::vector<int> chans;
+    for (int ch = 0; ch < C; ++ch)
+      if (p.p[ch] == rs_pdist[e]) chans.push_back(ch);
+    for (size_t b0 = 0; b0 < chans.size(); b0 += 16) {
+      const int cnt = int(std::min<size_t>(16, chans.size() - b0));
+      rs_grp.insert(rs_grp.end(), {rs_pdist[e], int(rs_gch.size()), cnt, int(e)});
+      rs_gch.insert(rs_gch.end(), chans.begin() + b0, chans.begin() + b0 + cnt);
+      rs_cgmax = std::max(rs_cgmax, cnt);
+    }
+  }
   // pack
   std::vector<char> blob;
   auto put = [&](const void *src, size_t bytes) {
@@ -458,7 +486,9 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
          o_xb = put(xblk.data(), std::max<size_t>(1, xblk.size()) * 4 * (xblk.empty() ? 0 : 1)),
          o_xg = put(xgrp.data(), xgrp.size() * 4),
          o_bl = put(blim.data(), blim.size() * 4), o_self = put(selfc.data(), selfc.size() * 8),
-         o_zero = put(zerov.data(), zerov.size() * 8);
+         o_zero = put(zerov.data(), zerov.size() * 8), o_rsu = put(rs_u.data(), rs_u.size() * 4),
+         o_rsg = put(rs_grp.data(), rs_grp.size() * 4), o_rsc = put(rs_gch.data(), rs_gch.size() * 4),
+         o_rsp = put(p.p, size_t(C) * 4);
   blob.resize(align256(blob.size()) + 256);
   if (hipGetDevice(&pl.device) != hipSuccess) return fail(PSWFLR_ERR_DEVICE, "hipGetDevice failed");
   if (table_alloc(blob.size(), pl.device, &pl.dtab, &pl.dtab_bytes) != hipSuccess) {
@@ -486,6 +516,40 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   t.blim = reinterpret_cast<const int *>(b + o_bl);
   t.self_coef = reinterpret_cast<const double *>(b + o_self);
   t.zero_V = reinterpret_cast<const double *>(b + o_zero);
+  pl.rst.ucoef = reinterpret_cast<const float *>(b + o_rsu);
+  pl.rst.pch = reinterpret_cast<const int *>(b + o_rsp);
+  pl.rs_grp = reinterpret_cast<const int *>(b + o_rsg);
+  pl.rs_gch = reinterpret_cast<const int *>(b + o_rsc);
+  pl.rs_ngrp = int(rs_grp.size() / 4);
+  pl.rs_cgmax = rs_cgmax;
+  {
+    // cells of edge >= r_c (the whole box along a shorter axis), fewer than
+    // max(64, max_atoms) cells in all; neighbour offsets -R..R
+    RsGeo &rg = pl.rsg;
+    rg = RsGeo{};
+    rg.C = C;
+    double edge_min = p.r_c;
+    for (;;) {
+      int64_t tot = 1;
+      for (int a = 0; a < 3; ++a) tot *= std::max(1, int(std::floor(p.box[a] / edge_min)));
+      if (tot <= std::max<int64_t>(64, max_atoms)) break;
+      edge_min *= 1.25;
+    }
+    rg.ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+      rg.nc[a] = std::max(1, int(std::floor(p.box[a] / edge_min)));
+      const double edge = p.box[a] / rg.nc[a];
+      rg.R[a] = std::max(1, int(std::ceil(p.r_c / edge - 1e-12)));
+      rg.L[a] = float(p.box[a]);
+      rg.Llo[a] = float(p.box[a] - double(rg.L[a]));
+      rg.cells_per_len[a] = float(rg.nc[a] / p.box[a]);
+      rg.ncell *= rg.nc[a];
+    }
+    rg.rc = float(p.r_c);
+    rg.rc2 = float(p.r_c * p.r_c);
+    rg.inv_rc = float(1.0 / p.r_c);
+    rg.srec = 4 + (C + 3) / 4 * 4;
+  }
 
   // ---- workspace layout for max_atoms ----
   const int64_t Nm = std::max<int64_t>(max_atoms, 1);
@@ -514,6 +578,15 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   pl.off_qpart = take(size_t((Nm + kQChunk - 1) / kQChunk + 1) * C * 2 * 8);
   pl.off_qsum = take(size_t(C) * 2 * 8);
   pl.off_status = take(2 * sizeof(int));
+  pl.off_rs_rec_b = take(size_t(Nm) * pl.rsg.srec * 4);
+  pl.off_rs_rec_a = take(size_t(Nm) * pl.rsg.srec * 4);
+  pl.off_rs_perm_b = take(size_t(Nm) * 4);
+  pl.off_rs_perm_a = take(size_t(Nm) * 4);
+  pl.off_rs_cell_of = take(size_t(Nm) * 4);
+  pl.off_rs_slot = take(size_t(Nm) * 4);
+  pl.off_rs_count = take(size_t(pl.rsg.ncell) * 4);
+  pl.off_rs_start = take(size_t(pl.rsg.ncell + 1) * 4);
+  pl.off_rs_part = take(size_t(pl.rsg.ncell) * (C + 6) * 8);
   pl.ws_bytes = o;
   pl.max_atoms = max_atoms;
 
@@ -756,6 +829,39 @@ pswflr_status pswflr_execute_noalloc(pswflr_plan plan, pswflr_stream stream, int
   const bool adjoint = forces || potential;
   e = run_forward(plan, st, g, w, pos, q, adjoint ? 1 : 0, energy, virial, false);
   if (e == hipSuccess && adjoint) e = run_adjoint(plan, st, g, w, forces, potential, 1, nullptr, false);
+  if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return PSWFLR_OK;
+}
+
+pswflr_status pswflr_realspace(pswflr_plan plan, pswflr_stream stream, void *workspace, size_t ws_bytes,
+                               int64_t n_atoms, const float *pos, const float *q, double *energy, float *forces,
+                               double *virial, float *potential) {
+  pswflr_status s = check_call(plan, workspace, ws_bytes, n_atoms, pos, q);
+  if (s != PSWFLR_OK) return s;
+  if (!energy) return fail(PSWFLR_ERR_INVALID_ARG, "energy output is required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  {
+    Geo g = plan->geo;
+    g.N = n_atoms;
+    Work w = carve(*plan, workspace, n_atoms);
+    if ((s = check_inputs(*plan, st, g, w, pos, q)) != PSWFLR_OK) return s;
+  }
+  RsGeo rg = plan->rsg;
+  rg.N = n_atoms;
+  char *b = static_cast<char *>(workspace);
+  RsWork rw{};
+  rw.rec_b = reinterpret_cast<float *>(b + plan->off_rs_rec_b);
+  rw.rec_a = reinterpret_cast<float *>(b + plan->off_rs_rec_a);
+  rw.perm_b = reinterpret_cast<int *>(b + plan->off_rs_perm_b);
+  rw.perm_a = reinterpret_cast<int *>(b + plan->off_rs_perm_a);
+  rw.cell_of = reinterpret_cast<int *>(b + plan->off_rs_cell_of);
+  rw.slot = reinterpret_cast<int *>(b + plan->off_rs_slot);
+  rw.count = reinterpret_cast<int *>(b + plan->off_rs_count);
+  rw.start = reinterpret_cast<int *>(b + plan->off_rs_start);
+  rw.part = reinterpret_cast<double *>(b + plan->off_rs_part);
+  hipError_t e = launch_realspace(rg, plan->rst, rw, plan->rs_grp, plan->rs_gch, plan->rs_ngrp, plan->rs_cgmax, pos,
+                                  q, energy, forces, virial, potential, st);
+  if (e == hipSuccess) e = mark_use(st, &plan, 1);
   if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return PSWFLR_OK;
 }
