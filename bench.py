@@ -134,52 +134,67 @@ def batch_leg(reps=10):
             "sequential_ms": round(t_seq * 1e3, 3), "sequential_atoms_s": round(atoms / t_seq, 1)}
 
 
-def serving_leg(nreq=400, seed=6, fractions=(0.5, 0.8, 0.95), slots=4):
+def serving_leg(nreq=2000, seed=6, fractions=(0.5, 0.8, 0.95), slots=4, max_batch=16):
     """Continuous-batching latency on the Poisson request mix (sizes
     log-uniform in [100, 5e4] atoms, density 0.1, channels p = 1 and 6,
     tolerance 1e-5): the one-at-a-time capacity is measured first (one
-    slot, requests back to back), then the same requests arrive as Poisson
-    processes at the given fractions of it and are served with `slots`
-    overlapping evaluations.  Latency = completion - arrival, including the
-    host plan, both copies and the evaluation."""
+    slot, one request per launch, back to back), then the same requests
+    arrive as Poisson processes at the given fractions of it and are served
+    with `slots` overlapping launches, the requests admitted together
+    coalesced into one batched launch (up to max_batch).  Latency =
+    completion - arrival, including the host plan, both copies and the
+    evaluation; the phases behind the tail (plan, wait for a slot, service)
+    are reported with it.  Every buffer is sized before the timed traces and
+    a warm-up trace runs on the executor the rates use."""
     from paper_2606_06617_amd import workloads as wl
     from paper_2606_06617_amd.serving import HipExecutor, Server, latency_stats, make_requests
 
     stream = wl.serving_stream(nreq=nreq, rate=1.0, seed=seed)
     reqs = make_requests(stream)
     # warm the host caches that plans of any box share (window bandwidth
-    # grid, kernel fits) and the device code paths
-    ex = HipExecutor(slots=1)
-    for r in reqs:
-        ex.prepare(r)
-    warm = Server(HipExecutor(slots=1))
-    warm.run_trace([reqs[i] for i in range(min(8, nreq))], realtime=False)
-    warm.close()
-    ex1 = HipExecutor(slots=1)
-    ex1.reserve(max(r.n_atoms for r in reqs), max(len(r.ps) for r in reqs))
+    # grid, kernel fits), and size the buffers for the largest request
+    ex1 = HipExecutor(slots=1, max_batch=1)
+    max_ws = max(ex1.prepare(r)[0].workspace_bytes for r in reqs)
+    maxn, maxc = max(r.n_atoms for r in reqs), max(len(r.ps) for r in reqs)
+    ex1.reserve(maxn, maxc, max_ws)
+    warm = Server(ex1)
+    warm.run_trace(reqs[:32], realtime=False)
     solo = Server(ex1)
     t0 = time.perf_counter()
-    done = solo.run_trace(reqs, realtime=False)
+    solo.run_trace(reqs, realtime=False)
     span = time.perf_counter() - t0
-    solo.close()
     capacity = nreq / span
+    atoms = sum(r.n_atoms for r in reqs)
     out = {"requests_per_rate": nreq, "capacity_req_s": round(capacity, 1),
-           "atoms_per_request": "log-uniform [100, 50000]", "slots": slots, "rates": []}
+           "capacity_atoms_s": round(atoms / span, 1), "atoms_per_request": "log-uniform [100, 50000]",
+           "slots": slots, "max_batch": max_batch, "rates": []}
+    ex = HipExecutor(slots=slots, max_batch=max_batch)
+    ex.reserve(maxn, maxc, max_ws, n_requests=4)
     rng = np.random.default_rng(seed + 1)
-    for f in fractions:
-        gaps = rng.exponential(1.0 / (f * capacity), size=nreq)
-        for r, t in zip(reqs, np.cumsum(gaps)):
+
+    def replay(f, subset):
+        gaps = rng.exponential(1.0 / (f * capacity), size=len(subset))
+        for r, t in zip(subset, np.cumsum(gaps)):
             r.t_arrival, r.t_done, r.t_admit, r.t_ready, r.error = float(t), None, None, None, None
-        ex = HipExecutor(slots=slots)
-        ex.reserve(max(r.n_atoms for r in reqs), max(len(r.ps) for r in reqs))
         srv = Server(ex)
-        res = srv.run_trace(reqs, realtime=True)
+        res = srv.run_trace(subset, realtime=True)
         srv.close()
+        return srv, res
+
+    replay(0.8, reqs[:200])   # warm-up on the executor the rates use (untimed)
+    for f in fractions:
+        srv, res = replay(f, reqs)
         st = latency_stats(res)
         out["rates"].append({"load": f, "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
-                             "mean_ms": round(st["mean_ms"], 3), "req_s": round(st["throughput_req_s"], 1),
-                             "max_concurrency": srv.max_concurrency})
-    del done
+                             "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
+                             "req_s": round(st["throughput_req_s"], 1),
+                             "atoms_s": round(st["throughput_atoms_s"], 1),
+                             "wait_p99_ms": round(st["wait_p99_ms"], 3), "wait_max_ms": round(st["wait_max_ms"], 3),
+                             "service_p99_ms": round(st["service_p99_ms"], 3),
+                             "service_max_ms": round(st["service_max_ms"], 3),
+                             "plan_p99_ms": round(st["plan_p99_ms"], 3),
+                             "max_concurrency": srv.max_concurrency, "launches": srv.launches,
+                             "max_coalesced": srv.max_coalesced})
     return out
 
 

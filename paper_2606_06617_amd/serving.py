@@ -9,9 +9,11 @@ Plans (the per-box host set-up, a fraction of a millisecond once the
 shared host caches are warm) are built as requests arrive: inline by
 default, or on a worker pool (plan_workers > 0) -- Python threads share one
 interpreter lock, which can delay the scheduling loop by its switch
-interval, so the pool only pays when plan building is slow.  Each request's result does not depend on
-what else is in flight: every kernel works on one structure's own buffers
-and all reductions have a fixed order.
+interval, so the pool only pays when plan building is slow.  The requests
+admitted together in one poll (up to the executor's max_batch) run as one
+batched launch on one slot.  Each request's result does not depend on what
+else is in flight or what it was batched with: every kernel works on one
+structure's own buffers and all reductions have a fixed order.
 
 The scheduler is written against a small executor interface so that its
 admission logic is exercised on the CPU with a simulated executor
@@ -55,40 +57,53 @@ class Request:
 
 
 class HipExecutor:
-    """Runs requests through the C ABI on per-slot HIP streams."""
+    """Runs requests through the C ABI on per-slot HIP streams.
 
-    def __init__(self, slots=4, r_c=5.0, c=0.0, tol=1e-5, support=8, device="cuda:0"):
+    Every slot owns its device buffers (workspace, inputs, outputs) and its
+    pinned host staging; both grow geometrically and are reused, so serving
+    allocates nothing per request once the buffers have reached the sizes
+    the trace needs (reserve() sizes them up front).  Several requests
+    admitted together run as one pswflr_execute_batch call on one slot
+    (one launch per stage for all of them)."""
+
+    def __init__(self, slots=4, r_c=5.0, c=0.0, tol=1e-5, support=8, device="cuda:0", max_batch=16):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
         self.r_c, self.c, self.tol, self.support = r_c, c, tol, support
-        # per-slot pinned staging, grown geometrically and reused: a slot
-        # takes a new request only after the previous one's copies are done,
-        # and no request pays a pinned allocation
+        self.max_batch = int(max_batch)
         self._pinned = [dict() for _ in range(slots)]
+        self._dev = [dict() for _ in range(slots)]
 
-    def reserve(self, n_atoms, n_channels):
-        """Allocate every slot's pinned staging for requests of up to
-        n_atoms atoms and n_channels channels ahead of serving."""
+    def reserve(self, n_atoms, n_channels, workspace_bytes=0, n_requests=1):
+        """Size every slot's pinned staging and device buffers for launches
+        of up to n_requests requests holding n_atoms atoms and n_channels
+        channels each, and a workspace of workspace_bytes, ahead of serving."""
         torch = self.torch
+        na, nr = n_atoms * n_requests, n_requests
         for slot in range(self.slots):
-            self._stage(slot, "pos", (n_atoms, 3), torch.float32)
-            self._stage(slot, "q", (n_channels, n_atoms), torch.float32)
-            self._stage(slot, "energy", (3 * n_channels + 1,), torch.float64)
-            self._stage(slot, "forces", (n_atoms, 3), torch.float32)
-            self._stage(slot, "virial", (6,), torch.float64)
+            for store, pin in ((self._pinned[slot], True), (self._dev[slot], False)):
+                self._buf(store, slot, "pos", 3 * na, torch.float32, pin)
+                self._buf(store, slot, "q", n_channels * na, torch.float32, pin)
+                self._buf(store, slot, "energy", (3 * n_channels + 1) * nr, torch.float64, pin)
+                self._buf(store, slot, "forces", 3 * na, torch.float32, pin)
+                self._buf(store, slot, "virial", 6 * nr, torch.float64, pin)
+            if workspace_bytes:
+                self._buf(self._dev[slot], slot, "ws", workspace_bytes * nr + (1 << 20), torch.uint8, False)
+        torch.cuda.synchronize(self.device)
 
-    def _stage(self, slot, name, shape, dtype):
-        n = 1
-        for d in shape:
-            n *= d
-        buf = self._pinned[slot].get(name)
+    def _buf(self, store, slot, name, n, dtype, pinned):
+        buf = store.get(name)
         if buf is None or buf.numel() < n:
             size = max(n, 2 * buf.numel() if buf is not None else 0, 1)
-            buf = self.torch.empty(size, dtype=dtype, pin_memory=True)
-            self._pinned[slot][name] = buf
-        return buf[:n].view(*shape)
+            if pinned:
+                buf = self.torch.empty(size, dtype=dtype, pin_memory=True)
+            else:
+                with self.torch.cuda.stream(self.streams[slot]):
+                    buf = self.torch.empty(size, dtype=dtype, device=self.device)
+            store[name] = buf
+        return buf[:n]
 
     @property
     def slots(self):
@@ -108,36 +123,97 @@ class HipExecutor:
         return plan, foot
 
     def launch(self, req, plan, slot):
+        return self.launch_many([req], [plan], slot)
+
+    def launch_many(self, reqs, plans, slot):
+        """Stage the requests' inputs, run them (one execute, or one batched
+        execute for several) on the slot's stream and queue the copies back."""
+        import ctypes
+
+        from . import _lib
         torch = self.torch
         st = self.streams[slot]
-        N, C = req.n_atoms, len(req.ps)
+        pin, dev = self._pinned[slot], self._dev[slot]
+        Ns = [r.n_atoms for r in reqs]
+        Cs = [len(r.ps) for r in reqs]
+        nq = sum(c * n for c, n in zip(Cs, Ns))
+        ne = sum(3 * c + 1 for c in Cs)
+        na = sum(Ns)
+        n = len(reqs)
+        pos_h = self._buf(pin, slot, "pos", 3 * na, torch.float32, True)
+        q_h = self._buf(pin, slot, "q", nq, torch.float32, True)
+        e_h = self._buf(pin, slot, "energy", ne, torch.float64, True)
+        f_h = self._buf(pin, slot, "forces", 3 * na, torch.float32, True)
+        w_h = self._buf(pin, slot, "virial", 6 * n, torch.float64, True)
+        pos_d = self._buf(dev, slot, "pos", 3 * na, torch.float32, False)
+        q_d = self._buf(dev, slot, "q", nq, torch.float32, False)
+        e_d = self._buf(dev, slot, "energy", ne, torch.float64, False)
+        f_d = self._buf(dev, slot, "forces", 3 * na, torch.float32, False)
+        w_d = self._buf(dev, slot, "virial", 6 * n, torch.float64, False)
+        pn, qn = pos_h.numpy(), q_h.numpy()
+        a0 = q0 = 0
+        for r, N, C in zip(reqs, Ns, Cs):
+            pn[3 * a0:3 * (a0 + N)] = r.pos.reshape(-1)
+            qn[q0:q0 + C * N] = r.q.reshape(-1)
+            a0 += N
+            q0 += C * N
+        L = _lib.lib()
         with torch.cuda.stream(st):
-            pos_h = self._stage(slot, "pos", (N, 3), torch.float32)
-            q_h = self._stage(slot, "q", (C, N), torch.float32)
-            pos_h.copy_(torch.from_numpy(req.pos))
-            q_h.copy_(torch.from_numpy(req.q))
-            pos = pos_h.to(self.device, non_blocking=True)
-            q = q_h.to(self.device, non_blocking=True)
-            out = plan.execute(pos, q, forces=True, virial=True, stream=st)
-            e_h = self._stage(slot, "energy", (3 * C + 1,), torch.float64)
-            f_h = self._stage(slot, "forces", (N, 3), torch.float32)
-            w_h = self._stage(slot, "virial", (6,), torch.float64)
-            e_h.copy_(out["energy"], non_blocking=True)
-            f_h.copy_(out["forces"], non_blocking=True)
-            w_h.copy_(out["virial"], non_blocking=True)
+            pos_d.copy_(pos_h, non_blocking=True)
+            q_d.copy_(q_h, non_blocking=True)
+            sptr = ctypes.c_void_p(st.cuda_stream)
+            if n == 1:
+                ws = self._buf(dev, slot, "ws", plans[0].workspace_bytes, torch.uint8, False)
+                _lib.check(L.pswflr_execute(plans[0].handle, sptr, ws.data_ptr(), ws.numel(), Ns[0],
+                                            pos_d.data_ptr(), q_d.data_ptr(), e_d.data_ptr(), f_d.data_ptr(),
+                                            w_d.data_ptr(), None))
+            else:
+                handles = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+                natoms = (ctypes.c_int64 * n)(*Ns)
+                need = ctypes.c_size_t()
+                _lib.check(L.pswflr_batch_workspace(n, handles, natoms, ctypes.byref(need)))
+                ws = self._buf(dev, slot, "ws", need.value, torch.uint8, False)
+                ios = (_lib.IO * n)()
+                pb, qb, eb, fb, wb = (pos_d.data_ptr(), q_d.data_ptr(), e_d.data_ptr(), f_d.data_ptr(),
+                                      w_d.data_ptr())
+                a0 = q0 = e0 = 0
+                for i, (N, C) in enumerate(zip(Ns, Cs)):
+                    io = ios[i]
+                    io.n_atoms = N
+                    io.pos = pb + 12 * a0
+                    io.q = qb + 4 * q0
+                    io.energy = eb + 8 * e0
+                    io.forces = fb + 12 * a0
+                    io.virial = wb + 48 * i
+                    io.potential = None
+                    a0 += N
+                    q0 += C * N
+                    e0 += 3 * C + 1
+                _lib.check(L.pswflr_execute_batch(n, handles, ios, sptr, ws.data_ptr(), ws.numel()))
+            e_h.copy_(e_d, non_blocking=True)
+            f_h.copy_(f_d, non_blocking=True)
+            w_h.copy_(w_d, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(st)
-        # keep device tensors alive until the event completes
-        return {"event": ev, "host": (e_h, f_h, w_h), "dev": (pos, q, out)}
+        return {"event": ev, "host": (e_h, f_h, w_h), "sizes": (Ns, Cs), "plans": plans}
 
     def done(self, token):
         return token["event"].query()
 
-    def finish(self, req, token):
+    def finish_many(self, reqs, token):
         e_h, f_h, w_h = token["host"]
-        req.energy = e_h.numpy().copy()
-        req.forces = f_h.numpy().copy()
-        req.virial = w_h.numpy().copy()
+        en, fn, wn = e_h.numpy(), f_h.numpy(), w_h.numpy()
+        Ns, Cs = token["sizes"]
+        a0 = e0 = 0
+        for i, (r, N, C) in enumerate(zip(reqs, Ns, Cs)):
+            r.energy = en[e0:e0 + 3 * C + 1].copy()
+            r.forces = fn[3 * a0:3 * (a0 + N)].reshape(N, 3).copy()
+            r.virial = wn[6 * i:6 * i + 6].copy()
+            a0 += N
+            e0 += 3 * C + 1
+
+    def finish(self, req, token):
+        self.finish_many([req], token)
 
     def budget_default(self):
         free, _ = self.torch.cuda.mem_get_info(self.device)
@@ -158,11 +234,13 @@ class Server:
                      if plan_workers > 0 else None)
         self.clock = clock
         self.pending = collections.deque()        # (req, future of (plan, footprint))
-        self.inflight = {}                         # slot -> (req, plan, token)
+        self.inflight = {}                         # slot -> (requests, token)
         self.used = 0
         self.done = []
         self.peak_used = 0
         self.max_concurrency = 0
+        self.max_coalesced = 0
+        self.launches = 0
         self.t0 = None
 
     def now(self):
@@ -183,46 +261,67 @@ class Server:
 
     def _retire(self):
         for slot in list(self.inflight):
-            req, plan, token = self.inflight[slot]
+            reqs, token = self.inflight[slot]
             if self.ex.done(token):
-                self.ex.finish(req, token)
-                req.t_done = self.now()
-                self.used -= req.footprint
+                if len(reqs) == 1:
+                    self.ex.finish(reqs[0], token)
+                else:
+                    self.ex.finish_many(reqs, token)
+                t = self.now()
+                for req in reqs:
+                    req.t_done = t
+                    self.used -= req.footprint
+                    self.done.append(req)
                 del self.inflight[slot]
-                self.done.append(req)
 
     def _admit(self):
+        """Admit head-of-queue requests in FIFO order while a slot is free and
+        their footprints fit the budget; the requests admitted for one slot
+        in one poll (up to the executor's max_batch) run as one launch."""
+        max_batch = getattr(self.ex, "max_batch", 1)
         free_slots = [s for s in range(self.ex.slots) if s not in self.inflight]
         while self.pending and free_slots:
-            req, fut = self.pending[0]
-            if not fut.done():
-                break                               # FIFO: wait for the head's plan
-            try:
-                plan, foot = fut.result()
-            except Exception as exc:                # malformed request: fail it, keep serving
+            group, plans = [], []
+            while self.pending and len(group) < max_batch:
+                req, fut = self.pending[0]
+                if not fut.done():
+                    break                               # FIFO: wait for the head's plan
+                try:
+                    plan, foot = fut.result()
+                except Exception as exc:                # malformed request: fail it, keep serving
+                    self.pending.popleft()
+                    req.error = "%s: %s" % (type(exc).__name__, exc)
+                    req.t_done = self.now()
+                    self.done.append(req)
+                    continue
+                req.footprint = int(foot)
+                if req.t_ready is None:
+                    req.t_ready = self.now()
+                if foot > self.budget:
+                    self.pending.popleft()
+                    req.error = "footprint %d B exceeds the HBM budget %d B" % (foot, self.budget)
+                    req.t_done = self.now()
+                    self.done.append(req)
+                    continue
+                if self.used + foot > self.budget:
+                    break                               # wait for memory to free up
                 self.pending.popleft()
-                req.error = "%s: %s" % (type(exc).__name__, exc)
-                req.t_done = self.now()
-                self.done.append(req)
-                continue
-            req.footprint = int(foot)
-            if req.t_ready is None:
-                req.t_ready = self.now()
-            if foot > self.budget:
-                self.pending.popleft()
-                req.error = "footprint %d B exceeds the HBM budget %d B" % (foot, self.budget)
-                req.t_done = self.now()
-                self.done.append(req)
-                continue
-            if self.used + foot > self.budget:
-                break                               # wait for memory to free up
-            self.pending.popleft()
-            slot = free_slots.pop(0)
-            req.t_admit = self.now()
-            self.used += foot
+                req.t_admit = self.now()
+                self.used += foot
+                group.append(req)
+                plans.append(plan)
+            if not group:
+                break
             self.peak_used = max(self.peak_used, self.used)
-            self.inflight[slot] = (req, plan, self.ex.launch(req, plan, slot))
+            slot = free_slots.pop(0)
+            if len(group) == 1:
+                token = self.ex.launch(group[0], plans[0], slot)
+            else:
+                token = self.ex.launch_many(group, plans, slot)
+            self.inflight[slot] = (group, token)
+            self.launches += 1
             self.max_concurrency = max(self.max_concurrency, len(self.inflight))
+            self.max_coalesced = max(self.max_coalesced, len(group))
 
     def poll(self):
         self._retire()
@@ -264,14 +363,25 @@ class Server:
 
 
 def latency_stats(reqs):
-    lat = np.array([r.latency for r in reqs if r.error is None and r.latency is not None])
-    if lat.size == 0:
+    """Latency percentiles (arrival to completion) and the phases behind
+    them: ready (plan built) - arrival, admit - ready (waiting for a slot or
+    memory), done - admit (device work and copies)."""
+    ok = [r for r in reqs if r.error is None and r.latency is not None]
+    if not ok:
         return {"n": 0}
+    lat = np.array([r.latency for r in ok])
     span = max(r.t_done for r in reqs if r.t_done is not None) - min(r.t_arrival for r in reqs)
-    atoms = sum(r.n_atoms for r in reqs if r.error is None)
+    atoms = sum(r.n_atoms for r in ok)
+    plan = np.array([r.t_ready - r.t_arrival for r in ok])
+    wait = np.array([r.t_admit - r.t_ready for r in ok])
+    serv = np.array([r.t_done - r.t_admit for r in ok])
     return {"n": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
-            "throughput_req_s": float(lat.size / span), "throughput_atoms_s": float(atoms / span)}
+            "max_ms": float(lat.max() * 1e3),
+            "throughput_req_s": float(lat.size / span), "throughput_atoms_s": float(atoms / span),
+            "plan_p99_ms": float(np.percentile(plan, 99) * 1e3), "plan_max_ms": float(plan.max() * 1e3),
+            "wait_p99_ms": float(np.percentile(wait, 99) * 1e3), "wait_max_ms": float(wait.max() * 1e3),
+            "service_p99_ms": float(np.percentile(serv, 99) * 1e3), "service_max_ms": float(serv.max() * 1e3)}
 
 
 def make_requests(stream, ps=(1, 6), density=0.1):

@@ -123,3 +123,34 @@ def test_latency_statistics_and_poisson_replay():
     for r in out:
         assert r.latency >= r.n_atoms * 1e-6 - 1e-9
     srv.close()
+
+
+class BatchSimExecutor(SimExecutor):
+    """Also runs several requests per launch (service time of their sum)."""
+
+    max_batch = 4
+
+    def launch_many(self, reqs, plans, slot):
+        for r in reqs:
+            self.launched.append((r.rid, slot, self.clock()))
+        return {"t_end": self.clock() + self.per_atom * sum(r.n_atoms for r in reqs), "n": len(reqs)}
+
+    def finish_many(self, reqs, token):
+        for r in reqs:
+            r.energy = np.array([float(r.n_atoms)])
+
+
+def test_requests_admitted_together_share_one_launch():
+    clock = FakeClock()
+    ex = BatchSimExecutor(clock, slots=1, per_atom=1e-3)
+    srv = Server(ex, budget=10 ** 9, clock=clock)
+    # one long request occupies the slot; six arrive meanwhile: the next
+    # launch takes four of them (max_batch), the one after the last two
+    reqs = [_req(0, 100, 0.0)] + [_req(i, 10, 0.01 + 0.001 * i) for i in range(1, 7)]
+    _drive(srv, clock, reqs)
+    assert all(r.error is None and r.t_done is not None for r in reqs)
+    assert srv.launches == 3 and srv.max_coalesced == 4
+    starts = {rid: t for rid, _, t in ex.launched}
+    assert len({starts[i] for i in range(1, 5)}) == 1 and starts[5] == starts[6] > starts[1]
+    # FIFO order is kept across launches
+    assert [r.rid for r in sorted(reqs, key=lambda r: (r.t_admit, r.rid))] == list(range(7))
