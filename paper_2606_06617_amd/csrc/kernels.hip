@@ -546,10 +546,16 @@ constexpr int kSpreadOutMax = (kSpreadMaxPts + kSpreadThreads - 1) / kSpreadThre
 // (one row past the staged candidates holds zeros: the padding of the
 // matrix-core hit groups points there)
 constexpr int kSpreadHitList = 68;  // per wave and block: 64 hits padded to whole groups of four
-__host__ __device__ __forceinline__ int spread_stage_floats(int S) { return (kSpreadCap + 1) * (kSpreadCGM + S); }
-__host__ __device__ __forceinline__ int spread_lds_floats(int S) {
-  return spread_stage_floats(S) + 5 * kSpreadList + 2 * kSpreadMaxCells + 1 + 3 + kWinSeg * (kWinDeg + 1) +
-         2 * kSpreadCap + (kSpreadThreads / 64) * kSpreadNBW * kSpreadHitList / 2;
+// staged charges per candidate: 16 for the matrix-core variant, the
+// accumulator count rounded to 4 otherwise
+__host__ __device__ constexpr int spread_qstride(int cg) { return spread_mfma(cg) ? kSpreadCGM : spread_cg4(cg); }
+__host__ __device__ __forceinline__ int spread_stage_floats(int S, int cg) {
+  return (kSpreadCap + 1) * (spread_qstride(cg) + S);
+}
+// the block bits and hit lists only exist for the matrix-core variant
+__host__ __device__ __forceinline__ int spread_lds_floats(int S, int cg) {
+  return spread_stage_floats(S, cg) + 5 * kSpreadList + 2 * kSpreadMaxCells + 1 + 3 + kWinSeg * (kWinDeg + 1) +
+         (spread_mfma(cg) ? 2 * kSpreadCap + (kSpreadThreads / 64) * kSpreadNBW * kSpreadHitList / 2 : 0);
 }
 __host__ __device__ __forceinline__ int spread_pad4(int b) { return (b + 3) & ~3; }
 // blocks along z of a tile edge (1, 2 or 4 supported); 0 if unsupported
@@ -691,11 +697,11 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
         bits |= 1u << (x >> 2);
       }
     }
-    cbits[4 * k + a] = static_cast<unsigned short>(bits);
+    if constexpr (MF) cbits[4 * k + a] = static_cast<unsigned short>(bits);
     if (a == 0) {
 #pragma unroll
       for (int c = 0; c < spread_cg4(CG); c += 4)
-        *reinterpret_cast<float4 *>(cq + k * kSpreadCGM + c) =
+        *reinterpret_cast<float4 *>(cq + k * spread_qstride(CG) + c) =
             make_float4(c < ncg ? qv[c] : 0.0f, c + 1 < ncg ? qv[c + 1] : 0.0f, c + 2 < ncg ? qv[c + 2] : 0.0f,
                         c + 3 < ncg ? qv[c + 3] : 0.0f);
     }
@@ -795,7 +801,7 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
       const int kq = min(k, ncand - 1);
 #pragma unroll
       for (int c = 0; c < spread_cg4(CG); c += 4) {
-        const float4 q4 = *reinterpret_cast<const float4 *>(cq + kq * kSpreadCGM + c);
+        const float4 q4 = *reinterpret_cast<const float4 *>(cq + kq * spread_qstride(CG) + c);
         qreg[c] = q4.x;
         qreg[c + 1] = q4.y;
         qreg[c + 2] = q4.z;
@@ -834,7 +840,7 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   const int sz[3] = {spread_pad4(Bx), spread_pad4(By), spread_pad4(Bz)};
   const int S = sz[0] + sz[1] + sz[2];
   float *cq = smem;                                                 // [cap + 1][CGM]
-  float *cw = cq + (kSpreadCap + 1) * kSpreadCGM;                   // [cap + 1][S]
+  float *cw = cq + (kSpreadCap + 1) * spread_qstride(CG);           // [cap + 1][S]
   float *lf = cw + (kSpreadCap + 1) * S;                            // [list][3] window offsets delta
   int *ld = reinterpret_cast<int *>(lf + 3 * kSpreadList);          // [list] packed window starts
   int *li = ld + kSpreadList;                                       // [list] atom index
@@ -848,7 +854,7 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
 
   const int tid = threadIdx.x, lane = tid & 63;
   // the zero row past the staged candidates (padding of the hit groups)
-  for (int e = tid; e < kSpreadCGM; e += kSpreadThreads) cq[kSpreadCap * kSpreadCGM + e] = 0.0f;
+  for (int e = tid; e < spread_qstride(CG); e += kSpreadThreads) cq[kSpreadCap * spread_qstride(CG) + e] = 0.0f;
   for (int e = tid; e < S; e += kSpreadThreads) cw[kSpreadCap * S + e] = 0.0f;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps block bookkeeping scalar
   const int cell = bx;
@@ -1008,7 +1014,7 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   // same (x, y, z) element(s) of every channel.
   float *stage = smem;  // reuses the candidate area
   const int nt = Bx * By * Bz;
-  const int cpp = max(1, min(ncg, spread_stage_floats(S) / nt));
+  const int cpp = max(1, min(ncg, spread_stage_floats(S, CG) / nt));
   const bool vec = (Bz & 3) == 0;
   const int epr = vec ? 4 : 1;                       // floats per element
   const int nel = nt / epr;                          // elements per channel
@@ -2050,7 +2056,7 @@ static inline unsigned nblocks(int64_t n, int per) { return unsigned((n + per - 
 size_t spread_lds_bytes(const Geo &g, int ncg) {
   (void)ncg;
   const int S = spread_pad4(g.B[0]) + spread_pad4(g.B[1]) + spread_pad4(g.B[2]);
-  return size_t(spread_lds_floats(S)) * 4;
+  return size_t(spread_lds_floats(S, spread_cg_template(ncg))) * 4;
 }
 int spread_max_cells() { return kSpreadMaxCells; }
 // candidate cells a tile of edges b has to screen (see spread_body)
@@ -2066,7 +2072,7 @@ bool spread_tile_ok(int bx, int by, int bz) {
   const int cpw = kSpreadNBW / nbz, nby = spread_pad4(by) / 4, ncol = (spread_pad4(bx) / 4) * nby;
   const int S = spread_pad4(bx) + spread_pad4(by) + spread_pad4(bz);
   return nby % cpw == 0 && ncol <= cpw * (kSpreadThreads / 64) && S <= kSpreadMaxS &&
-         bx * by * bz <= spread_stage_floats(S);
+         bx * by * bz <= spread_stage_floats(S, 2);
 }
 size_t gather_lds_bytes(const Geo &g, int ncg) {
   (void)ncg;
@@ -2154,9 +2160,9 @@ hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t
 
 template <int P, int NBZ, int CG>
 static hipError_t spread_pzc(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
-  hipError_t e = lds_request(reinterpret_cast<const void *>(&k_spread<P, NBZ, CG>), spread_lds_bytes(g, ncg));
+  hipError_t e = lds_request(reinterpret_cast<const void *>(&k_spread<P, NBZ, CG>), spread_lds_bytes(g, CG));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_spread<P, NBZ, CG>), dim3(g.ncell), dim3(kSpreadThreads), spread_lds_bytes(g, ncg), st, g, t,
+  hipLaunchKernelGGL((k_spread<P, NBZ, CG>), dim3(g.ncell), dim3(kSpreadThreads), spread_lds_bytes(g, CG), st, g, t,
                      w, cg0, ncg);
   LAUNCH_CHECK();
   return hipSuccess;
