@@ -96,41 +96,60 @@ def measured_traffic(workload_name, kernel):
 
 def batch_leg(reps=10):
     """The 64-structure training batch (N in [200, 4000], grids 24^3-64^3,
-    p = 1 and 6, forces and virial): one batched call (a launch per stage
-    over all structures) against the same structures evaluated one after
-    another, both with workspaces reused; atoms/s over the batch."""
+    p = 1 and 6): one batched call on flat arrays (a launch per stage over
+    all structures) with forces and virial, against the same structures
+    evaluated one call after another, both with workspaces and outputs
+    reused; and the training step of the batch: energy-only batched forward
+    plus the batched hand-written adjoint (dE/dq, dE/dr of every structure).
+    atoms/s over the batch, host wall time per call."""
     import torch
 
     from paper_2606_06617_amd import workloads as wl
-    from paper_2606_06617_amd.api import Plan, execute_batch
+    from paper_2606_06617_amd.api import Batch, Plan
 
     structs = wl.diff_batch()
     dev = torch.device("cuda:0")
     plans = [Plan(st["box"], st["ps"], r_c=R_C, c=C_MOL, grid=st["grid"], support=st["support"] or 0,
                   max_atoms=st["pos"].shape[0]) for st in structs]
     inputs = [(torch.from_numpy(st["pos"]).to(dev), torch.from_numpy(st["q"]).to(dev)) for st in structs]
-    atoms = sum(int(x[0].shape[0]) for x in inputs)
-    outs, ws = execute_batch(plans, inputs)
+    batch = Batch(plans, [x[0].shape[0] for x in inputs])
+    pos, q = Batch.concat(inputs)
+    atoms = batch.atoms
+    ws = batch.new_workspace(dev)
+    out = batch.execute(pos, q, forces=True, virial=True, workspace=ws)
     for _ in range(2):
-        outs, ws = execute_batch(plans, inputs, workspace=ws)
+        batch.execute(pos, q, forces=True, virial=True, workspace=ws, out=out)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        outs, ws = execute_batch(plans, inputs, workspace=ws)
+        batch.execute(pos, q, forces=True, virial=True, workspace=ws, out=out)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
-    wss = [p.new_workspace(dev) for p in plans]
-    for p, (pos, q), w_ in zip(plans, inputs, wss):
-        p.execute(pos, q, forces=True, virial=True, workspace=w_)
+    g = torch.ones(sum(batch.Cs), dtype=torch.float64, device=dev)
+    eo = {"energy": torch.empty(batch.elen, dtype=torch.float64, device=dev)}
+    for _ in range(2):
+        batch.execute(pos, q, forces=False, virial=False, workspace=ws, out=eo)
+        batch.backward(ws, pos, q, g)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        for p, (pos, q), w_ in zip(plans, inputs, wss):
-            p.execute(pos, q, forces=True, virial=True, workspace=w_)
+        batch.execute(pos, q, forces=False, virial=False, workspace=ws, out=eo)
+        batch.backward(ws, pos, q, g)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / reps
+    wss = [p.new_workspace(dev) for p in plans]
+    for p, (ps_, qs_), w_ in zip(plans, inputs, wss):
+        p.execute(ps_, qs_, forces=True, virial=True, workspace=w_)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for p, (ps_, qs_), w_ in zip(plans, inputs, wss):
+            p.execute(ps_, qs_, forces=True, virial=True, workspace=w_)
     torch.cuda.synchronize()
     t_seq = (time.perf_counter() - t0) / reps
     return {"structures": len(structs), "atoms": atoms, "support": plans[0].info["support"],
             "batched_ms": round(t_batch * 1e3, 3), "batched_atoms_s": round(atoms / t_batch, 1),
+            "forward_adjoint_ms": round(t_train * 1e3, 3), "forward_adjoint_atoms_s": round(atoms / t_train, 1),
             "sequential_ms": round(t_seq * 1e3, 3), "sequential_atoms_s": round(atoms / t_seq, 1)}
 
 

@@ -249,6 +249,35 @@ pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans,
                                    const pswflr_io *io, pswflr_stream stream,
                                    void *workspace, size_t ws_bytes);
 
+/* The batched call with every array flat: the structures' atoms, charges
+ * and outputs follow each other in one device array each, in batch order.
+ *   n_atoms   [n] host: atoms of each structure (N_i)
+ *   pos       [sum N_i][3]; q: the blocks [C_i][N_i] one after another
+ *   energy    the blocks [3 C_i + 1]; forces [sum N_i][3] or NULL;
+ *   virial    [n][6] or NULL; potential: blocks [C_i][N_i] or NULL
+ * Same semantics, workspace (pswflr_batch_workspace) and errors as
+ * pswflr_execute_batch; the per-structure pointers are formed here, so the
+ * caller passes four pointers instead of a table. */
+pswflr_status pswflr_execute_batch_flat(int32_t n, const pswflr_plan *plans, const int64_t *n_atoms,
+                                        const float *pos, const float *q, double *energy,
+                                        float *forces, double *virial, float *potential,
+                                        pswflr_stream stream, void *workspace, size_t ws_bytes);
+
+/* Adjoint of an energy-only batched forward (pswflr_execute_batch or
+ * _flat with forces and potentials NULL, same plans, atoms, workspace, and
+ * no other call on that workspace in between): the hand-written backward of
+ * every structure's energy at once (Fig. 1 caption: gradients by
+ * differentiation; the scaled inverse transforms and the gather, one launch
+ * per stage over all structures).
+ *   grad_energy [sum C_i] device: dL/dE_c of each structure's channels
+ *   grad_q      blocks [C_i][N_i] or NULL: dL/dq
+ *   grad_pos    [sum N_i][3] or NULL: dL/dr
+ * Errors: INVALID_ARG, WORKSPACE, DEVICE. */
+pswflr_status pswflr_backward_batch_flat(int32_t n, const pswflr_plan *plans, const int64_t *n_atoms,
+                                         const float *pos, const float *q, const double *grad_energy,
+                                         float *grad_q, float *grad_pos, pswflr_stream stream,
+                                         void *workspace, size_t ws_bytes);
+
 /* Per-stage device timing, for measurement (the paper times whole
  * forward+backward evaluations after warm-ups; Methods, "Performance
  * comparison in differentiable long-range evaluations").  While enabled,

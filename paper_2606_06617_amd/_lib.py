@@ -94,6 +94,10 @@ def lib():
     L.pswflr_batch_workspace.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                          ctypes.POINTER(sz)]
     L.pswflr_execute_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(IO), vp, vp, sz]
+    L.pswflr_execute_batch_flat.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(i64), vp, vp, vp, vp,
+                                            vp, vp, vp, vp, sz]
+    L.pswflr_backward_batch_flat.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(i64), vp, vp, vp, vp,
+                                             vp, vp, vp, sz]
     L.pswflr_profile_enable.argtypes = [vp, ctypes.c_int]
     L.pswflr_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     L.pswflr_status_string.argtypes = [ctypes.c_int]
@@ -102,6 +106,7 @@ def lib():
     for name in ("pswflr_plan_create", "pswflr_plan_info", "pswflr_plan_destroy", "pswflr_execute",
                  "pswflr_execute_noalloc", "pswflr_realspace",
                  "pswflr_backward", "pswflr_batch_workspace", "pswflr_execute_batch",
+                 "pswflr_execute_batch_flat", "pswflr_backward_batch_flat",
                  "pswflr_profile_enable", "pswflr_profile_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L

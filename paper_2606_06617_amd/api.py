@@ -195,6 +195,115 @@ def execute_batch(plans, inputs, forces=True, virial=True, potential=False, work
     return outs, ws
 
 
+class Batch:
+    """Many structures laid out flat for the batched calls: positions
+    [sum N_i, 3] and charges (the blocks [C_i, N_i] one after another) in
+    one device tensor each, with the per-structure plans.  The ctypes tables
+    (plan handles, atom counts) are built once here, so a call marshals four
+    pointers."""
+
+    def __init__(self, plans, n_atoms):
+        self.plans = list(plans)
+        self.n = len(self.plans)
+        self.n_atoms = [int(x) for x in n_atoms]
+        self.Cs = [p.C for p in self.plans]
+        self.handles = (ctypes.c_void_p * max(1, self.n))(*[p.handle.value for p in self.plans])
+        self.natoms = (ctypes.c_int64 * max(1, self.n))(*self.n_atoms)
+        self.atoms = sum(self.n_atoms)
+        self.qlen = sum(c * m for c, m in zip(self.Cs, self.n_atoms))
+        self.elen = sum(3 * c + 1 for c in self.Cs)
+        # index of each structure's E_lr in the flat energy array
+        ends, e0 = [], 0
+        for c in self.Cs:
+            ends.append(e0 + 3 * c)
+            e0 += 3 * c + 1
+        self.elr_index = ends
+        need = ctypes.c_size_t()
+        _lib.check(_lib.lib().pswflr_batch_workspace(self.n, self.handles, self.natoms, ctypes.byref(need)))
+        self.workspace_bytes = max(1, need.value)
+
+    @staticmethod
+    def concat(inputs):
+        """Flat (pos, q) from a list of per-structure (pos [N,3], q [C,N])."""
+        pos = torch.cat([p.reshape(-1) for p, _ in inputs]) if inputs else torch.empty(0)
+        q = torch.cat([c.reshape(-1) for _, c in inputs]) if inputs else torch.empty(0)
+        return pos.contiguous(), q.contiguous()
+
+    def new_workspace(self, device="cuda"):
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+
+    def execute(self, pos, q, forces=True, virial=True, potential=False, workspace=None, stream=None, out=None):
+        """One batched call on flat inputs: returns flat energy (blocks
+        [3C_i + 1]), forces [sum N_i, 3], virial [n, 6], potentials (blocks
+        [C_i, N_i]) and E_lr per structure [n]."""
+        dev = pos.device
+        if pos.dtype != torch.float32 or q.dtype != torch.float32 or not (pos.is_contiguous() and q.is_contiguous()):
+            raise ValueError("pos and q must be contiguous float32 tensors")
+        if pos.numel() != 3 * self.atoms or q.numel() != self.qlen:
+            raise ValueError("flat inputs do not match the batch's atom and channel counts")
+        o = out or {}
+        with (torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()):
+            ws = workspace if workspace is not None else self.new_workspace(dev)
+            e = o.get("energy")
+            if e is None:
+                e = torch.empty(self.elen, dtype=torch.float64, device=dev)
+            F = (o.get("forces") if o.get("forces") is not None else
+                 torch.empty((self.atoms, 3), dtype=torch.float32, device=dev)) if forces else None
+            W = (o.get("virial") if o.get("virial") is not None else
+                 torch.empty((self.n, 6), dtype=torch.float64, device=dev)) if virial else None
+            phi = (o.get("potential") if o.get("potential") is not None else
+                   torch.empty(self.qlen, dtype=torch.float32, device=dev)) if potential else None
+        st = _lib.lib().pswflr_execute_batch_flat(self.n, self.handles, self.natoms, _ptr(pos), _ptr(q), _ptr(e),
+                                                  _ptr(F), _ptr(W), _ptr(phi), _stream(stream), _ptr(ws),
+                                                  ws.numel())
+        _lib.check(st)
+        return {"energy": e, "forces": F, "virial": W, "potential": phi, "workspace": ws}
+
+    def backward(self, workspace, pos, q, grad_energy, want_q=True, want_pos=True, stream=None):
+        """Adjoint of an energy-only batched call on the same workspace:
+        grad_energy [sum C_i] (dL/dE per channel) -> dL/dq (flat blocks) and
+        dL/dr [sum N_i, 3]."""
+        dev = pos.device
+        with (torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()):
+            gq = torch.empty(self.qlen, dtype=torch.float32, device=dev) if want_q else None
+            gp = torch.empty((self.atoms, 3), dtype=torch.float32, device=dev) if want_pos else None
+            g = grad_energy.to(device=dev, dtype=torch.float64).contiguous()
+        st = _lib.lib().pswflr_backward_batch_flat(self.n, self.handles, self.natoms, _ptr(pos), _ptr(q), _ptr(g),
+                                                   _ptr(gq), _ptr(gp), _stream(stream), _ptr(workspace),
+                                                   workspace.numel())
+        _lib.check(st)
+        return gq, gp
+
+
+class PSWFLRBatchFunction(torch.autograd.Function):
+    """E_lr of every structure of a Batch, [n], as a differentiable function
+    of the flat positions and charges: one batched energy-only forward, and
+    one batched hand-written adjoint for all structures' gradients."""
+
+    @staticmethod
+    def forward(ctx, pos, q, batch):
+        ws = batch.new_workspace(pos.device)
+        out = batch.execute(pos.detach(), q.detach(), forces=False, virial=False, potential=False, workspace=ws)
+        ctx.batch = batch
+        ctx.ws = ws
+        ctx.save_for_backward(pos.detach(), q.detach())
+        idx = torch.tensor(batch.elr_index, device=pos.device, dtype=torch.long)
+        return out["energy"].index_select(0, idx)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        pos, q = ctx.saved_tensors
+        batch = ctx.batch
+        reps = torch.tensor(batch.Cs, device=grad_out.device, dtype=torch.long)
+        g = torch.repeat_interleave(grad_out.detach().to(torch.float64), reps)   # dL/dE per channel
+        gq, gp = batch.backward(ctx.ws, pos, q, g, want_q=ctx.needs_input_grad[1], want_pos=ctx.needs_input_grad[0])
+        return (gp.view_as(pos) if gp is not None else None), (gq.view_as(q) if gq is not None else None), None
+
+
+def lr_energy_batch(pos, q, batch):
+    return PSWFLRBatchFunction.apply(pos, q, batch)
+
+
 def _check_inputs(pos, q, C, max_atoms):
     if not (pos.is_cuda and q.is_cuda):
         raise ValueError("pos and q must be CUDA (HIP) tensors")

@@ -222,8 +222,9 @@ struct BatchItem {
   double *virial;
   float *pot;
   int qblocks;
-  int pad_;
+  int mode;               // x pass: 0 energy only, 1 energy + potential grid, 2 adjoint
   int64_t nlines;
+  const double *grad;     // adjoint calls: dL/dE per channel (device), else NULL
 };
 
 // Stages of one evaluation, in launch order.

@@ -2350,7 +2350,7 @@ __global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather
       yfwd_body(g, it.t, it.ay, it.w, vb % gx, vb / gx);
       break;
     }
-    case kBsXmul: xmul_body(g, it.t, it.ax, it.w, mode, nullptr, vb % g.nxblk, vb / g.nxblk); break;
+    case kBsXmul: xmul_body(g, it.t, it.ax, it.w, it.mode, it.grad, vb % g.nxblk, vb / g.nxblk); break;
     case kBsFinalize: finalize_body(g, it.t, it.w, it.energy, it.virial); break;
     case kBsYinv: {
       const int gx = (g.KZ + g.kzq - 1) / g.kzq;
@@ -2360,13 +2360,13 @@ __global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather
     case kBsZinv: zinv_body(g, it.t, it.az, it.w, it.nlines, vb); break;
     case kBsGather:
       switch (g.P) {
-        case 2: gather_body<2>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
-        case 3: gather_body<3>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
-        case 4: gather_body<4>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
-        case 5: gather_body<5>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
-        case 6: gather_body<6>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
-        case 7: gather_body<7>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
-        default: gather_body<8>(g, it.t, it.w, it.forces, it.pot, 1, nullptr, vb); break;
+        case 2: gather_body<2>(g, it.t, it.w, it.forces, it.pot, it.mode == 2 ? 2 : 1, it.grad, vb); break;
+        case 3: gather_body<3>(g, it.t, it.w, it.forces, it.pot, it.mode == 2 ? 2 : 1, it.grad, vb); break;
+        case 4: gather_body<4>(g, it.t, it.w, it.forces, it.pot, it.mode == 2 ? 2 : 1, it.grad, vb); break;
+        case 5: gather_body<5>(g, it.t, it.w, it.forces, it.pot, it.mode == 2 ? 2 : 1, it.grad, vb); break;
+        case 6: gather_body<6>(g, it.t, it.w, it.forces, it.pot, it.mode == 2 ? 2 : 1, it.grad, vb); break;
+        case 7: gather_body<7>(g, it.t, it.w, it.forces, it.pot, it.mode == 2 ? 2 : 1, it.grad, vb); break;
+        default: gather_body<8>(g, it.t, it.w, it.forces, it.pot, it.mode == 2 ? 2 : 1, it.grad, vb); break;
       }
       break;
   }

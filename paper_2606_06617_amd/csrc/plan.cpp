@@ -990,8 +990,26 @@ pswflr_status pswflr_batch_workspace(int32_t n, const pswflr_plan *plans, const 
   return PSWFLR_OK;
 }
 
-pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const pswflr_io *io,
-                                   pswflr_stream stream, void *workspace, size_t ws_bytes) {
+}  // extern "C"
+
+namespace {
+
+// One structure of a batched call, forward or adjoint.
+struct BatchEntry {
+  int64_t n_atoms;
+  const float *pos, *q;
+  double *energy;
+  float *forces;      // forward: forces; adjoint: dL/dr
+  double *virial;
+  float *potential;   // forward: potentials; adjoint: dL/dq
+  const double *grad; // adjoint: dL/dE per channel
+};
+
+// Batched forward (every stage, one launch per stage over all structures)
+// or adjoint (scaled inverse transforms and the gather of an energy-only
+// batched forward on the same workspace).
+pswflr_status batch_impl(int32_t n, const pswflr_plan *plans, const BatchEntry *io, pswflr_stream stream,
+                         void *workspace, size_t ws_bytes, bool adjoint_call) {
   if (n == 0) return PSWFLR_OK;
   if (n < 0 || !plans || !io) return fail(PSWFLR_ERR_INVALID_ARG, "bad batch arguments");
   std::vector<int64_t> na(n);
@@ -1003,13 +1021,14 @@ pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const ps
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
     return fail(PSWFLR_ERR_WORKSPACE, "workspace not 256-byte aligned");
   for (int i = 0; i < n; ++i) {
-    if (!io[i].energy) return fail(PSWFLR_ERR_INVALID_ARG, "energy output is required");
+    if (!adjoint_call && !io[i].energy) return fail(PSWFLR_ERR_INVALID_ARG, "energy output is required");
+    if (adjoint_call && !io[i].grad) return fail(PSWFLR_ERR_INVALID_ARG, "grad_energy is required");
     if (io[i].n_atoms > 0 && (!io[i].pos || !io[i].q)) return fail(PSWFLR_ERR_INVALID_ARG, "pos and q required");
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   char *ws = static_cast<char *>(workspace);
   const size_t hdr = batch_header_bytes(n);
-  {
+  if (!adjoint_call) {
     size_t off = hdr;
     for (int i = 0; i < n; ++i) {
       Geo gi = plans[i]->geo;
@@ -1025,8 +1044,10 @@ pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const ps
   if (!fused) {  // channel groups beyond one spreading launch: one call per structure
     size_t off = hdr;
     for (int i = 0; i < n; ++i) {
-      s = pswflr_execute(plans[i], stream, ws + off, plans[i]->ws_bytes, io[i].n_atoms, io[i].pos, io[i].q,
-                         io[i].energy, io[i].forces, io[i].virial, io[i].potential);
+      s = adjoint_call ? pswflr_backward(plans[i], stream, ws + off, plans[i]->ws_bytes, io[i].n_atoms, io[i].pos,
+                                         io[i].q, io[i].grad, io[i].potential, io[i].forces)
+                       : pswflr_execute(plans[i], stream, ws + off, plans[i]->ws_bytes, io[i].n_atoms, io[i].pos,
+                                        io[i].q, io[i].energy, io[i].forces, io[i].virial, io[i].potential);
       if (s != PSWFLR_OK) return s;
       off += align256(plans[i]->ws_bytes);
     }
@@ -1058,7 +1079,10 @@ pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const ps
     it.pot = io[i].potential;
     it.qblocks = qsum_blocks(it.g);
     it.nlines = int64_t(it.g.C) * it.g.M[0] * it.g.M[1];
-    adj[i] = io[i].forces || io[i].potential;
+    it.grad = adjoint_call ? io[i].grad : nullptr;
+    adj[i] = adjoint_call || io[i].forces || io[i].potential;
+    // energy-only structures keep their spectrum for a later adjoint call
+    it.mode = adjoint_call ? 2 : (adj[i] ? 1 : 0);
     off += align256(pl.ws_bytes);
   }
   std::vector<int> total(kNumBatchStages);
@@ -1087,6 +1111,9 @@ pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const ps
   const int *d_prefix = reinterpret_cast<const int *>(ws + align256(size_t(n) * sizeof(BatchItem)));
   StageRunner run{plans[0], st};
   for (int stg = 0; stg < kNumBatchStages; ++stg) {
+    // the adjoint runs the scaled x pass and what follows it, minus the
+    // energy reduction
+    if (adjoint_call && (stg < kBsXmul || stg == kBsFinalize)) continue;
     e = run(stage_profile_id(stg), [&] {
       if (stg != kBsSpread)
         return launch_batch_stage(d_items, d_prefix + stg * (n + 1), n, stg, total[stg], lds[stg], 1, st);
@@ -1100,6 +1127,72 @@ pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const ps
   if ((e = mark_use(st, plans, n)) != hipSuccess)
     return fail(PSWFLR_ERR_DEVICE, std::string("event record failed: ") + hipGetErrorString(e));
   return PSWFLR_OK;
+}
+
+// Per-structure pointers into flat arrays: atoms, charges and outputs of
+// consecutive structures follow each other.
+std::vector<BatchEntry> flat_entries(int32_t n, const pswflr_plan *plans, const int64_t *n_atoms, const float *pos,
+                                     const float *q, double *energy, float *forces, double *virial,
+                                     float *potential, const double *grad, bool adjoint_call) {
+  std::vector<BatchEntry> io(std::max(0, n));
+  int64_t a0 = 0, q0 = 0, e0 = 0, c0 = 0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t N = n_atoms[i], C = plans[i]->geo.C;
+    BatchEntry &b = io[i];
+    b.n_atoms = N;
+    b.pos = pos ? pos + 3 * a0 : nullptr;
+    b.q = q ? q + q0 : nullptr;
+    b.energy = energy ? energy + e0 : nullptr;
+    b.forces = forces ? forces + 3 * a0 : nullptr;
+    b.virial = virial ? virial + 6 * i : nullptr;
+    b.potential = potential ? potential + q0 : nullptr;
+    b.grad = grad ? grad + c0 : nullptr;
+    a0 += N;
+    q0 += C * N;
+    e0 += 3 * C + 1;
+    c0 += C;
+  }
+  (void)adjoint_call;
+  return io;
+}
+
+}  // namespace
+
+extern "C" {
+
+pswflr_status pswflr_execute_batch(int32_t n, const pswflr_plan *plans, const pswflr_io *io,
+                                   pswflr_stream stream, void *workspace, size_t ws_bytes) {
+  if (n > 0 && (!plans || !io)) return fail(PSWFLR_ERR_INVALID_ARG, "bad batch arguments");
+  std::vector<BatchEntry> e(std::max(0, n));
+  for (int i = 0; i < n; ++i)
+    e[i] = BatchEntry{io[i].n_atoms, io[i].pos, io[i].q, io[i].energy, io[i].forces, io[i].virial, io[i].potential,
+                      nullptr};
+  return batch_impl(n, plans, e.data(), stream, workspace, ws_bytes, false);
+}
+
+pswflr_status pswflr_execute_batch_flat(int32_t n, const pswflr_plan *plans, const int64_t *n_atoms,
+                                        const float *pos, const float *q, double *energy, float *forces,
+                                        double *virial, float *potential, pswflr_stream stream, void *workspace,
+                                        size_t ws_bytes) {
+  if (n == 0) return PSWFLR_OK;
+  if (n < 0 || !plans || !n_atoms) return fail(PSWFLR_ERR_INVALID_ARG, "bad batch arguments");
+  for (int i = 0; i < n; ++i)
+    if (!plans[i]) return fail(PSWFLR_ERR_INVALID_ARG, "NULL plan in batch");
+  auto e = flat_entries(n, plans, n_atoms, pos, q, energy, forces, virial, potential, nullptr, false);
+  return batch_impl(n, plans, e.data(), stream, workspace, ws_bytes, false);
+}
+
+pswflr_status pswflr_backward_batch_flat(int32_t n, const pswflr_plan *plans, const int64_t *n_atoms,
+                                         const float *pos, const float *q, const double *grad_energy,
+                                         float *grad_q, float *grad_pos, pswflr_stream stream, void *workspace,
+                                         size_t ws_bytes) {
+  if (n == 0) return PSWFLR_OK;
+  if (n < 0 || !plans || !n_atoms || !grad_energy) return fail(PSWFLR_ERR_INVALID_ARG, "bad batch arguments");
+  if (!grad_q && !grad_pos) return PSWFLR_OK;
+  for (int i = 0; i < n; ++i)
+    if (!plans[i]) return fail(PSWFLR_ERR_INVALID_ARG, "NULL plan in batch");
+  auto e = flat_entries(n, plans, n_atoms, pos, q, nullptr, grad_pos, nullptr, grad_q, grad_energy, true);
+  return batch_impl(n, plans, e.data(), stream, workspace, ws_bytes, true);
 }
 
 const char *pswflr_status_string(pswflr_status status) {
