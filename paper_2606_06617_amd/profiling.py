@@ -12,11 +12,19 @@ bench.py:
   device-to-device copy of known size launched in the same process
   (``bench.py --calib-copy-mib``): factor = copy bytes / counter bytes.
 
-A traffic summary records the SHA-256 of the kernel source it was measured
-on; bench.py reports the traffic only while the source is unchanged.
+* instruction and unit counters (``rocprofv3 --pmc`` with SQ counters, at
+  most 8 per run) of chosen kernels: per-dispatch means, per-atom counts and
+  utilisations derived with the kernel's average duration from a
+  kernel-trace summary and the chip's 256 CUs x 4 SIMDs at 2.4 GHz.
+
+A traffic or counter summary records the SHA-256 of the kernel source it
+was measured on; bench.py reports the traffic only while the source is
+unchanged.
 
   python -m paper_2606_06617_amd.profiling stats <kernel_stats.csv> --out F --cmd "..."
   python -m paper_2606_06617_amd.profiling traffic <fetch.csv> <write.csv> --copy-bytes B --out F --cmd "..."
+  python -m paper_2606_06617_amd.profiling counters <pmc1.csv> [<pmc2.csv> ...] --stats S --atoms N
+         --kernels K1 K2 --out F --cmd "..."
 
 B is what the copy moves in total, read plus written (2 x --calib-copy-mib
 MiB, the calib_copy_bytes bench.py prints).
@@ -127,6 +135,68 @@ def read_traffic(path):
     return rows, sha
 
 
+CLOCK_HZ = 2.4e9
+SIMDS = 256 * 4
+
+
+def counter_table(paths, kernels):
+    """{kernel: {counter: mean per dispatch}} over every counter in the files."""
+    acc = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(lambda: collections.defaultdict(set))
+    regs = {}
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            k = short_name(r["Kernel_Name"])
+            if k not in kernels:
+                continue
+            acc[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[k][r["Counter_Name"]].add((path, r["Dispatch_Id"]))
+            regs[k] = (r.get("VGPR_Count"), r.get("Accum_VGPR_Count"), r.get("SGPR_Count"), r.get("LDS_Block_Size"))
+    return {k: {c: acc[k][c] / len(disp[k][c]) for c in acc[k]} for k in acc}, regs
+
+
+def derived(cnt, avg_us, atoms):
+    """Per-atom instruction counts and unit utilisations of one kernel.
+
+    valu_busy = 4 SQ_ACTIVE_INST_VALU / (SIMDs x cycles of the launch),
+    mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / (SIMDs x cycles),
+    lds_bank_conflict = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE,
+    with cycles = average duration x 2.4 GHz."""
+    cyc = avg_us * 1e-6 * CLOCK_HZ
+    out = {}
+    for c, label in (("SQ_INSTS_VALU", "valu_per_atom"), ("SQ_INSTS_SALU", "salu_per_atom"),
+                     ("SQ_INSTS_LDS", "lds_per_atom"), ("SQ_INSTS_VALU_MFMA_F32", "mfma_f32_per_atom")):
+        if c in cnt:
+            out[label] = cnt[c] / atoms
+    if "SQ_ACTIVE_INST_VALU" in cnt and cyc > 0:
+        out["valu_busy"] = 4.0 * cnt["SQ_ACTIVE_INST_VALU"] / (SIMDS * cyc)
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in cnt and cyc > 0:
+        out["mfma_busy"] = cnt["SQ_VALU_MFMA_BUSY_CYCLES"] / (SIMDS * cyc)
+    if "SQ_LDS_BANK_CONFLICT" in cnt and cnt.get("SQ_LDS_IDX_ACTIVE"):
+        out["lds_bank_conflict"] = cnt["SQ_LDS_BANK_CONFLICT"] / cnt["SQ_LDS_IDX_ACTIVE"]
+    return out
+
+
+def write_counters(table, regs, stats, atoms, out, cmd):
+    avg = {r["kernel"]: r["avg_us"] for r in stats}
+    with open(out, "w") as f:
+        f.write("# rocprofv3 SQ counters per dispatch (separate --pmc runs of at most 8 counters)\n")
+        f.write("# command: %s\n" % cmd)
+        f.write("# durations from the kernel-trace summary; utilisations over 256 CUs x 4 SIMDs at 2.4 GHz:\n")
+        f.write("#   valu_busy = 4 SQ_ACTIVE_INST_VALU / (SIMDs x cycles), mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES /\n")
+        f.write("#   (SIMDs x cycles), lds_bank_conflict = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE; per-atom counts\n")
+        f.write("#   are wave instructions per atom of the %d-atom frame\n" % atoms)
+        f.write("source_sha256 %s\n" % source_hash())
+        for k in sorted(table):
+            v, a, sg, lds = regs.get(k, (None,) * 4)
+            f.write("\n[%s] avg %.2f us; VGPR %s AGPR %s SGPR %s LDS %s B\n" % (k, avg.get(k, float("nan")), v, a, sg,
+                                                                             lds))
+            for c in sorted(table[k]):
+                f.write("  %-28s %18.1f\n" % (c, table[k][c]))
+            for name, val in derived(table[k], avg.get(k, 0.0), atoms).items():
+                f.write("  %-28s %18.4f\n" % (name, val))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -142,9 +212,19 @@ def main():
                         "2 x --calib-copy-mib MiB)")
     t.add_argument("--out", required=True)
     t.add_argument("--cmd", required=True)
+    u = sub.add_parser("counters")
+    u.add_argument("csvs", nargs="+")
+    u.add_argument("--stats", required=True, help="kernel_stats.csv of a kernel-trace run of the same command")
+    u.add_argument("--atoms", type=int, required=True)
+    u.add_argument("--kernels", nargs="+", required=True)
+    u.add_argument("--out", required=True)
+    u.add_argument("--cmd", required=True)
     a = ap.parse_args()
     if a.what == "stats":
         write_stats(kernel_stats(a.csv), a.out, a.cmd)
+    elif a.what == "counters":
+        table, regs = counter_table(a.csvs, set(a.kernels))
+        write_counters(table, regs, kernel_stats(a.stats), a.atoms, a.out, a.cmd)
     else:
         tr, ff, fw = traffic(a.fetch_csv, a.write_csv, a.copy_bytes)
         write_traffic(tr, ff, fw, a.copy_bytes, a.out, a.cmd)
