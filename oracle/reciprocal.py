@@ -19,10 +19,15 @@ Zero-frequency terms E_0 = a_p Q_net^2 (oracle.kernels) are added by
 `evaluate`; they contribute 2 a_p Q_net to every potential, nothing to the
 forces and E_0 delta_ab to the virial (every a_p scales as 1/V).
 
+`force_vjp` differentiates L = sum_i v_i . F_i once more (the double
+backward of force-matching training).
+
 Pins: forces against central finite differences of E_k, virial against
 finite differences of the energy under affine strain, zero net force,
 translation invariance, E(lambda q) = lambda^2 E, and the total-energy pins
-of tests/test_oracle_invariants.py that use E_k.
+of tests/test_oracle_invariants.py that use E_k; force_vjp against central
+finite differences of sum_i v_i . F_i in charges and positions
+(tests/test_oracle_double_backward.py).
 """
 import numpy as np
 
@@ -81,6 +86,43 @@ def reciprocal_channel(pos, q, box, p, c, r_c, forces=True, potential=True,
             W += np.einsum("k,ka,kb->ab", wgt, kv, kv) / V
             W += np.eye(3) * np.sum(fk * S2) / V
     return {"E": E, "phi": phi, "F": F, "W": W}
+
+
+def force_vjp(pos, q, box, ps, c, r_c, v):
+    """Derivatives of L = sum_i v_i . F_i (a force-matching loss linearised
+    at upstream gradient v [N, 3]) with respect to the charges and the
+    positions, from the same Fourier sum.  With T(k) = sum_i q_i (v_i . k)
+    e^{i k.r_i}, L = (1/V) sum_k Phi_p Im(conj(S) T) over the whole ball, so
+
+      dL/dq_j = (1/V) sum_k Phi_p Im(e^{-i k.r_j} T + conj(S) (v_j . k) e^{i k.r_j})
+      dL/dr_j = (q_j/V) sum_k Phi_p k [-Re(e^{-i k.r_j} T) + (v_j . k) Re(conj(S) e^{i k.r_j})]
+
+    (every term is even in k: the half space is counted twice).  E_0 does
+    not depend on the positions and adds nothing.  Returns dq [C, N] and
+    dr [N, 3] (summed over channels)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.atleast_2d(np.asarray(q, dtype=np.float64))
+    v = np.asarray(v, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    V = float(np.prod(box))
+    C, n = q.shape
+    _, kvec, kn = half_space_modes(box, c / r_c)
+    dq = np.zeros((C, n))
+    dr = np.zeros((n, 3))
+    for ch in range(C):
+        fk = kernels.phi_hat(int(ps[ch]), kn, c, r_c)
+        for s in range(0, kn.size, 4096):
+            kv = kvec[s:s + 4096]
+            f = fk[s:s + 4096]
+            ph = np.exp(1j * (pos @ kv.T))            # [N, K]
+            vk = v @ kv.T                             # [N, K] v_i . k
+            S = q[ch] @ ph
+            T = (q[ch][:, None] * vk * ph).sum(axis=0)
+            a = np.conj(ph) * T[None, :]              # e^{-ik r_j} T
+            b = np.conj(S)[None, :] * ph              # conj(S) e^{ik r_j}
+            dq[ch] += (2.0 / V) * ((a.imag + vk * b.imag) @ f)
+            dr += (2.0 / V) * q[ch][:, None] * (((-a.real + vk * b.real) * f[None, :]) @ kv)
+    return dq, dr
 
 
 def evaluate(pos, q, box, ps, c, r_c, forces=True, potential=True, virial=True):
