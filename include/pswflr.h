@@ -165,6 +165,25 @@ pswflr_status pswflr_execute(pswflr_plan plan, pswflr_stream stream, void *works
                              const float *q, double *energy, float *forces,
                              double *virial, float *potential);
 
+/* Second derivatives for force-matching training (Fig. 1 caption: forces
+ * are gradients of the energy, so a loss on forces needs the derivatives of
+ * the forces).  Given v [N][3] (device float, dL/dF_i of a loss L on the
+ * forces of the immediately preceding pswflr_execute, which must have
+ * computed forces or potentials with this plan, workspace, positions and
+ * charges, and no other call on that workspace in between), writes the
+ * derivatives of L through the forces:
+ *   grad_q   [C][N] float: dL/dq_i^(c) = -v_i . grad phi_c(r_i) - (W^T A u_c)_i
+ *   grad_pos [N][3] float: dL/dr_i = -sum_c q_i^(c) (Hess phi_c(r_i) v_i
+ *                                    + grad_i (W^T A u_c))
+ * with phi_c the forward's potential, u_c the dipole grid sum_i q_i^(c)
+ * (v_i . grad_{r_i}) W(n h - r_i), W the PSWF window and A the forward's
+ * convolution (Eq. EthetaLR).  Both outputs are required (device, caller-
+ * owned).  The forward's potential grid in the workspace is consumed.
+ * Errors: INVALID_ARG, WORKSPACE, DEVICE. */
+pswflr_status pswflr_force_vjp(pswflr_plan plan, pswflr_stream stream, void *workspace,
+                                size_t ws_bytes, int64_t n_atoms, const float *pos,
+                                const float *q, const float *v, float *grad_q, float *grad_pos);
+
 /* The real-space complement of the split (Eq. realLR; Methods,
  * "Implementation details"): for each channel c,
  *   E_real^(c) = 1/2 sum_n sum'_{i,j} q_i q_j (1 - G_p(r)) / r^p,

@@ -91,6 +91,7 @@ def lib():
     L.pswflr_backward.argtypes = [vp, vp, vp, sz, i64, vp, vp, vp, vp, vp]
     L.pswflr_execute_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
     L.pswflr_realspace.argtypes = [vp, vp, vp, sz, i64, vp, vp, vp, vp, vp, vp]
+    L.pswflr_force_vjp.argtypes = [vp, vp, vp, sz, i64, vp, vp, vp, vp, vp]
     L.pswflr_batch_workspace.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                          ctypes.POINTER(sz)]
     L.pswflr_execute_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(IO), vp, vp, sz]
@@ -104,7 +105,7 @@ def lib():
     L.pswflr_status_string.restype = ctypes.c_char_p
     L.pswflr_last_error.argtypes = [ctypes.c_char_p, sz]
     for name in ("pswflr_plan_create", "pswflr_plan_info", "pswflr_plan_destroy", "pswflr_execute",
-                 "pswflr_execute_noalloc", "pswflr_realspace",
+                 "pswflr_execute_noalloc", "pswflr_realspace", "pswflr_force_vjp",
                  "pswflr_backward", "pswflr_batch_workspace", "pswflr_execute_batch",
                  "pswflr_execute_batch_flat", "pswflr_backward_batch_flat",
                  "pswflr_profile_enable", "pswflr_profile_read"):

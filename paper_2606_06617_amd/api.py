@@ -125,6 +125,21 @@ class Plan:
         _lib.check(st)
         return {"energy": energy, "forces": F, "virial": W, "potential": phi, "workspace": ws}
 
+    def force_vjp(self, workspace, pos, q, v, stream=None):
+        """Derivatives of sum_i v_i . F_i in charges [C,N] and positions
+        [N,3], after an execute with forces on the same workspace (whose
+        potential grid it consumes)."""
+        N = pos.shape[0]
+        dev = pos.device
+        with (torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()):
+            gq = torch.empty((self.C, N), dtype=torch.float32, device=dev)
+            gp = torch.empty((N, 3), dtype=torch.float32, device=dev)
+            vv = v.to(device=dev, dtype=torch.float32).contiguous()
+        st = _lib.lib().pswflr_force_vjp(self.handle, _stream(stream), _ptr(workspace), workspace.numel(), N,
+                                         _ptr(pos), _ptr(q), _ptr(vv), _ptr(gq), _ptr(gp))
+        _lib.check(st)
+        return gq, gp
+
     def backward(self, workspace, pos, q, grad_energy, want_q=True, want_pos=True, stream=None):
         """Adjoint of an energy-only execute on the same workspace."""
         N = pos.shape[0]
@@ -359,3 +374,30 @@ class PSWFLRFunction(torch.autograd.Function):
 
 def lr_energy(pos, q, plan):
     return PSWFLRFunction.apply(pos, q, plan)
+
+
+class PSWFLRForces(torch.autograd.Function):
+    """Forces F = -dE_lr/dr [N,3] as a differentiable function of (pos, q),
+    for losses on forces (force matching): forward is the evaluation with
+    forces; backward takes dL/dF and runs the library's second-derivative
+    call (Hessian gather of the potential grid, dipole spread through the
+    same convolution), once per forward."""
+
+    @staticmethod
+    def forward(ctx, pos, q, plan):
+        ws = plan.new_workspace(pos.device)
+        out = plan.execute(pos.detach(), q.detach(), forces=True, virial=False, potential=False, workspace=ws)
+        ctx.plan = plan
+        ctx.ws = ws
+        ctx.save_for_backward(pos.detach(), q.detach())
+        return out["forces"]
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        pos, q = ctx.saved_tensors
+        gq, gp = ctx.plan.force_vjp(ctx.ws, pos, q, grad_f.detach())
+        return gp, gq, None
+
+
+def lr_forces(pos, q, plan):
+    return PSWFLRForces.apply(pos, q, plan)

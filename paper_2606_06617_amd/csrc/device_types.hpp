@@ -209,6 +209,16 @@ struct RsWork {
   double *part;           // [ncell][C + 6]: per-cell energy and virial partials
 };
 
+// Options of a spreading launch beyond the plain charge grid: another
+// charge array (cell order [C][N]; NULL: the sorted charges), the axis whose
+// window factor is replaced by its derivative (-1: none), and whether the
+// result is added to the grid instead of stored.
+struct SpreadSrc {
+  const float *q = nullptr;
+  int dax = -1;
+  int acc = 0;
+};
+
 // One structure of a batched call: everything a stage body needs.
 struct BatchItem {
   Geo g;

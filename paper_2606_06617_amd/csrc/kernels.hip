@@ -333,6 +333,25 @@ __device__ __forceinline__ float2 win_eval_d(const float *wc, float t) {
   return make_float2(r, t < 0.0f ? -dv : dv);
 }
 
+// value, d/dt and d^2/dt^2
+__device__ __forceinline__ float3 win_eval_dd(const float *wc, float t) {
+  float a = fabsf(t);
+  float y = a * kWinSeg;
+  int s = min(int(y), kWinSeg - 1);
+  float tau = 2.0f * (y - s) - 1.0f;
+  float c[12];
+  win_coef(wc, s, c);
+  float r = c[kWinDeg], d1 = 0.0f, d2 = 0.0f;   // d2 accumulates p'' / 2
+#pragma unroll
+  for (int d = kWinDeg - 1; d >= 0; --d) {
+    d2 = fmaf(d2, tau, d1);
+    d1 = fmaf(d1, tau, r);
+    r = fmaf(r, tau, c[d]);
+  }
+  const float sc = 2.0f * kWinSeg;
+  return make_float3(r, (t < 0.0f ? -d1 : d1) * sc, 2.0f * d2 * sc * sc);
+}
+
 __device__ __forceinline__ int unpack_n0(unsigned v, int a) { return int((v >> (10 * a)) & 1023u); }
 
 // ---------------------------------------------------------------------------
@@ -655,7 +674,7 @@ template <int P, int NBZ, int CG>
 __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg0, int ncg, int ncand, const int *sz,
                                              float *cq, float *cw, const int *cd, const float *cf, const int *ci,
                                              const float *wcf, const int (&bo)[3], bool wval, unsigned short *cbits,
-                                             unsigned short *hl, SpreadAcc<CG> &accs) {
+                                             unsigned short *hl, SpreadAcc<CG> &accs, const SpreadSrc &src) {
   constexpr int CPW = kSpreadNBW / NBZ;
   constexpr bool MF = spread_mfma(CG);
   const int tid = threadIdx.x, lane = tid & 63;
@@ -674,8 +693,9 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
       // all charge loads in flight at once (channel index clamped, unused
       // channels zeroed when stored)
       const int i = ci[k];
+      const float *qs = src.q ? src.q : w.q_a;
 #pragma unroll
-      for (int c = 0; c < spread_cg4(CG); ++c) qv[c] = w.q_a[int64_t(cg0 + min(c, ncg - 1)) * g.N + i];
+      for (int c = 0; c < spread_cg4(CG); ++c) qv[c] = qs[int64_t(cg0 + min(c, ncg - 1)) * g.N + i];
     }
     const int d = ((cd[k] >> (10 * a)) & 1023) - kSpreadBias;  // tile-relative window start
     const float r = cf[3 * k + a];
@@ -693,7 +713,11 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
       if (x < 0) x += Ma;
       if (x >= Ma) x -= Ma;
       if (x < Ba) {
-        dst[(a == 2 && !MF) ? (x & 3) * NBZ + (x >> 2) : x] = win_eval(wcf, (2.0f * (l + r)) / P - 1.0f);
+        const float tt = (2.0f * (l + r)) / P - 1.0f;
+        // the derivative factor d psi / dt * 2 / (P h) on the chosen axis
+        // (dipole grids of the second derivatives), psi elsewhere
+        dst[(a == 2 && !MF) ? (x & 3) * NBZ + (x >> 2) : x] =
+            a == src.dax ? win_eval_d(wcf, tt).y * g.dwin[a] : win_eval(wcf, tt);
         bits |= 1u << (x >> 2);
       }
     }
@@ -833,7 +857,8 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
 }
 
 template <int P, int NBZ, int CG>
-__device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, int bx) {
+__device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, int bx,
+                                            const SpreadSrc &src) {
   constexpr int CPW = kSpreadNBW / NBZ;
   extern __shared__ float smem[];
   const int Bx = g.B[0], By = g.B[1], Bz = g.B[2];
@@ -979,7 +1004,7 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
     while (nlist - c0 >= kSpreadCap || (last && c0 < nlist)) {
       const int n = min(kSpreadCap, nlist - c0);
       spread_flush<P, NBZ, CG>(g, w, cg0, ncg, n, sz, cq, cw, ld + c0, lf + 3 * c0, li + c0, wcf, bo, wval, cbits, hl,
-                               acc);
+                               acc, src);
       c0 += n;
     }
     // keep the unflushed tail (fewer than kSpreadCap <= threads entries)
@@ -1071,10 +1096,16 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
 #pragma unroll
       for (int r = 0; r < kSpreadOutMax; ++r) {
         if (goff[r] < 0) continue;
-        if (vec)
-          *reinterpret_cast<float4 *>(gch + goff[r]) = *reinterpret_cast<const float4 *>(sch + soffs[r]);
-        else
-          gch[goff[r]] = sch[soffs[r]];
+        if (vec) {
+          float4 v = *reinterpret_cast<const float4 *>(sch + soffs[r]);
+          if (src.acc) {
+            const float4 o = *reinterpret_cast<const float4 *>(gch + goff[r]);
+            v = make_float4(v.x + o.x, v.y + o.y, v.z + o.z, v.w + o.w);
+          }
+          *reinterpret_cast<float4 *>(gch + goff[r]) = v;
+        } else {
+          gch[goff[r]] = src.acc ? sch[soffs[r]] + gch[goff[r]] : sch[soffs[r]];
+        }
       }
     }
     __syncthreads();
@@ -1083,8 +1114,8 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
 
 // CG: channel accumulators per point (2, 4 or 12); a launch covers ncg <= CG
 template <int P, int NBZ, int CG>
-__global__ __launch_bounds__(kSpreadThreads, 4) void k_spread(Geo g, Tables t, Work w, int cg0, int ncg) {
-  spread_body<P, NBZ, CG>(g, t, w, cg0, ncg, blockIdx.x);
+__global__ __launch_bounds__(kSpreadThreads, 4) void k_spread(Geo g, Tables t, Work w, int cg0, int ncg, SpreadSrc src) {
+  spread_body<P, NBZ, CG>(g, t, w, cg0, ncg, blockIdx.x, src);
 }
 
 // ---------------------------------------------------------------------------
@@ -1743,7 +1774,9 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis 
 // (per channel only for the potential).
 //   phi_i   = sum_n pg(n) W(n h - r_i)
 //   F_i     = q_i sum_n pg(n) grad W(n h - r_i)
-// mode 1: forces/potentials; mode 2: adjoint (grad_q = g phi, grad_r = -g F).
+// mode 1: forces/potentials; mode 2: adjoint (grad_q = g phi, grad_r = -g F);
+// mode 3: as 1 without the zero-frequency term in the potentials (grids that
+// are not the charge grid's potential).
 constexpr int kGatherThreads = 512;
 constexpr int kGatherLanes = 4;                                 // lanes per atom
 constexpr int kGatherAtoms = kGatherThreads / kGatherLanes;     // atoms per pass
@@ -1921,7 +1954,7 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
         if (act && l == 0) {
           const double gsc = mode == 2 ? grad[c] : 1.0;
           // potential includes the zero-frequency term dE_0/dq = 2 a Q_net
-          const float zero = float(2.0 * t.zero_V[c] / g.V * w.qsum[2 * c] * gsc);
+          const float zero = mode == 3 ? 0.0f : float(2.0 * t.zero_V[c] / g.V * w.qsum[2 * c] * gsc);
           pout[int64_t(c) * g.N + dst_atom] = vphi + zero;
         }
       }
@@ -2044,6 +2077,109 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_check_inputs(const float *__re
 
 
 // ---------------------------------------------------------------------------
+// Second derivatives for force-matching training (the derivatives of
+// L = sum_i v_i . F_i).  With psi the potential grid of the forward call
+// (phi = W^T psi, F_i = -q_i grad_i (W^T psi)) and u the dipole grid
+// u(n) = sum_i q_i (v_i . grad_{r_i}) W(n h - r_i):
+//   dL/dq_i = -v_i . grad phi(r_i) - (W^T A u)_i
+//   dL/dr_i = -q_i (Hess phi(r_i)) v_i - q_i grad_i (W^T A u)
+// where A is the forward's convolution (FFT, Phi_p / What^2, inverse FFT).
+
+// dipole charges in cell order: qd[a][c][k] = -q_c(k) v_a(k), so that
+// u = sum_a spread(qd[a], derivative factor on axis a)
+__global__ __launch_bounds__(PSWF_THREADS) void k_dd_prep(Geo g, Work w, const float *__restrict__ v, float *qd) {
+  const int64_t e = int64_t(blockIdx.x) * PSWF_THREADS + threadIdx.x;
+  const int64_t cn = int64_t(g.C) * g.N;
+  if (e >= cn) return;
+  const int64_t k = e % g.N;
+  const int i = w.perm_a[k];
+  const float qv = w.q_a[e];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) qd[a * cn + e] = -qv * v[3 * int64_t(i) + a];
+}
+
+// one thread per atom: grad phi and the Hessian of phi at the atom from the
+// potential grid (separable window, its first and second derivatives);
+// writes s1 = v . grad phi per channel and -sum_c q_c (Hess phi_c) v
+template <int P>
+__global__ __launch_bounds__(PSWF_THREADS) void k_gather_hess(Geo g, Tables t, Work w, const float *__restrict__ v,
+                                                             float *__restrict__ s1, float *__restrict__ hv) {
+  __shared__ float wcf[kWinSeg * (kWinDeg + 1)];
+  for (int e = threadIdx.x; e < kWinSeg * (kWinDeg + 1); e += PSWF_THREADS) wcf[e] = t.win[e];
+  __syncthreads();
+  const int64_t k = int64_t(blockIdx.x) * PSWF_THREADS + threadIdx.x;
+  if (k >= g.N) return;
+  const float4 rr = reinterpret_cast<const float4 *>(w.rec_a)[k];
+  const unsigned pk = __float_as_uint(rr.w);
+  const float dl[3] = {rr.x, rr.y, rr.z};
+  float W[3][P], D[3][P], DD[3][P];
+  int n[3][P];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int n0 = unpack_n0(pk, a);
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+      const float3 f = win_eval_dd(wcf, (2.0f * (l + dl[a])) / P - 1.0f);
+      W[a][l] = f.x;
+      D[a][l] = f.y * g.dwin[a];
+      DD[a][l] = f.z * g.dwin[a] * g.dwin[a];
+      int m = n0 + l;
+      if (m >= g.M[a]) m -= g.M[a];
+      n[a][l] = m;
+    }
+  }
+  const int i = w.perm_a[k];
+  const float vx = v[3 * int64_t(i)], vy = v[3 * int64_t(i) + 1], vz = v[3 * int64_t(i) + 2];
+  const int64_t chan = int64_t(g.M[0]) * g.M[1] * g.M[2];
+  float h0 = 0.f, h1 = 0.f, h2 = 0.f;
+  for (int c = 0; c < g.C; ++c) {
+    const float *psi = w.grid + int64_t(c) * chan;
+    float gx = 0.f, gy = 0.f, gz = 0.f, hxx = 0.f, hyy = 0.f, hzz = 0.f, hxy = 0.f, hxz = 0.f, hyz = 0.f;
+    for (int lx = 0; lx < P; ++lx) {
+      for (int ly = 0; ly < P; ++ly) {
+        const float *row = psi + (int64_t(n[0][lx]) * g.M[1] + n[1][ly]) * g.M[2];
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+        for (int lz = 0; lz < P; ++lz) {
+          const float val = row[n[2][lz]];
+          a0 = fmaf(W[2][lz], val, a0);
+          a1 = fmaf(D[2][lz], val, a1);
+          a2 = fmaf(DD[2][lz], val, a2);
+        }
+        const float ww = W[0][lx] * W[1][ly], dw = D[0][lx] * W[1][ly], wd = W[0][lx] * D[1][ly];
+        // d W / d x_a = -D_a (other factors); d2 W / d x_a d x_b = D_a D_b (...)
+        gx -= dw * a0;
+        gy -= wd * a0;
+        gz -= ww * a1;
+        hxx = fmaf(DD[0][lx] * W[1][ly], a0, hxx);
+        hyy = fmaf(W[0][lx] * DD[1][ly], a0, hyy);
+        hzz = fmaf(ww, a2, hzz);
+        hxy = fmaf(D[0][lx] * D[1][ly], a0, hxy);
+        hxz = fmaf(dw, a1, hxz);
+        hyz = fmaf(wd, a1, hyz);
+      }
+    }
+    s1[int64_t(c) * g.N + i] = vx * gx + vy * gy + vz * gz;
+    const float qc = w.q_a[int64_t(c) * g.N + k];
+    h0 -= qc * (hxx * vx + hxy * vy + hxz * vz);
+    h1 -= qc * (hxy * vx + hyy * vy + hyz * vz);
+    h2 -= qc * (hxz * vx + hyz * vy + hzz * vz);
+  }
+  hv[3 * int64_t(i)] = h0;
+  hv[3 * int64_t(i) + 1] = h1;
+  hv[3 * int64_t(i) + 2] = h2;
+}
+
+// dL/dq = -(s1 + s2), dL/dr = hv + F2 (caller order)
+__global__ __launch_bounds__(PSWF_THREADS) void k_dd_combine(int64_t cn, int64_t n3, float *__restrict__ gq,
+                                                            const float *__restrict__ s2, float *__restrict__ gp,
+                                                            const float *__restrict__ f2) {
+  const int64_t e = int64_t(blockIdx.x) * PSWF_THREADS + threadIdx.x;
+  if (e < cn) gq[e] = -(gq[e] + s2[e]);
+  if (e < n3) gp[e] += f2[e];
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 static inline unsigned nblocks(int64_t n, int per) { return unsigned((n + per - 1) / per); }
 
@@ -2159,43 +2295,47 @@ hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t
 }
 
 template <int P, int NBZ, int CG>
-static hipError_t spread_pzc(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
+static hipError_t spread_pzc(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st,
+                             const SpreadSrc &src) {
   hipError_t e = lds_request(reinterpret_cast<const void *>(&k_spread<P, NBZ, CG>), spread_lds_bytes(g, CG));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_spread<P, NBZ, CG>), dim3(g.ncell), dim3(kSpreadThreads), spread_lds_bytes(g, CG), st, g, t,
-                     w, cg0, ncg);
+                     w, cg0, ncg, src);
   LAUNCH_CHECK();
   return hipSuccess;
 }
 
 template <int P, int NBZ>
-static hipError_t spread_pz(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
+static hipError_t spread_pz(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st,
+                            const SpreadSrc &src) {
   switch (spread_cg_template(g.CG_spread)) {
-    case 2: return spread_pzc<P, NBZ, 2>(g, t, w, cg0, ncg, st);
-    case 4: return spread_pzc<P, NBZ, 4>(g, t, w, cg0, ncg, st);
-    default: return spread_pzc<P, NBZ, kSpreadCGM>(g, t, w, cg0, ncg, st);
+    case 2: return spread_pzc<P, NBZ, 2>(g, t, w, cg0, ncg, st, src);
+    case 4: return spread_pzc<P, NBZ, 4>(g, t, w, cg0, ncg, st, src);
+    default: return spread_pzc<P, NBZ, kSpreadCGM>(g, t, w, cg0, ncg, st, src);
   }
 }
 
 template <int P>
-static hipError_t spread_p(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
+static hipError_t spread_p(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st,
+                           const SpreadSrc &src) {
   switch (spread_nbz(g.B[2])) {
-    case 1: return spread_pz<P, 1>(g, t, w, cg0, ncg, st);
-    case 2: return spread_pz<P, 2>(g, t, w, cg0, ncg, st);
-    case 4: return spread_pz<P, 4>(g, t, w, cg0, ncg, st);
+    case 1: return spread_pz<P, 1>(g, t, w, cg0, ncg, st, src);
+    case 2: return spread_pz<P, 2>(g, t, w, cg0, ncg, st, src);
+    case 4: return spread_pz<P, 4>(g, t, w, cg0, ncg, st, src);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_spread(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st) {
+hipError_t launch_spread(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st,
+                         const SpreadSrc &src) {
   switch (g.P) {
-    case 2: return spread_p<2>(g, t, w, cg0, ncg, st);
-    case 3: return spread_p<3>(g, t, w, cg0, ncg, st);
-    case 4: return spread_p<4>(g, t, w, cg0, ncg, st);
-    case 5: return spread_p<5>(g, t, w, cg0, ncg, st);
-    case 6: return spread_p<6>(g, t, w, cg0, ncg, st);
-    case 7: return spread_p<7>(g, t, w, cg0, ncg, st);
-    case 8: return spread_p<8>(g, t, w, cg0, ncg, st);
+    case 2: return spread_p<2>(g, t, w, cg0, ncg, st, src);
+    case 3: return spread_p<3>(g, t, w, cg0, ncg, st, src);
+    case 4: return spread_p<4>(g, t, w, cg0, ncg, st, src);
+    case 5: return spread_p<5>(g, t, w, cg0, ncg, st, src);
+    case 6: return spread_p<6>(g, t, w, cg0, ncg, st, src);
+    case 7: return spread_p<7>(g, t, w, cg0, ncg, st, src);
+    case 8: return spread_p<8>(g, t, w, cg0, ncg, st, src);
   }
   return hipErrorInvalidValue;
 }
@@ -2303,6 +2443,53 @@ hipError_t noalloc_scratch(void **out) {
     addr[dev] = p;
   }
   *out = addr[dev];
+  return hipSuccess;
+}
+
+template <int P>
+static hipError_t hess_p(const Geo &g, const Tables &t, const Work &w, const float *v, float *s1, float *hv,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_hess<P>, dim3(nblocks(g.N, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, t, w, v, s1, hv);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_double_backward(const Geo &g, const Tables &t, const FftAxis &az, const FftAxis &ay,
+                                  const FftAxis &ax, const Work &w, const float *v, float *qd, float *s2, float *f2,
+                                  float *grad_q, float *grad_pos, hipStream_t st) {
+  if (g.N == 0) return hipSuccess;
+  hipError_t e = hipErrorInvalidValue;
+  switch (g.P) {
+    case 2: e = hess_p<2>(g, t, w, v, grad_q, grad_pos, st); break;
+    case 3: e = hess_p<3>(g, t, w, v, grad_q, grad_pos, st); break;
+    case 4: e = hess_p<4>(g, t, w, v, grad_q, grad_pos, st); break;
+    case 5: e = hess_p<5>(g, t, w, v, grad_q, grad_pos, st); break;
+    case 6: e = hess_p<6>(g, t, w, v, grad_q, grad_pos, st); break;
+    case 7: e = hess_p<7>(g, t, w, v, grad_q, grad_pos, st); break;
+    case 8: e = hess_p<8>(g, t, w, v, grad_q, grad_pos, st); break;
+  }
+  if (e != hipSuccess) return e;
+  const int64_t cn = int64_t(g.C) * g.N;
+  hipLaunchKernelGGL(k_dd_prep, dim3(nblocks(cn, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, w, v, qd);
+  LAUNCH_CHECK();
+  // the potential grid is no longer needed: the dipole grid takes its place
+  for (int a = 0; a < 3; ++a) {
+    SpreadSrc src;
+    src.q = qd + a * cn;
+    src.dax = a;
+    src.acc = a > 0;
+    for (int cg0 = 0; cg0 < g.C; cg0 += g.CG_spread)
+      if ((e = launch_spread(g, t, w, cg0, std::min(g.CG_spread, g.C - cg0), st, src)) != hipSuccess) return e;
+  }
+  if ((e = launch_zfwd(g, t, az, w, st)) != hipSuccess) return e;
+  if ((e = launch_yfwd(g, t, ay, w, st)) != hipSuccess) return e;
+  if ((e = launch_xmul(g, t, ax, w, 1, nullptr, st)) != hipSuccess) return e;
+  if ((e = launch_yinv(g, t, ay, w, st)) != hipSuccess) return e;
+  if ((e = launch_zinv(g, t, az, w, st)) != hipSuccess) return e;
+  if ((e = launch_gather(g, t, w, f2, s2, 3, nullptr, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dd_combine, dim3(nblocks(std::max(cn, 3 * g.N), PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, cn,
+                     3 * g.N, grad_q, s2, grad_pos, f2);
+  LAUNCH_CHECK();
   return hipSuccess;
 }
 
@@ -2425,7 +2612,7 @@ __global__ __launch_bounds__(kSpreadThreads, 4) void k_batch_spread(const BatchI
   const BatchItem &it = items[s];
   const Geo &g = it.g;
   if (g.P != P || spread_nbz(g.B[2]) != NBZ || spread_cg_template(g.C) != CG) return;
-  spread_body<P, NBZ, CG>(g, it.t, it.w, 0, g.C, b - prefix[s]);
+  spread_body<P, NBZ, CG>(g, it.t, it.w, 0, g.C, b - prefix[s], SpreadSrc{});
 }
 
 template <int P, int NBZ, int CG>

@@ -32,7 +32,8 @@ int spread_max_cells();
 
 hipError_t enqueue_sort(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st);
 hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t st);
-hipError_t launch_spread(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st);
+hipError_t launch_spread(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st,
+                         const SpreadSrc &src = SpreadSrc{});
 hipError_t launch_zfwd(const Geo &g, const Tables &t, const FftAxis &az, const Work &w, hipStream_t st);
 hipError_t launch_yfwd(const Geo &g, const Tables &t, const FftAxis &ay, const Work &w, hipStream_t st);
 // mode 0: energy only, 1: energy + potential grid, 2: adjoint scaled by grad[c]
@@ -42,6 +43,12 @@ hipError_t launch_yinv(const Geo &g, const Tables &t, const FftAxis &ay, const W
 hipError_t launch_zinv(const Geo &g, const Tables &t, const FftAxis &az, const Work &w, hipStream_t st);
 hipError_t launch_gather(const Geo &g, const Tables &t, const Work &w, float *forces, float *pot, int mode,
                          const double *grad, hipStream_t st);
+// derivatives of sum_i v_i . F_i after a forward call with forces on the
+// same workspace (its potential grid is overwritten); qd [3 C N], s2 [C N],
+// f2 [N][3] are scratch
+hipError_t launch_double_backward(const Geo &g, const Tables &t, const FftAxis &az, const FftAxis &ay,
+                                  const FftAxis &ax, const Work &w, const float *v, float *qd, float *s2, float *f2,
+                                  float *grad_q, float *grad_pos, hipStream_t st);
 // input validation: word w.status[1] gets bit 0 for a non-finite position,
 // bit 1 for a non-finite charge
 hipError_t launch_check_inputs(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st);

@@ -170,6 +170,7 @@ struct pswflr_plan_s {
   int rs_ngrp = 0, rs_cgmax = 0;
   size_t off_rs_rec_b = 0, off_rs_rec_a = 0, off_rs_perm_b = 0, off_rs_perm_a = 0, off_rs_cell_of = 0,
          off_rs_slot = 0, off_rs_count = 0, off_rs_start = 0, off_rs_part = 0;
+  size_t off_dd = 0;  // scratch of the second-derivative call: [3 C N + C N + 3 N] floats
   // optional per-stage event timing (measurement only)
   bool prof = false;
   std::mutex prof_mu;
@@ -587,6 +588,7 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   pl.off_rs_count = take(size_t(pl.rsg.ncell) * 4);
   pl.off_rs_start = take(size_t(pl.rsg.ncell + 1) * 4);
   pl.off_rs_part = take(size_t(pl.rsg.ncell) * (C + 6) * 8);
+  pl.off_dd = take(size_t(Nm) * (4 * size_t(C) + 3) * 4);
   pl.ws_bytes = o;
   pl.max_atoms = max_atoms;
 
@@ -861,6 +863,29 @@ pswflr_status pswflr_realspace(pswflr_plan plan, pswflr_stream stream, void *wor
   rw.part = reinterpret_cast<double *>(b + plan->off_rs_part);
   hipError_t e = launch_realspace(rg, plan->rst, rw, plan->rs_grp, plan->rs_gch, plan->rs_ngrp, plan->rs_cgmax, pos,
                                   q, energy, forces, virial, potential, st);
+  if (e == hipSuccess) e = mark_use(st, &plan, 1);
+  if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return PSWFLR_OK;
+}
+
+pswflr_status pswflr_force_vjp(pswflr_plan plan, pswflr_stream stream, void *workspace, size_t ws_bytes,
+                                int64_t n_atoms, const float *pos, const float *q, const float *v, float *grad_q,
+                                float *grad_pos) {
+  pswflr_status s = check_call(plan, workspace, ws_bytes, n_atoms, pos, q);
+  if (s != PSWFLR_OK) return s;
+  if (n_atoms > 0 && (!v || !grad_q || !grad_pos))
+    return fail(PSWFLR_ERR_INVALID_ARG, "v, grad_q and grad_pos are required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Geo g = plan->geo;
+  g.N = n_atoms;
+  Work w = carve(*plan, workspace, n_atoms);
+  char *b = static_cast<char *>(workspace) + plan->off_dd;
+  const size_t cn = size_t(g.C) * size_t(n_atoms);
+  float *qd = reinterpret_cast<float *>(b);
+  float *s2 = qd + 3 * cn;
+  float *f2 = s2 + cn;
+  hipError_t e = launch_double_backward(g, plan->tab, plan->az, plan->ay, plan->ax, w, v, qd, s2, f2, grad_q,
+                                        grad_pos, st);
   if (e == hipSuccess) e = mark_use(st, &plan, 1);
   if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return PSWFLR_OK;
