@@ -27,6 +27,8 @@ at fixed number density and replicated to large sizes):
                  >= L / 0.535 A clamped to [24, 64].
   serving_stream Poisson arrivals, N log-uniform in [100, 50000], density
                  0.1, p in {1, 6} neutralised N(0, 0.5).
+  nacl_primitive rock salt on its face-centred primitive (triclinic) cell.
+  triclinic_box  uniform random positions in a skewed cell.
 """
 import math
 
@@ -75,6 +77,61 @@ def nacl(ncell=4, a=5.64, jitter=0.1, seed=1):
     L = ncell * a
     return _finish(pos, q[None, :], [L, L, L], [1], (32, 32, 32), 6,
                    "nacl_%d" % pos.shape[0])
+
+
+def _finish_cell(pos, q, cell, ps, grid, support, name):
+    """As _finish for a general cell (lattice vectors as the rows of `cell`):
+    positions are wrapped into the parallelepiped through their fractional
+    coordinates; "box" holds the 3x3 cell."""
+    cell = np.asarray(cell, dtype=np.float64)
+    frac = np.asarray(pos, dtype=np.float64) @ np.linalg.inv(cell)
+    frac -= np.floor(frac)
+    frac = np.where(frac >= 1.0, 0.0, frac)
+    out = _finish(frac @ cell, q, [np.inf] * 3, ps, grid, support, name)
+    out["box"] = cell
+    return out
+
+
+def nacl_primitive(ncell=4, a=5.64, jitter=0.0, seed=7):
+    """Rock salt on its face-centred primitive cell (a triclinic description
+    of the same crystal): lattice vectors a/2 (0,1,1), a/2 (1,0,1),
+    a/2 (1,1,0), one Na+ at each lattice point and one Cl- displaced by
+    (a/2, 0, 0); ncell^3 primitive cells (2 ncell^3 ions)."""
+    rng = _rng(seed)
+    prim = 0.5 * a * np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0], [1.0, 1.0, 0.0]])
+    idx = np.array([[i, j, k] for i in range(ncell) for j in range(ncell)
+                    for k in range(ncell)], dtype=np.float64)
+    na = idx @ prim
+    cl = na + np.array([a / 2, 0.0, 0.0])
+    pos = np.empty((2 * na.shape[0], 3))
+    pos[0::2] = na
+    pos[1::2] = cl
+    q = np.empty(pos.shape[0])
+    q[0::2] = 1.0
+    q[1::2] = -1.0
+    if jitter > 0:
+        pos = pos + rng.normal(0.0, jitter, pos.shape)
+    return _finish_cell(pos, q[None, :], ncell * prim, [1], None, None, "nacl_prim_%d" % pos.shape[0])
+
+
+# a skewed cell shape (rows: lattice vectors before scaling); every angle
+# between lattice vectors differs from 90 degrees
+TRICLINIC_SHAPE = ((1.0, 0.0, 0.0), (0.31, 0.95, 0.0), (-0.22, 0.27, 0.93))
+
+
+def triclinic_box(n, ps=(1, 6), seed=8, density=DENSITY, shape=TRICLINIC_SHAPE, neutral=True):
+    """Uniform random positions in a triclinic cell of the given shape scaled
+    to the density; charges N(0, 0.5), neutralised per channel if asked."""
+    rng = _rng(seed)
+    shape = np.asarray(shape, dtype=np.float64)
+    s = (n / density / abs(np.linalg.det(shape))) ** (1.0 / 3.0)
+    cell = shape * s
+    pos = rng.uniform(0.0, 1.0, size=(n, 3)) @ cell
+    if neutral:
+        q = _neutral_charges(rng, len(ps), n)
+    else:
+        q = rng.normal(0.0, 0.5, size=(len(ps), n))
+    return _finish_cell(pos, q, cell, list(ps), None, None, "triclinic_%d" % n)
 
 
 def _random_rotations(rng, n):
