@@ -35,7 +35,8 @@ lattice basis (the same lattice described by other vectors); forces equal
 to minus central finite differences of the energy in a triclinic cell; the
 whole virial tensor, off-diagonal entries included, equal to minus central
 finite differences of the energy under affine strain of the cell and the
-positions.
+positions; force_vjp (the double backward) against central differences of
+L = sum v . F formed from the forces of evaluate.
 """
 import numpy as np
 
@@ -125,3 +126,39 @@ def evaluate(pos, q, cell, ps, c, r_c, sample=None, virial=True, chunk=8192):
             F += (2.0 / V) * q[ch][idx][:, None] * ((t.imag * f[None, :]) @ kv)
         phi[ch] += 2.0 * a * qn
     return {"Ek": Ek, "E0": E0, "Eself": Es, "phi": phi, "F": F, "W": W, "sample": idx}
+
+
+def force_vjp(pos, q, cell, ps, c, r_c, v):
+    """Derivatives of L = sum_i v_i . F_i (F the forces of sum_c E_k + E_0)
+    in the charges and positions, for a general cell: the same sums as
+    oracle.reciprocal.force_vjp over k = 2 pi m H^-T, V = |det H|.  With
+    T(k) = sum_i q_i (v_i . k) e^{i k.r_i} and S the structure factor,
+
+      dL/dq_j = (1/V) sum_k Phi_p Im(e^{-i k.r_j} T + conj(S) (v_j . k) e^{i k.r_j})
+      dL/dr_j = (q_j/V) sum_k Phi_p k [-Re(e^{-i k.r_j} T) + (v_j . k) Re(conj(S) e^{i k.r_j})]
+
+    over the whole ball (the half space counted twice).  Returns dq [C, N]
+    and dr [N, 3] (summed over channels)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.atleast_2d(np.asarray(q, dtype=np.float64))
+    v = np.asarray(v, dtype=np.float64)
+    H = np.asarray(cell, dtype=np.float64)
+    V = abs(float(np.linalg.det(H)))
+    C, n = q.shape
+    _, kvec, kn, _ = half_space_modes(H, c / r_c)
+    dq = np.zeros((C, n))
+    dr = np.zeros((n, 3))
+    for ch in range(C):
+        fk = kernels.phi_hat(int(ps[ch]), kn, c, r_c)
+        for s in range(0, kn.size, 4096):
+            kv = kvec[s:s + 4096]
+            f = fk[s:s + 4096]
+            ph = np.exp(1j * (pos @ kv.T))            # [N, K]
+            vk = v @ kv.T                             # v_i . k
+            S = q[ch] @ ph
+            T = (q[ch][:, None] * vk * ph).sum(axis=0)
+            a = np.conj(ph) * T[None, :]
+            b = np.conj(S)[None, :] * ph
+            dq[ch] += (2.0 / V) * ((a.imag + vk * b.imag) @ f)
+            dr += (2.0 / V) * q[ch][:, None] * (((-a.real + vk * b.real) * f[None, :]) @ kv)
+    return dq, dr

@@ -111,3 +111,39 @@ def test_orthorhombic_off_diagonal_virial_against_sheared_cell(p):
         H = np.diag(box)
         fd = -(_etot(pos @ Fp, q[:1], H @ Fp, [p]) - _etot(pos @ Fm, q[:1], H @ Fm, [p])) / (2 * h)
         assert r["W"][a, b] == pytest.approx(fd, rel=1e-6, abs=1e-8 * np.abs(r["W"]).max()), (a, b)
+
+
+def _vjp_system():
+    rng = np.random.default_rng(19)
+    H = np.array([[9.0, 0.0, 0.0], [2.2, 9.5, 0.0], [-1.4, 1.9, 8.1]])
+    n = 18
+    pos = rng.uniform(0.0, 1.0, (n, 3)) @ H
+    q = rng.normal(0.0, 0.5, (2, n))
+    v = rng.normal(0.0, 1.0, (n, 3))
+    return pos, q, H, (1, 6), v
+
+
+def _vjp_loss(pos, q, H, ps, v):
+    F = cellsum.evaluate(pos, q, H, ps, C_MOL, 5.0, virial=False)["F"]
+    return float(np.sum(v * F))
+
+
+def test_force_vjp_against_finite_differences_of_forces():
+    # the double backward in a triclinic cell: derivatives of L = sum v . F
+    # against central differences of L formed from the oracle's own forces
+    pos, q, H, ps, v = _vjp_system()
+    dq, dr = cellsum.force_vjp(pos, q, H, ps, C_MOL, 5.0, v)
+    h = 1e-6
+    for ch, j in ((0, 2), (1, 9), (0, 17)):
+        qp, qm = q.copy(), q.copy()
+        qp[ch, j] += h
+        qm[ch, j] -= h
+        fd = (_vjp_loss(pos, qp, H, ps, v) - _vjp_loss(pos, qm, H, ps, v)) / (2 * h)
+        assert dq[ch, j] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+    for j in (0, 11):
+        for a in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[j, a] += h
+            pm[j, a] -= h
+            fd = (_vjp_loss(pp, q, H, ps, v) - _vjp_loss(pm, q, H, ps, v)) / (2 * h)
+            assert dr[j, a] == pytest.approx(fd, rel=1e-5, abs=1e-8)
