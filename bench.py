@@ -288,7 +288,8 @@ def serving_leg(nreq=2000, seed=6, fractions=(0.5, 0.8, 0.95), slots=4, max_batc
                              "service_p99_ms": round(st["service_p99_ms"], 3),
                              "service_max_ms": round(st["service_max_ms"], 3),
                              "plan_p99_ms": round(st["plan_p99_ms"], 3),
-                             "max_concurrency": srv.max_concurrency, "launches": srv.launches,
+                             "max_concurrency": srv.max_concurrency,
+                             "max_inflight_requests": srv.max_inflight_requests, "launches": srv.launches,
                              "max_coalesced": srv.max_coalesced})
     return out
 

@@ -22,8 +22,12 @@
  * Conventions
  *  - Units: lengths in the caller's unit (Angstrom in the paper); energies in
  *    q^2 / length^p; any Coulomb or C6 prefactor is applied by the caller.
- *  - Cell: orthorhombic, edges box[0..2] > 0, origin at 0; positions outside
- *    [0, L) are wrapped.
+ *  - Cell: the cell tensor of the Fig. 1 caption, a 3x3 matrix H whose rows
+ *    are the lattice vectors (pswflr_params.cell), or an orthorhombic box
+ *    H = diag(box) when cell is all zeros; origin at 0.  The grid axes run
+ *    along the lattice vectors (M_a points on a_a), wave vectors are
+ *    k = 2 pi H^-1 m, V = |det H|.  Positions outside the cell are wrapped
+ *    (periodically, through their fractional coordinates).
  *  - Memory: every array argument of the execute calls is a DEVICE pointer
  *    owned by the caller; the library never allocates in the execute calls.
  *    A plan owns a small device table (kilobytes) allocated at creation.
@@ -95,6 +99,13 @@ typedef struct {
                                         planner's choice.  Each must divide
                                         the grid edge (autotuner knob)       */
   uint32_t flags;                    /* PSWFLR_FLAG_* bits, 0 for none        */
+  double cell[9];                    /* general cell: lattice vectors as rows
+                                        (row-major H); finite, non-singular
+                                        and not degenerate (every width across
+                                        a lattice plane > 1e-3 of the vector
+                                        lengths).  All zeros: the orthorhombic
+                                        box above; otherwise box is ignored.
+                                        Automatic grids use |a_a| per axis  */
 } pswflr_params;
 
 /* Resolved plan (Methods, "Parameter selection"): what the automatic
@@ -120,6 +131,7 @@ typedef struct {
   size_t grid_offset;     /* byte offset of the real grids [C][Mx][My][Mz]   */
   double self_coef[PSWFLR_MAX_CHANNELS]; /* E_self^(c) = self_coef * sum q^2 */
   double zero_coef[PSWFLR_MAX_CHANNELS]; /* E_0^(c) = zero_coef * (sum q)^2  */
+  double cell[9];         /* the cell H in use (rows: lattice vectors)       */
 } pswflr_info;
 
 /* Build a plan: host FP64 set-up of the PSWF, the kernel and window
@@ -187,7 +199,7 @@ pswflr_status pswflr_force_vjp(pswflr_plan plan, pswflr_stream stream, void *wor
 /* The real-space complement of the split (Eq. realLR; Methods,
  * "Implementation details"): for each channel c,
  *   E_real^(c) = 1/2 sum_n sum'_{i,j} q_i q_j (1 - G_p(r)) / r^p,
- * r = |r_j - r_i + n L| < r_c over all periodic images n (the prime drops
+ * r = |r_j - r_i + n H| < r_c over all periodic images n (the prime drops
  * i = j at n = 0), with G_p the PSWF mollifier of Eqs. G1, G6, G at the
  * plan's c and r_c.  Together with pswflr_execute this gives the complete
  * energy of Eq. realLR: E = sum_c (E_real + E_k + E_0 - E_self).
@@ -238,6 +250,19 @@ pswflr_status pswflr_backward(pswflr_plan plan, pswflr_stream stream, void *work
                               size_t ws_bytes, int64_t n_atoms, const float *pos,
                               const float *q, const double *grad_energy,
                               float *grad_q, float *grad_pos);
+
+/* Derivative of the energy with respect to the cell tensor (Fig. 1
+ * caption: the cell is an input and the virial comes from differentiation;
+ * constant-pressure dynamics moves the cell).  From a virial W [6] (device
+ * double, xx, yy, zz, xy, xz, yz, as written by pswflr_execute or
+ * pswflr_realspace with this plan: W = -dE/d(strain), positions moving with
+ * the cell), writes
+ *   grad_cell [9] device double, row-major: dE/dH_ab = -(H^-T W)_ab
+ * the derivative at fixed fractional coordinates (H -> H (1 + e)^T moves
+ * every position r -> (1 + e) r).  One work-item on `stream`; both pointers
+ * caller-owned.  Errors: INVALID_ARG, DEVICE. */
+pswflr_status pswflr_cell_gradient(pswflr_plan plan, pswflr_stream stream, const double *virial,
+                                   double *grad_cell);
 
 /* Many structures in one call (MLIP training batches, serving mixes; the
  * paper evaluates configurations of many sizes and boxes, Methods,

@@ -32,6 +32,7 @@ class Params(ctypes.Structure):
         ("c_spread", ctypes.c_double),
         ("tile", ctypes.c_int32 * 3),
         ("flags", ctypes.c_uint32),
+        ("cell", ctypes.c_double * 9),
     ]
 
 
@@ -55,6 +56,7 @@ class Info(ctypes.Structure):
         ("grid_offset", ctypes.c_size_t),
         ("self_coef", ctypes.c_double * MAX_CHANNELS),
         ("zero_coef", ctypes.c_double * MAX_CHANNELS),
+        ("cell", ctypes.c_double * 9),
     ]
 
 
@@ -92,6 +94,7 @@ def lib():
     L.pswflr_execute_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp]
     L.pswflr_realspace.argtypes = [vp, vp, vp, sz, i64, vp, vp, vp, vp, vp, vp]
     L.pswflr_force_vjp.argtypes = [vp, vp, vp, sz, i64, vp, vp, vp, vp, vp]
+    L.pswflr_cell_gradient.argtypes = [vp, vp, vp, vp]
     L.pswflr_batch_workspace.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                          ctypes.POINTER(sz)]
     L.pswflr_execute_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(IO), vp, vp, sz]
@@ -105,7 +108,7 @@ def lib():
     L.pswflr_status_string.restype = ctypes.c_char_p
     L.pswflr_last_error.argtypes = [ctypes.c_char_p, sz]
     for name in ("pswflr_plan_create", "pswflr_plan_info", "pswflr_plan_destroy", "pswflr_execute",
-                 "pswflr_execute_noalloc", "pswflr_realspace", "pswflr_force_vjp",
+                 "pswflr_execute_noalloc", "pswflr_realspace", "pswflr_force_vjp", "pswflr_cell_gradient",
                  "pswflr_backward", "pswflr_batch_workspace", "pswflr_execute_batch",
                  "pswflr_execute_batch_flat", "pswflr_backward_batch_flat",
                  "pswflr_profile_enable", "pswflr_profile_read"):
@@ -135,8 +138,18 @@ def make_params(box, ps, r_c, c=0.0, tol=1e-5, grid=None, support=0, c_spread=0.
     prm.n_channels = len(ps)
     for i, p in enumerate(ps):
         prm.p[i] = int(p)
+    rows = [list(r) if hasattr(r, "__len__") else None for r in box]
+    if len(rows) == 3 and all(r is not None and len(r) == 3 for r in rows):
+        # a 3x3 cell (lattice vectors as rows)
+        for a in range(3):
+            for b in range(3):
+                prm.cell[3 * a + b] = float(rows[a][b])
+    elif len(rows) == 3 and all(r is None for r in rows):
+        for a in range(3):
+            prm.box[a] = float(box[a])
+    else:
+        raise ValueError("box must be 3 edges or a 3x3 cell (rows: lattice vectors)")
     for a in range(3):
-        prm.box[a] = float(box[a])
         prm.grid[a] = int(grid[a]) if grid is not None else 0
     prm.r_c = float(r_c)
     prm.c = float(c or 0.0)

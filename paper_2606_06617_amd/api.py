@@ -21,7 +21,8 @@ def _stream(stream=None):
 class Plan:
     """A resolved PSWF-LR evaluation plan for one box and channel set.
 
-    box: 3 orthorhombic edges; ps: exponent per channel (1..6); r_c: the
+    box: 3 orthorhombic edges, or a 3x3 cell whose rows are the lattice
+    vectors (triclinic); ps: exponent per channel (1..6); r_c: the
     short-range cutoff (k_c = c / r_c); c: mollifier bandwidth (0: from tol);
     grid: (Mx, My, Mz) or None (from tol); support: window points per axis
     P (0: from tol); c_spread: window bandwidth (0: automatic); check_inputs:
@@ -50,9 +51,10 @@ class Plan:
             "grid_offset": inf.grid_offset,
             "self_coef": [inf.self_coef[i] for i in range(C)],
             "zero_coef": [inf.zero_coef[i] for i in range(C)],
+            "cell": tuple(tuple(inf.cell[3 * a + b] for b in range(3)) for a in range(3)),
         }
         self.ps = list(ps)
-        self.box = tuple(float(b) for b in box)
+        self.box = tuple(tuple(float(v) for v in b) if hasattr(b, "__len__") else float(b) for b in box)
         self.C = C
         self.max_atoms = int(max_atoms)
 
@@ -74,6 +76,16 @@ class Plan:
         ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
         assert ws.data_ptr() % 256 == 0
         return ws
+
+    def cell_gradient(self, virial, stream=None):
+        """dE/dH [3, 3] (rows of H: lattice vectors) at fixed fractional
+        coordinates from a device virial [6] of this plan's execute or
+        realspace call: the NPT box derivative, formed on the device."""
+        st = stream if stream is not None else torch.cuda.current_stream()
+        with torch.cuda.stream(st):
+            out = torch.empty(9, dtype=torch.float64, device=virial.device)
+        _lib.check(_lib.lib().pswflr_cell_gradient(self.handle, _stream(st), _ptr(virial), _ptr(out)))
+        return out.view(3, 3)
 
     def execute(self, pos, q, forces=True, virial=True, potential=False, workspace=None, stream=None,
                 out=None):

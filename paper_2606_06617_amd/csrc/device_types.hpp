@@ -41,20 +41,14 @@ inline FastDiv make_fastdiv(int d) {
   return f;
 }
 
-// Window start of one position component.  The grid coordinate
-// u = x M / L is formed as an unevaluated FP32 sum hi + lo: M / L = sh + sl
-// is carried in two floats and the product's rounding error is recovered
-// exactly by an FMA, so u is good to ~1e-14 relative (a plain FP32 product
-// would lose ~3e-5 grid units at M = 256).  The window covers the P nodes
-// n0 .. n0 + P - 1 with n0 = ceil(u - P/2); delta = n0 - (u - P/2) is in
-// [0, 1) and n0 is returned wrapped into [0, M).  Positions a few boxes
-// outside the cell keep their unwrapped coordinate (only the integer start
-// is wrapped, exactly); beyond 2^22 grid units the whole multiple of M is
-// removed from the coordinate first.
-PSWF_HD inline void window_start(float x, float sh, float sl, int M, int P, int *n0, float *delta) {
+// Window start from a grid coordinate u given as an unevaluated FP32 sum
+// p + lo (see grid_coord).  The window covers the P nodes n0 .. n0 + P - 1
+// with n0 = ceil(u - P/2); delta = n0 - (u - P/2) is in [0, 1) and n0 is
+// returned wrapped into [0, M).  Coordinates a few cells outside keep their
+// unwrapped value (only the integer start is wrapped, exactly); beyond 2^22
+// grid units the whole multiple of M is removed from p first.
+PSWF_HD inline void window_start_dw(float p, float lo, int M, int P, int *n0, float *delta) {
   const float Mf = float(M);
-  float p = x * sh;
-  const float lo = std::fma(x, sh, -p) + x * sl;
   if (std::fabs(p) >= 4194304.0f) p = std::fma(-std::floor(p / Mf), Mf, p);
   // s = u - P/2 = shi + slo by an error-free two-sum
   const float half = 0.5f * float(P);
@@ -76,6 +70,37 @@ PSWF_HD inline void window_start(float x, float sh, float sl, int M, int P, int 
   *n0 = n;
 }
 
+// Grid coordinate of one axis, u = sum_b T_b r_b (T: one row of
+// diag(M) H^-T, H the cell with lattice vectors as rows, so that u / M is the
+// fractional coordinate), as an unevaluated FP32 sum hi + lo.  Each T_b is
+// carried as two floats th + tl, each product's rounding error is recovered
+// by an FMA and the three products are added by error-free two-sums, so u is
+// good to ~1e-14 of the largest term (a plain FP32 product would lose ~3e-5
+// grid units at M = 256).  Zero entries (an orthorhombic cell) add exact
+// zeros.
+PSWF_HD inline void grid_coord(const float r[3], const float *th, const float *tl, float *hi, float *lo) {
+  float s = 0.0f, e = 0.0f;
+  for (int b = 0; b < 3; ++b) {
+    const float pr = r[b] * th[b];
+    const float pe = std::fma(r[b], th[b], -pr) + r[b] * tl[b];
+    const float t = s + pr;
+    const float bv = t - s;
+    const float err = (s - (t - bv)) + (pr - bv);
+    s = t;
+    e += err + pe;
+  }
+  *hi = s;
+  *lo = e;
+}
+
+// Window start of one component of an orthorhombic position: u = x M / L
+// with M / L = sh + sl (FP32 double word).
+PSWF_HD inline void window_start(float x, float sh, float sl, int M, int P, int *n0, float *delta) {
+  const float p = x * sh;
+  const float lo = std::fma(x, sh, -p) + x * sl;
+  window_start_dw(p, lo, M, P, n0, delta);
+}
+
 // Stockham factorisation of one transform length.
 struct FftAxis {
   int n = 1;
@@ -95,9 +120,11 @@ struct KChan {
   float pad[2];
 };
 
-// One problem geometry.  Positions become grid coordinates in FP32
-// double-word arithmetic: M / L is carried as an unevaluated sum of two
-// floats (a single FP32 product would lose ~3e-5 grid units at M = 256).
+// One problem geometry in a general (triclinic) cell H, lattice vectors as
+// rows (an orthorhombic box is H = diag(L)).  Positions become grid
+// coordinates u = T r, T = diag(M) H^-T, in FP32 double-word arithmetic;
+// wave vectors are k = 2 pi H^-1 m for the integer frequencies m of the
+// grid axes.
 struct Geo {
   int C;                  // channels
   int64_t N;              // atoms
@@ -110,12 +137,12 @@ struct Geo {
   int B[3];               // tile edge per axis
   int nc[3];              // tiles per axis
   int ncell;
-  double L[3];            // box (host side)
-  float sM_hi[3], sM_lo[3];  // M / L = sM_hi + sM_lo (FP32 double word)
-  float kunit[3];         // 2 pi / L
+  double L[3];            // lattice vector lengths |a_a| (host side)
+  float T_hi[9], T_lo[9]; // T[a][b] = M_a (H^-T)[a][b] = T_hi + T_lo (FP32 double word), row-major
+  float gT[9];            // (2 / P) T[a][b]: window-argument derivative -> d/dr_b
+  float kmat[9];          // k_b = sum_a kmat[3 b + a] m_a, kmat = 2 pi H^-1
   float kc2;              // k_c^2
   float kinv;             // r_c / c  (kappa = k * kinv)
-  float dwin[3];          // 2 / (P h): d t / d r for the window derivative
   float invV;
   double V;
   int CG_spread;          // channels per spread pass
@@ -179,9 +206,11 @@ struct Work {
 
 // Real-space complement of the split (Eq. realLR): the pair kernel
 // K_p(r) = (1 - G_p(r / r_c)) / r^p for 0 < r < r_c over all periodic
-// images.  Cells of edge >= r_c (or the whole box along an axis shorter
-// than r_c); a cell's neighbours are the offsets -R..R on each axis, each
-// offset one periodic image of the cell it wraps to.
+// images.  Cells are a grid on the fractional coordinates, their widths
+// across each lattice plane >= r_c (or the whole cell along an axis whose
+// width is shorter than r_c); a cell's neighbours are the offsets -R..R on
+// each axis, each offset one periodic image (shift by lattice vectors) of
+// the cell it wraps to.
 constexpr int kRsSeg = 16;   // complement polynomial: segments on rho in [0, 1]
 constexpr int kRsDeg = 11;
 constexpr int kRsCoef = kRsSeg * (kRsDeg + 1);
@@ -191,8 +220,8 @@ struct RsGeo {
   int nc[3];              // cells per axis
   int R[3];               // neighbour offsets per axis
   int ncell;
-  float L[3], Llo[3];     // box edges as FP32 double words
-  float cells_per_len[3]; // nc / L
+  float A_hi[9], A_lo[9]; // lattice vectors (rows of H) as FP32 double words
+  float Binv[9];          // rows of H^-T: fractional coordinate s_a = Binv[a] . r
   float rc, rc2, inv_rc;
   int srec;               // floats per atom record: position + pad, then C charges (multiple of 4)
 };

@@ -383,16 +383,22 @@ __device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const floa
   float dl[3];
   int cell[3];
   bool bad = false;
+  float rp[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float x = pos[3 * i + a];
-    if (!isfinite(x)) {  // reported through the status word; placed at 0
+    rp[a] = pos[3 * i + a];
+    if (!isfinite(rp[a])) {  // reported through the status word; placed at 0
       bad = true;
-      x = 0.0f;
+      rp[a] = 0.0f;
     }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float uh, ul;
+    grid_coord(rp, g.T_hi + 3 * a, g.T_lo + 3 * a, &uh, &ul);
     int n0;
     float delta;
-    window_start(x, g.sM_hi[a], g.sM_lo[a], g.M[a], g.P, &n0, &delta);
+    window_start_dw(uh, ul, g.M[a], g.P, &n0, &delta);
     dl[a] = delta;
     packed |= unsigned(n0) << (10 * a);
     cell[a] = n0 / g.B[a];
@@ -714,10 +720,10 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
       if (x >= Ma) x -= Ma;
       if (x < Ba) {
         const float tt = (2.0f * (l + r)) / P - 1.0f;
-        // the derivative factor d psi / dt * 2 / (P h) on the chosen axis
-        // (dipole grids of the second derivatives), psi elsewhere
+        // the derivative factor d psi / dt * 2 / P (per grid unit) on the
+        // chosen axis (dipole grids of the second derivatives), psi elsewhere
         dst[(a == 2 && !MF) ? (x & 3) * NBZ + (x >> 2) : x] =
-            a == src.dax ? win_eval_d(wcf, tt).y * g.dwin[a] : win_eval(wcf, tt);
+            a == src.dax ? win_eval_d(wcf, tt).y * (2.0f / P) : win_eval(wcf, tt);
         bits |= 1u << (x >> 2);
       }
     }
@@ -1371,10 +1377,12 @@ __device__ __forceinline__ void xmul_reg(const Geo &g, const Tables &t, const Wo
   rfft_outer<16, 16, -1>(v);
 
   const int fy = iy <= g.FY ? iy : iy - g.NY;
-  const float ky = fy * g.kunit[1];
   const float dy = t.Dy[iy];
   const int kz = kz0 + col;
-  const float kzv = kz * g.kunit[2];
+  // k = 2 pi H^-1 m: the column's (m_y, m_z) part, then m_x per mode
+  const float cyx = fmaf(g.kmat[1], float(fy), g.kmat[2] * kz);
+  const float cyy = fmaf(g.kmat[4], float(fy), g.kmat[5] * kz);
+  const float cyz = fmaf(g.kmat[7], float(fy), g.kmat[8] * kz);
   const float dyz = on ? dy * t.Dz[kz] : 0.0f;
   const float wz = (kz == 0) ? 1.0f : 2.0f;
   const float scale = (mode == 2 ? float(grad[c]) : 1.0f) * g.invV;
@@ -1383,7 +1391,9 @@ __device__ __forceinline__ void xmul_reg(const Geo &g, const Tables &t, const Wo
   for (int k2 = 0; k2 < 16; ++k2) {
     const int mx = j + 16 * k2;
     const int fx = mx <= 128 ? mx : mx - 256;
-    const float kx = fx * g.kunit[0];
+    const float kx = fmaf(g.kmat[0], float(fx), cyx);
+    const float ky = fmaf(g.kmat[3], float(fx), cyy);
+    const float kzv = fmaf(g.kmat[6], float(fx), cyz);
     const float k2v = kx * kx + ky * ky + kzv * kzv;
     float mult = 0.0f;
     if (on && k2v > 0.0f && k2v <= g.kc2 && mx != 128) {
@@ -1484,9 +1494,11 @@ __device__ __forceinline__ void xmul_body(const Geo &g, const Tables &t, const F
     if (col < ncol) {
       const int iy = ciy[col], kz = ckz[col];
       const int fy = iy <= g.FY ? iy : iy - g.NY;
-      const float ky = fy * g.kunit[1];
       const int fx = mx <= Mx / 2 ? mx : mx - Mx;
-      const float kx = fx * g.kunit[0], kzv = kz * g.kunit[2];
+      // k = 2 pi H^-1 m
+      const float kx = fmaf(g.kmat[0], float(fx), fmaf(g.kmat[1], float(fy), g.kmat[2] * kz));
+      const float ky = fmaf(g.kmat[3], float(fx), fmaf(g.kmat[4], float(fy), g.kmat[5] * kz));
+      const float kzv = fmaf(g.kmat[6], float(fx), fmaf(g.kmat[7], float(fy), g.kmat[8] * kz));
       const float k2 = kx * kx + ky * ky + kzv * kzv;
       if (k2 > 0.0f && k2 <= g.kc2 && 2 * abs(fx) != Mx) {
         const float k = sqrtf(k2);
@@ -1883,15 +1895,15 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
     for (int i = 0; i < P; ++i) {
       const int src = i % kGatherLanes, j = i / kGatherLanes;
       wx[i] = __shfl(vx[j].x, src, kGatherLanes);
-      dwx[i] = __shfl(vx[j].y, src, kGatherLanes) * g.dwin[0];
+      dwx[i] = __shfl(vx[j].y, src, kGatherLanes);
       wz[i] = __shfl(vz[j].x, src, kGatherLanes);
-      dwz[i] = __shfl(vz[j].y, src, kGatherLanes) * g.dwin[2];
+      dwz[i] = __shfl(vz[j].y, src, kGatherLanes);
     }
     float wy[R], dwy[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       wy[j] = vy[j].x;
-      dwy[j] = vy[j].y * g.dwin[1];
+      dwy[j] = vy[j].y;
     }
     const int base = o[0] * plane + o[1] * SZ + o[2];
     float f0 = 0.f, f1 = 0.f, f2 = 0.f;
@@ -1966,10 +1978,11 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
       f2 += __shfl_xor(f2, off, kGatherLanes);
     }
     if (act && l == 0 && fout) {
+      // window-argument derivatives on the grid axes -> d/dr: F_b = sum_a gT[a][b] f_a
       const int64_t oo = 3 * int64_t(dst_atom);
-      fout[oo] = sg * f0;
-      fout[oo + 1] = sg * f1;
-      fout[oo + 2] = sg * f2;
+      fout[oo] = sg * fmaf(g.gT[0], f0, fmaf(g.gT[3], f1, g.gT[6] * f2));
+      fout[oo + 1] = sg * fmaf(g.gT[1], f0, fmaf(g.gT[4], f1, g.gT[7] * f2));
+      fout[oo + 2] = sg * fmaf(g.gT[2], f0, fmaf(g.gT[5], f1, g.gT[8] * f2));
     }
   }
 }
@@ -2094,8 +2107,11 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_dd_prep(Geo g, Work w, const f
   const int64_t k = e % g.N;
   const int i = w.perm_a[k];
   const float qv = w.q_a[e];
+  const float vx = v[3 * int64_t(i)], vy = v[3 * int64_t(i) + 1], vz = v[3 * int64_t(i) + 2];
+  // v . grad_r = (T v) . grad_u: the dipole in grid units
 #pragma unroll
-  for (int a = 0; a < 3; ++a) qd[a * cn + e] = -qv * v[3 * int64_t(i) + a];
+  for (int a = 0; a < 3; ++a)
+    qd[a * cn + e] = -qv * fmaf(g.T_hi[3 * a], vx, fmaf(g.T_hi[3 * a + 1], vy, g.T_hi[3 * a + 2] * vz));
 }
 
 // one thread per atom: grad phi and the Hessian of phi at the atom from the
@@ -2121,15 +2137,24 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_gather_hess(Geo g, Tables t, W
     for (int l = 0; l < P; ++l) {
       const float3 f = win_eval_dd(wcf, (2.0f * (l + dl[a])) / P - 1.0f);
       W[a][l] = f.x;
-      D[a][l] = f.y * g.dwin[a];
-      DD[a][l] = f.z * g.dwin[a] * g.dwin[a];
+      D[a][l] = f.y * (2.0f / P);
+      DD[a][l] = f.z * (4.0f / (P * P));
       int m = n0 + l;
       if (m >= g.M[a]) m -= g.M[a];
       n[a][l] = m;
     }
   }
   const int i = w.perm_a[k];
-  const float vx = v[3 * int64_t(i)], vy = v[3 * int64_t(i) + 1], vz = v[3 * int64_t(i) + 2];
+  // derivatives are taken in grid units u = T r: grad_r = T^T grad_u,
+  // Hess_r = T^T Hess_u T, so v . grad_r phi = (T v) . grad_u phi and
+  // Hess_r v = T^T (Hess_u (T v))
+  float vx, vy, vz;
+  {
+    const float v0 = v[3 * int64_t(i)], v1 = v[3 * int64_t(i) + 1], v2 = v[3 * int64_t(i) + 2];
+    vx = fmaf(g.T_hi[0], v0, fmaf(g.T_hi[1], v1, g.T_hi[2] * v2));
+    vy = fmaf(g.T_hi[3], v0, fmaf(g.T_hi[4], v1, g.T_hi[5] * v2));
+    vz = fmaf(g.T_hi[6], v0, fmaf(g.T_hi[7], v1, g.T_hi[8] * v2));
+  }
   const int64_t chan = int64_t(g.M[0]) * g.M[1] * g.M[2];
   float h0 = 0.f, h1 = 0.f, h2 = 0.f;
   for (int c = 0; c < g.C; ++c) {
@@ -2165,9 +2190,9 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_gather_hess(Geo g, Tables t, W
     h1 -= qc * (hxy * vx + hyy * vy + hyz * vz);
     h2 -= qc * (hxz * vx + hyz * vy + hzz * vz);
   }
-  hv[3 * int64_t(i)] = h0;
-  hv[3 * int64_t(i) + 1] = h1;
-  hv[3 * int64_t(i) + 2] = h2;
+  hv[3 * int64_t(i)] = fmaf(g.T_hi[0], h0, fmaf(g.T_hi[3], h1, g.T_hi[6] * h2));
+  hv[3 * int64_t(i) + 1] = fmaf(g.T_hi[1], h0, fmaf(g.T_hi[4], h1, g.T_hi[7] * h2));
+  hv[3 * int64_t(i) + 2] = fmaf(g.T_hi[2], h0, fmaf(g.T_hi[5], h1, g.T_hi[8] * h2));
 }
 
 // dL/dq = -(s1 + s2), dL/dr = hv + F2 (caller order)
@@ -2177,6 +2202,18 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_dd_combine(int64_t cn, int64_t
   const int64_t e = int64_t(blockIdx.x) * PSWF_THREADS + threadIdx.x;
   if (e < cn) gq[e] = -(gq[e] + s2[e]);
   if (e < n3) gp[e] += f2[e];
+}
+
+// dE/dH_ab = -sum_k (H^-1)_ka W_kb at fixed fractional coordinates: with
+// H -> H (1 + e)^T, dE = sum (dE/dH)_ab H_ak e_bk must equal -sum W_bk e_bk
+__global__ void k_cell_gradient(CellInv hinv, const double *__restrict__ virial, double *__restrict__ grad) {
+  const int e = threadIdx.x;
+  if (e >= 9) return;
+  const int a = e / 3, b = e % 3;
+  const int vi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+  double s = 0.0;
+  for (int k = 0; k < 3; ++k) s += hinv.m[3 * k + a] * virial[vi[k][b]];
+  grad[e] = -s;
 }
 
 // ---------------------------------------------------------------------------
@@ -2407,6 +2444,11 @@ hipError_t launch_gather(const Geo &g, const Tables &t, const Work &w, float *fo
     case 8: return gather_p<8>(g, t, w, forces, pot, mode, grad, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_cell_gradient(const CellInv &hinv, const double *virial, double *grad, hipStream_t st) {
+  hipLaunchKernelGGL(k_cell_gradient, dim3(1), dim3(64), 0, st, hinv, virial, grad);
+  return hipGetLastError();
 }
 
 hipError_t launch_check_inputs(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st) {

@@ -55,6 +55,13 @@ hipError_t launch_check_inputs(const Geo &g, const Work &w, const float *pos, co
 hipError_t launch_finalize(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial,
                            hipStream_t st);
 
+// dE/dH = -(H^-T W) from a device virial [6] (xx, yy, zz, xy, xz, yz);
+// hinv is H^-1 row-major (host values, passed by value)
+struct CellInv {
+  double m[9];
+};
+hipError_t launch_cell_gradient(const CellInv &hinv, const double *virial, double *grad, hipStream_t st);
+
 // real-space complement: binning, ordering, pair sums and the FP64 reduction
 // (realspace.hip); grp/gch describe channel groups sharing one exponent
 hipError_t launch_realspace(const RsGeo &g, const RsTables &t, const RsWork &w, const int *grp, const int *gch,

@@ -153,6 +153,7 @@ struct pswflr_plan_s {
   Geo geo{};
   FftAxis az, ay, ax;
   Tables tab{};
+  double hinv[9] = {0};   // H^-1 row-major (cell gradient)
   void *dtab = nullptr;
   size_t dtab_bytes = 0;  // capacity of the block dtab points to
   hipEvent_t last_use = nullptr;  // the stream event recorded after its last call (not owned)
@@ -185,8 +186,51 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
     return fail(PSWFLR_ERR_INVALID_ARG, "n_channels must be in 1..64");
   for (int c = 0; c < p.n_channels; ++c)
     if (p.p[c] < 1 || p.p[c] > 6) return fail(PSWFLR_ERR_INVALID_ARG, "exponent p must be in 1..6");
+  // the cell H, lattice vectors as rows (the cell tensor); an all-zero
+  // cell means the orthorhombic box diag(box)
+  double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  bool general = false;
+  for (int i = 0; i < 9; ++i) general = general || p.cell[i] != 0.0;
+  if (general && p.cell[1] == 0.0 && p.cell[2] == 0.0 && p.cell[3] == 0.0 && p.cell[5] == 0.0 &&
+      p.cell[6] == 0.0 && p.cell[7] == 0.0 && p.cell[0] > 0.0 && p.cell[4] > 0.0 && p.cell[8] > 0.0) {
+    // a diagonal cell is the orthorhombic box (same plan, same bits)
+    general = false;
+    p.box[0] = p.cell[0];
+    p.box[1] = p.cell[4];
+    p.box[2] = p.cell[8];
+  }
+  if (general) {
+    for (int i = 0; i < 9; ++i) {
+      if (!std::isfinite(p.cell[i])) return fail(PSWFLR_ERR_INVALID_ARG, "cell entries must be finite");
+      H[i / 3][i % 3] = p.cell[i];
+    }
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      if (!(p.box[a] > 0.0) || !std::isfinite(p.box[a])) return fail(PSWFLR_ERR_INVALID_ARG, "box edges must be > 0");
+      H[a][a] = p.box[a];
+    }
+  }
+  const double det = H[0][0] * (H[1][1] * H[2][2] - H[1][2] * H[2][1]) -
+                     H[0][1] * (H[1][0] * H[2][2] - H[1][2] * H[2][0]) +
+                     H[0][2] * (H[1][0] * H[2][1] - H[1][1] * H[2][0]);
+  double len[3], wid[3], Hinv[3][3];
+  for (int a = 0; a < 3; ++a) {
+    len[a] = std::sqrt(H[a][0] * H[a][0] + H[a][1] * H[a][1] + H[a][2] * H[a][2]);
+    // width of the cell across the plane of the other two lattice vectors
+    const int b = (a + 1) % 3, c2 = (a + 2) % 3;
+    const double cx = H[b][1] * H[c2][2] - H[b][2] * H[c2][1], cy = H[b][2] * H[c2][0] - H[b][0] * H[c2][2],
+                 cz = H[b][0] * H[c2][1] - H[b][1] * H[c2][0];
+    wid[a] = std::fabs(det) / std::sqrt(cx * cx + cy * cy + cz * cz);
+    // column a of H^-1 is the cross product of rows b and c over det
+    Hinv[0][a] = cx / det;
+    Hinv[1][a] = cy / det;
+    Hinv[2][a] = cz / det;
+  }
+  if (!(std::fabs(det) > 0.0) || !std::isfinite(det))
+    return fail(PSWFLR_ERR_INVALID_ARG, "the cell must have non-zero volume");
+  // widths far below the lengths: a degenerate cell (reduce the lattice basis first)
   for (int a = 0; a < 3; ++a)
-    if (!(p.box[a] > 0.0) || !std::isfinite(p.box[a])) return fail(PSWFLR_ERR_INVALID_ARG, "box edges must be > 0");
+    if (!(wid[a] > 1e-3 * len[a])) return fail(PSWFLR_ERR_INVALID_ARG, "cell too skewed: reduce its lattice basis");
   if (!(p.r_c > 0.0) || !std::isfinite(p.r_c)) return fail(PSWFLR_ERR_INVALID_ARG, "r_c must be > 0");
   if (max_atoms < 0 || max_atoms > (int64_t(1) << 31) - 1)
     return fail(PSWFLR_ERR_INVALID_ARG, "max_atoms must be in [0, 2^31)");
@@ -207,7 +251,7 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
     } else {
       // h <= eta pi / k_c with eta = 0.6, rounded up to a 2,3,5-smooth size
       const double hmax = 0.6 * kPi / kc;
-      M[a] = smooth_size(p.box[a] / hmax, a == 2);
+      M[a] = smooth_size(len[a] / hmax, a == 2);
     }
     if (M[a] > PSWFLR_MAX_GRID) return fail(PSWFLR_ERR_UNSUPPORTED, "grid edge exceeds 1024");
     if (!is_smooth235(M[a])) return fail(PSWFLR_ERR_UNSUPPORTED, "grid edges must factor into 2, 3 and 5");
@@ -218,7 +262,8 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
     return fail(PSWFLR_ERR_UNSUPPORTED, "a channel's grid must hold fewer than 2^30 points");
   double eta = 0.0, h[3];
   for (int a = 0; a < 3; ++a) {
-    h[a] = p.box[a] / M[a];
+    // the ball's largest frequency along grid axis a is k_c |a_a| / 2 pi
+    h[a] = len[a] / M[a];
     eta = std::max(eta, kc * h[a] / kPi);
   }
   if (!(eta < 1.0))
@@ -248,23 +293,27 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   g.N = 0;
   for (int a = 0; a < 3; ++a) {
     g.M[a] = M[a];
-    g.L[a] = p.box[a];
-    const double sM = double(M[a]) / p.box[a];
-    g.sM_hi[a] = float(sM);
-    g.sM_lo[a] = float(sM - double(g.sM_hi[a]));
-    g.kunit[a] = float(2.0 * kPi / p.box[a]);
-    g.dwin[a] = float(2.0 / (P * h[a]));
+    g.L[a] = len[a];
+    for (int b = 0; b < 3; ++b) {
+      // T = diag(M) H^-T: u_a = sum_b T[a][b] r_b
+      const double T = general ? double(M[a]) * Hinv[b][a] : (a == b ? double(M[a]) / p.box[a] : 0.0);
+      g.T_hi[3 * a + b] = float(T);
+      g.T_lo[3 * a + b] = float(T - double(g.T_hi[3 * a + b]));
+      g.gT[3 * a + b] = float(2.0 / P * T);
+      // k = 2 pi H^-1 m: kmat[b][a]
+      g.kmat[3 * b + a] = float(2.0 * kPi * (general ? Hinv[b][a] : (a == b ? 1.0 / p.box[a] : 0.0)));
+    }
   }
   g.Nz = M[2] / 2;
   g.P = P;
-  g.V = p.box[0] * p.box[1] * p.box[2];
+  g.V = std::fabs(det);
   g.invV = float(1.0 / g.V);
   g.kc2 = float(kc * kc);
   g.kinv = float(p.r_c / c);
   // pruned spectrum extents (ball |k| <= k_c strictly inside Nyquist)
-  const int kzmax = int(std::floor(kc * p.box[2] / (2 * kPi)));
+  const int kzmax = int(std::floor(kc * len[2] / (2 * kPi)));
   g.KZ = std::min(kzmax + 1, g.Nz);
-  g.FY = std::min(int(std::floor(kc * p.box[1] / (2 * kPi))), (M[1] - 1) / 2);
+  g.FY = std::min(int(std::floor(kc * len[1] / (2 * kPi))), (M[1] - 1) / 2);
   g.NY = 2 * g.FY + 1;
 
   // tiles (binning cells): over all divisor triples, maximise the fraction
@@ -384,12 +433,27 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   const int xstep = xreg ? g.kb : g.kbx;
   std::vector<int> xblk, xgrp, blim(g.NY, 0);
   int fill = g.kbx;  // columns used in the open block
+  // |k|^2 = m^T G m with G = (2 pi)^2 H^-T H^-1; minimised over m_x it is
+  // the quadratic form S (Schur complement) in (m_y, m_z)
+  double G[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      double v = 0.0;
+      for (int e = 0; e < 3; ++e)
+        v += (general ? Hinv[e][a] : (e == a ? 1.0 / p.box[a] : 0.0)) *
+             (general ? Hinv[e][b] : (e == b ? 1.0 / p.box[b] : 0.0));
+      G[a][b] = 4.0 * kPi * kPi * v;
+    }
+  const double Syy = G[1][1] - G[1][0] * G[0][1] / G[0][0], Syz = G[1][2] - G[1][0] * G[0][2] / G[0][0],
+               Szz = G[2][2] - G[2][0] * G[0][2] / G[0][0];
   for (int iy = 0; iy < g.NY; ++iy) {
     const int fy = iy <= g.FY ? iy : iy - g.NY;
-    const double ky = 2 * kPi * fy / p.box[1];
-    const double r2 = kc * kc - ky * ky;
-    if (r2 < 0) continue;
-    const int kzl = std::min(g.KZ - 1, int(std::floor(std::sqrt(r2) * p.box[2] / (2 * kPi))));
+    // k_z columns 0 .. the largest m_z with some m_x inside the ball
+    const double disc = Syz * Syz * fy * fy - Szz * (Syy * fy * fy - kc * kc);
+    if (disc < 0) continue;
+    const double zhi = (-Syz * fy + std::sqrt(disc)) / Szz;
+    if (zhi < 0) continue;
+    const int kzl = std::min(g.KZ - 1, int(std::floor(zhi)));
     for (int kz0 = 0; kz0 <= kzl; kz0 += xstep) {
       const int ncol = std::min(xstep, g.KZ - kz0);
       if (xreg || fill + ncol > g.kbx) {
@@ -532,18 +596,21 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
     double edge_min = p.r_c;
     for (;;) {
       int64_t tot = 1;
-      for (int a = 0; a < 3; ++a) tot *= std::max(1, int(std::floor(p.box[a] / edge_min)));
+      for (int a = 0; a < 3; ++a) tot *= std::max(1, int(std::floor(wid[a] / edge_min)));
       if (tot <= std::max<int64_t>(64, max_atoms)) break;
       edge_min *= 1.25;
     }
     rg.ncell = 1;
     for (int a = 0; a < 3; ++a) {
-      rg.nc[a] = std::max(1, int(std::floor(p.box[a] / edge_min)));
-      const double edge = p.box[a] / rg.nc[a];
+      // a vector of length r has fractional component <= r / wid[a] along a
+      rg.nc[a] = std::max(1, int(std::floor(wid[a] / edge_min)));
+      const double edge = wid[a] / rg.nc[a];
       rg.R[a] = std::max(1, int(std::ceil(p.r_c / edge - 1e-12)));
-      rg.L[a] = float(p.box[a]);
-      rg.Llo[a] = float(p.box[a] - double(rg.L[a]));
-      rg.cells_per_len[a] = float(rg.nc[a] / p.box[a]);
+      for (int b = 0; b < 3; ++b) {
+        rg.A_hi[3 * a + b] = float(H[a][b]);
+        rg.A_lo[3 * a + b] = float(H[a][b] - double(rg.A_hi[3 * a + b]));
+        rg.Binv[3 * a + b] = float(general ? Hinv[b][a] : (a == b ? 1.0 / p.box[a] : 0.0));
+      }
       rg.ncell *= rg.nc[a];
     }
     rg.rc = float(p.r_c);
@@ -598,6 +665,10 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   inf.c = c; inf.r_c = p.r_c; inf.k_c = kc; inf.c_spread = cs; inf.eta = eta;
   for (int a = 0; a < 3; ++a) { inf.h[a] = h[a]; inf.grid[a] = M[a]; inf.tile[a] = g.B[a]; }
   inf.volume = g.V;
+  for (int i = 0; i < 9; ++i) {
+    inf.cell[i] = H[i / 3][i % 3];
+    pl.hinv[i] = general ? Hinv[i / 3][i % 3] : (i % 4 == 0 ? 1.0 / p.box[i / 3] : 0.0);
+  }
   inf.support = P;
   inf.n_channels = C;
   inf.kz_keep = g.KZ;
@@ -863,6 +934,18 @@ pswflr_status pswflr_realspace(pswflr_plan plan, pswflr_stream stream, void *wor
   rw.part = reinterpret_cast<double *>(b + plan->off_rs_part);
   hipError_t e = launch_realspace(rg, plan->rst, rw, plan->rs_grp, plan->rs_gch, plan->rs_ngrp, plan->rs_cgmax, pos,
                                   q, energy, forces, virial, potential, st);
+  if (e == hipSuccess) e = mark_use(st, &plan, 1);
+  if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return PSWFLR_OK;
+}
+
+pswflr_status pswflr_cell_gradient(pswflr_plan plan, pswflr_stream stream, const double *virial,
+                                   double *grad_cell) {
+  if (!plan || !virial || !grad_cell) return fail(PSWFLR_ERR_INVALID_ARG, "plan, virial and grad_cell are required");
+  CellInv hi{};
+  for (int i = 0; i < 9; ++i) hi.m[i] = plan->hinv[i];
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_cell_gradient(hi, virial, grad_cell, st);
   if (e == hipSuccess) e = mark_use(st, &plan, 1);
   if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return PSWFLR_OK;

@@ -1,7 +1,7 @@
 // Real-space complement of the PSWF split on gfx950 (Eq. realLR with the
 // mollifier of Eqs. G1, G6, G; Methods, "Implementation details"):
 //
-//   E_real^(c) = 1/2 sum_n sum'_{i,j} q_i q_j K_p(|r_j - r_i + n L|),
+//   E_real^(c) = 1/2 sum_n sum'_{i,j} q_i q_j K_p(|r_j - r_i + n H|),
 //   K_p(r) = (1 - G_p(r / r_c)) / r^p  for 0 < r < r_c, 0 beyond,
 //
 // with potentials dE/dq_i, forces -dE/dr_i and the virial -dE/d(strain).
@@ -9,11 +9,14 @@
 // (16 segments of degree 11, fitted on the host in FP64), its derivative
 // taken from the same polynomial.
 //
-// Atoms are binned into cells of edge >= r_c (the whole box along an axis
-// shorter than r_c) by a counting sort with a deterministic order inside each
-// cell (ascending caller index).  One wave per cell: lane l takes home atom
-// l / 4 of a group of 16 and every fourth atom of each neighbour cell
-// (offsets -R..R per axis, each one periodic image of the cell it wraps to),
+// The cell may be triclinic (lattice vectors as the rows of H).  Atoms are
+// binned on their fractional coordinates into cells whose widths across the
+// lattice planes are >= r_c (the whole cell along an axis narrower than r_c)
+// by a counting sort with a deterministic order inside each cell (ascending
+// caller index).  One wave per cell: lane l takes home atom l / 4 of a group
+// of 16 and every fourth atom of each neighbour cell (offsets -R..R per
+// axis, each one periodic image of the cell it wraps to, shifted by lattice
+// vectors),
 // so the four lanes of an atom read the same neighbour record as the lanes
 // of the other atoms (broadcast loads).  Every lane accumulates only its own
 // atom: no atomics, a fixed summation order, bitwise reproducible results.
@@ -40,25 +43,36 @@ __global__ __launch_bounds__(256) void k_rs_zero(RsWork w, int ncell) {
   if (i < ncell) w.count[i] = 0;
 }
 
-// wrapped position (FP32 double-word box edge) and cell per atom; the
-// record [x, y, z, 0, q_0 .. q_{C-1}] in caller order
+// wrapped position and cell per atom; the record [x, y, z, 0, q_0 .. q_{C-1}]
+// in caller order.  The fractional coordinates s = H^-T r pick the cell and
+// the whole cells k = floor(s) to remove: r - k H with the lattice vectors
+// as FP32 double words.
 __global__ __launch_bounds__(256) void k_rs_bin(RsGeo g, RsWork w, const float *__restrict__ pos,
                                                 const float *__restrict__ q) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= g.N) return;
-  float xw[3];
+  float r[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r[a] = pos[3 * i + a];
+    if (!isfinite(r[a])) r[a] = 0.0f;
+  }
+  float kf[3];
   int cc[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float x = pos[3 * i + a];
-    if (!isfinite(x)) x = 0.0f;
-    const float k = floorf(x / g.L[a]);
-    float v = fmaf(-k, g.Llo[a], fmaf(-k, g.L[a], x));
-    if (v < 0.0f) v += g.L[a];
-    if (v >= g.L[a]) v -= g.L[a];
-    if (!(v >= 0.0f && v < g.L[a])) v = 0.0f;
-    xw[a] = v;
-    cc[a] = min(int(v * g.cells_per_len[a]), g.nc[a] - 1);
+    const float sa = fmaf(g.Binv[3 * a], r[0], fmaf(g.Binv[3 * a + 1], r[1], g.Binv[3 * a + 2] * r[2]));
+    kf[a] = floorf(sa);
+    float f = sa - kf[a];
+    if (!(f >= 0.0f)) f = 0.0f;
+    cc[a] = min(int(f * g.nc[a]), g.nc[a] - 1);
+  }
+  float xw[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    float v = fmaf(-kf[2], g.A_hi[6 + b], fmaf(-kf[1], g.A_hi[3 + b], fmaf(-kf[0], g.A_hi[b], r[b])));
+    v = fmaf(-kf[2], g.A_lo[6 + b], fmaf(-kf[1], g.A_lo[3 + b], fmaf(-kf[0], g.A_lo[b], v)));
+    xw[b] = v;
   }
   float *rec = w.rec_b + i * g.srec;
   *reinterpret_cast<float4 *>(rec) = make_float4(xw[0], xw[1], xw[2], 0.0f);
@@ -167,14 +181,22 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pairs(RsGeo g, RsTables t, Rs
             while (az >= g.nc[2]) { az -= g.nc[2]; ++kz; }
             const int nb = (ax * g.nc[1] + ay) * g.nc[2] + az;
             const int js = w.start[nb], je = w.start[nb + 1];
-            const float fx = float(kx), fy = float(ky), fz = float(kz);
+            // the image shift k H (lattice vectors as double words): hi
+            // part added to r_j, then r_i subtracted, then the lo part
+            const float kv[3] = {float(kx), float(ky), float(kz)};
+            float shi[3], slo[3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              const float th[3] = {g.A_hi[b], g.A_hi[3 + b], g.A_hi[6 + b]};
+              const float tl[3] = {g.A_lo[b], g.A_lo[3 + b], g.A_lo[6 + b]};
+              grid_coord(kv, th, tl, &shi[b], &slo[b]);
+            }
             for (int j = js + part; j < je; j += 4) {
               const float *rj = w.rec_a + int64_t(j) * g.srec;
               const float4 xj = *reinterpret_cast<const float4 *>(rj);
-              // d = r_j + (k L) - r_i with the box as a double word
-              const float dxv = fmaf(fx, g.Llo[0], fmaf(fx, g.L[0], xj.x) - xi.x);
-              const float dyv = fmaf(fy, g.Llo[1], fmaf(fy, g.L[1], xj.y) - xi.y);
-              const float dzv = fmaf(fz, g.Llo[2], fmaf(fz, g.L[2], xj.z) - xi.z);
+              const float dxv = ((xj.x + shi[0]) - xi.x) + slo[0];
+              const float dyv = ((xj.y + shi[1]) - xi.y) + slo[1];
+              const float dzv = ((xj.z + shi[2]) - xi.z) + slo[2];
               const float r2 = fmaf(dxv, dxv, fmaf(dyv, dyv, dzv * dzv));
               if (!(r2 < g.rc2) || !(r2 > 0.0f)) continue;
               const float rinv = rsqrtf(r2);

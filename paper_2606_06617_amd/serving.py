@@ -238,7 +238,8 @@ class Server:
         self.used = 0
         self.done = []
         self.peak_used = 0
-        self.max_concurrency = 0
+        self.max_concurrency = 0                   # launches in flight at once
+        self.max_inflight_requests = 0             # requests in flight at once
         self.max_coalesced = 0
         self.launches = 0
         self.t0 = None
@@ -321,6 +322,8 @@ class Server:
             self.inflight[slot] = (group, token)
             self.launches += 1
             self.max_concurrency = max(self.max_concurrency, len(self.inflight))
+            self.max_inflight_requests = max(self.max_inflight_requests,
+                                             sum(len(g) for g, _ in self.inflight.values()))
             self.max_coalesced = max(self.max_coalesced, len(group))
 
     def poll(self):

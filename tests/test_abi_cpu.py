@@ -65,7 +65,39 @@ def test_argument_errors_before_device(kw, status):
     assert _create(**kw) == status
 
 
-def test_struct_layout_matches_header():
-    # offsets the C side relies on (x86-64 SysV layout of pswflr_params)
-    assert _lib.Params.box.offset == 264      # 4 + 4*64, padded to 8
-    assert ctypes.sizeof(_lib.IO) == 7 * 8
+
+
+SKEWED = ((12.0, 0.0, 0.0), (3.0, 11.0, 0.0), (-2.0, 2.5, 10.0))
+
+
+@pytest.mark.parametrize("cell,status", [
+    (((12.0, 0.0, 0.0), (24.0, 0.0, 0.0), (0.0, 0.0, 10.0)), 1),     # singular
+    (((12.0, 0.0, 0.0), (0.0, float("nan"), 0.0), (0.0, 0.0, 10.0)), 1),
+    (((12.0, 0.0, 0.0), (12.0, 1e-3, 0.0), (0.0, 0.0, 10.0)), 1),    # degenerate: reduce the basis
+])
+def test_cell_errors_before_device(cell, status):
+    assert _create(box=cell, grid=(24, 24, 24)) == status
+
+
+def test_cell_nyquist_uses_lattice_vector_lengths():
+    # |a_1| = 11.4 A on 10 points: k_c h / pi = 2.4048 * 1.14 / pi > 0.87 is
+    # fine; on 8 points it exceeds 1
+    assert _create(box=SKEWED, grid=(24, 8, 24)) == 1
+
+
+def test_struct_layout_matches_header(tmp_path):
+    # offsets and sizes of the parameter and info structs as the C compiler
+    # lays them out, against the ctypes mirrors
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "pswflr.h"\n'
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu\\n", offsetof(pswflr_params, box), '
+        'offsetof(pswflr_params, flags), offsetof(pswflr_params, cell), sizeof(pswflr_params), '
+        'offsetof(pswflr_info, cell), sizeof(pswflr_info), sizeof(pswflr_io)); return 0; }\n')
+    exe = str(tmp_path / "layout")
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", exe], check=True)
+    got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [_lib.Params.box.offset, _lib.Params.flags.offset, _lib.Params.cell.offset,
+                   ctypes.sizeof(_lib.Params), _lib.Info.cell.offset, ctypes.sizeof(_lib.Info),
+                   ctypes.sizeof(_lib.IO)]

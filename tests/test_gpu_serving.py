@@ -18,7 +18,9 @@ pytestmark = pytest.mark.gpu
 def test_mixed_stream_results_equal_alone():
     from paper_2606_06617_amd.api import Plan
     from paper_2606_06617_amd.serving import HipExecutor, Server, latency_stats, make_requests
-    stream = wl.serving_stream(nreq=24, rate=2000.0, seed=11, nmin=100, nmax=6000)
+    # arrivals 50 us apart on average: later requests arrive while earlier
+    # ones are on the device
+    stream = wl.serving_stream(nreq=24, rate=20000.0, seed=11, nmin=100, nmax=6000)
     reqs = make_requests(stream)
     print("serving", len(reqs), "requests, sizes", [r.n_atoms for r in reqs], flush=True)
     ex = HipExecutor(slots=4)
@@ -28,7 +30,11 @@ def test_mixed_stream_results_equal_alone():
     st = latency_stats(out)
     assert st["n"] == len(reqs)
     assert srv.peak_used <= srv.budget
-    assert srv.max_concurrency >= 2
+    # requests overlap on the device: several launches at once, or requests
+    # admitted while others run coalesced into one launch
+    print("max launches in flight", srv.max_concurrency, "max requests in flight", srv.max_inflight_requests,
+          "largest coalesced launch", srv.max_coalesced, flush=True)
+    assert srv.max_inflight_requests >= 2
     for r in out[:8]:
         plan = Plan(r.box, r.ps, r_c=5.0, c=0.0, tol=1e-5, support=8, max_atoms=r.n_atoms)
         ref = plan.execute(torch.from_numpy(r.pos).cuda(), torch.from_numpy(r.q).cuda())

@@ -1,0 +1,195 @@
+"""Triclinic cells on the GPU (the cell tensor of the Fig. 1 caption:
+lattice vectors as the rows of H, grid axes along them, k = 2 pi H^-1 m),
+through the C ABI, against the FP64 general-cell oracle:
+
+* energy per channel, forces, potentials and the whole virial tensor
+  against the plain general-cell Fourier sum (oracle.cellsum) at the
+  method's bars, with explicit and with automatic (tol = 1e-5) plans;
+* a diagonal cell is the orthorhombic box, bit for bit;
+* the same lattice under another basis gives the same energies and forces;
+* the real-space complement against oracle.realspace in a skewed cell, and
+  the rock-salt Madelung energy from the GPU split on the face-centred
+  primitive cell;
+* the cell gradient dE/dH (constant-pressure box derivative) against
+  central differences of the oracle's energy in H at fixed fractional
+  coordinates;
+* the double backward against oracle.cellsum.force_vjp."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cellsum, realspace
+from paper_2606_06617_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+C_MOL, RC = 12.024, 5.0
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rel_rms(a, b):
+    return float(np.sqrt(np.mean((a - b) ** 2)) / np.sqrt(np.mean(b ** 2)))
+
+
+def _w3(v):
+    return np.array([[v[0], v[3], v[4]], [v[3], v[1], v[5]], [v[4], v[5], v[2]]])
+
+
+def _run(plan, w, potential=True):
+    out = plan.execute(torch.from_numpy(w["pos"]).cuda(), torch.from_numpy(w["q"]).cuda(), forces=True,
+                       virial=True, potential=potential)
+    torch.cuda.synchronize()
+    return out
+
+
+def _against_cellsum(w, plan, c, nsample=None):
+    N = w["pos"].shape[0]
+    out = _run(plan, w)
+    e = out["energy"].cpu().numpy()
+    F = out["forces"].cpu().numpy().astype(np.float64)
+    phi = out["potential"].cpu().numpy().astype(np.float64)
+    Wg = _w3(out["virial"].cpu().numpy())
+    sample = None
+    if nsample is not None and N > nsample:
+        sample = np.sort(np.random.default_rng(N).choice(N, nsample, replace=False))
+    r = cellsum.evaluate(w["pos"].astype(np.float64), w["q"].astype(np.float64), w["box"], w["ps"], c, RC,
+                         sample=sample)
+    idx = r["sample"]
+    eg = e[:-1].reshape(-1, 3)
+    Eg, Er = eg[:, 0] + eg[:, 1], r["Ek"] + r["E0"]
+    rel_e = np.abs(Eg - Er) / np.abs(Er)
+    ef = _rel_rms(F[idx], r["F"])
+    ep = _rel_rms(phi[:, idx], r["phi"])
+    ew = np.abs(Wg - r["W"]).max() / np.abs(r["W"]).max()
+    print(w["name"], "grid", plan.info["grid"], "P", plan.info["support"], "rel energy",
+          np.array2string(rel_e, precision=2), "force %.2e potential %.2e virial %.2e" % (ef, ep, ew), flush=True)
+    assert np.all(rel_e <= 1e-5), rel_e
+    assert np.allclose(eg[:, 2], r["Eself"], rtol=1e-9)
+    assert ef <= 1e-4 and ep <= 1e-4 and ew <= 1e-4, (ef, ep, ew)
+    return out
+
+
+@pytest.mark.parametrize("neutral", [True, False])
+def test_triclinic_against_the_general_cell_sum(neutral):
+    from paper_2606_06617_amd.api import Plan
+    w = wl.triclinic_box(3000, ps=(1, 3, 6), seed=51, neutral=neutral)
+    plan = Plan(w["box"], w["ps"], r_c=RC, c=C_MOL, grid=(40, 40, 40), support=8, max_atoms=3000)
+    _against_cellsum(w, plan, C_MOL)
+
+
+def test_triclinic_automatic_plan():
+    from paper_2606_06617_amd.api import Plan
+    tol = 1e-5
+    w = wl.triclinic_box(20000, ps=(1, 6), seed=52)
+    plan = Plan(w["box"], w["ps"], r_c=RC, c=0.0, tol=tol, max_atoms=20000)
+    _against_cellsum(w, plan, math.log(3.0 / tol), nsample=1500)
+
+
+def test_diagonal_cell_is_the_box_bit_for_bit():
+    from paper_2606_06617_amd.api import Plan
+    w = wl.random_box(2000, ps=(1, 6), seed=53, aspect=(1.0, 1.2, 0.9))
+    kw = dict(r_c=RC, c=C_MOL, grid=(32, 36, 30), support=7, max_atoms=2000)
+    a = _run(Plan(w["box"], w["ps"], **kw), w)
+    b = _run(Plan(np.diag(w["box"]), w["ps"], **kw), w)
+    for key in ("energy", "forces", "virial", "potential"):
+        assert torch.equal(a[key], b[key]), key
+
+
+def test_change_of_lattice_basis():
+    from paper_2606_06617_amd.api import Plan
+    w = wl.triclinic_box(2500, ps=(1, 6), seed=54)
+    U = np.array([[1, 0, 0], [1, 1, 0], [0, -1, 1]], dtype=np.float64)   # unimodular
+    H2 = U @ w["box"]
+    p1 = Plan(w["box"], w["ps"], r_c=RC, c=C_MOL, tol=1e-5, support=8, max_atoms=2500)
+    p2 = Plan(H2, w["ps"], r_c=RC, c=C_MOL, tol=1e-5, support=8, max_atoms=2500)
+    a, b = _run(p1, w), _run(p2, w)
+    ea, eb = a["energy"].cpu().numpy(), b["energy"].cpu().numpy()
+    print("grids", p1.info["grid"], p2.info["grid"], "energies", ea[-1], eb[-1], flush=True)
+    assert abs(ea[-1] - eb[-1]) <= 2e-5 * abs(ea[-1])
+    assert _rel_rms(a["forces"].cpu().numpy(), b["forces"].cpu().numpy().astype(np.float64)) <= 1e-4
+
+
+def test_realspace_in_a_skewed_cell():
+    from paper_2606_06617_amd.api import Plan
+    w = wl.triclinic_box(1200, ps=(1, 3, 6), seed=55, neutral=False)
+    plan = Plan(w["box"], w["ps"], r_c=RC, c=C_MOL, grid=(24, 24, 24), support=6, max_atoms=1200)
+    out = plan.realspace(torch.from_numpy(w["pos"]).cuda(), torch.from_numpy(w["q"]).cuda(), forces=True,
+                         virial=True, potential=True)
+    torch.cuda.synchronize()
+    r = realspace.evaluate(w["pos"].astype(np.float64), w["q"].astype(np.float64), w["box"], w["ps"], C_MOL, RC)
+    e = out["energy"].cpu().numpy()
+    rel_e = np.abs(e - r["Ereal"]) / np.abs(r["Ereal"])
+    ef = _rel_rms(out["forces"].cpu().numpy().astype(np.float64), r["F"])
+    ep = _rel_rms(out["potential"].cpu().numpy().astype(np.float64), r["phi"])
+    ew = np.abs(_w3(out["virial"].cpu().numpy()) - r["W"]).max() / np.abs(r["W"]).max()
+    print("real space rel energy", rel_e, "force %.2e potential %.2e virial %.2e" % (ef, ep, ew), flush=True)
+    assert np.all(rel_e <= 1e-5) and ef <= 1e-5 and ep <= 1e-5 and ew <= 1e-5
+
+
+def test_rock_salt_madelung_on_the_primitive_cell():
+    from paper_2606_06617_amd.api import Plan
+    with open(os.path.join(GOLDEN, "madelung_nacl.txt")) as f:
+        madelung = float([ln for ln in f if ln.strip() and not ln.startswith("#")][0])
+    a = 5.64
+    w = wl.nacl_primitive(ncell=4, a=a)
+    ref = -0.5 * w["pos"].shape[0] * madelung / (a / 2)
+    plan = Plan(w["box"], w["ps"], r_c=RC, c=30.0, grid=(48, 48, 48), support=8, max_atoms=w["pos"].shape[0])
+    pos, q = torch.from_numpy(w["pos"]).cuda(), torch.from_numpy(w["q"]).cuda()
+    rec = plan.execute(pos, q, forces=True, virial=False)
+    rs = plan.realspace(pos, q, forces=True, virial=False)
+    torch.cuda.synchronize()
+    e = rec["energy"].cpu().numpy()
+    E = float(rs["energy"].cpu().numpy()[0] + e[-1] - e[2])
+    F = (rec["forces"] + rs["forces"]).cpu().numpy()
+    print("Madelung on the primitive cell: GPU %.10f exact %.10f rel %.2e, max |F| %.2e"
+          % (E, ref, abs(E / ref - 1), np.abs(F).max()), flush=True)
+    assert E == pytest.approx(ref, rel=2e-6)
+    assert np.abs(F).max() <= 1e-4          # a perfect lattice: every force vanishes
+
+
+def test_cell_gradient_against_energy_differences():
+    from paper_2606_06617_amd.api import Plan
+    w = wl.triclinic_box(600, ps=(1, 6), seed=56, neutral=False)
+    H = w["box"]
+    plan = Plan(H, w["ps"], r_c=RC, c=C_MOL, grid=(24, 24, 24), support=8, max_atoms=600)
+    out = _run(plan, w, potential=False)
+    G = plan.cell_gradient(out["virial"]).cpu().numpy()
+    torch.cuda.synchronize()
+    frac = w["pos"].astype(np.float64) @ np.linalg.inv(H)
+    q = w["q"].astype(np.float64)
+
+    def energy(Hx):
+        r = cellsum.evaluate(frac @ Hx, q, Hx, w["ps"], C_MOL, RC, sample=[], virial=False)
+        return float(np.sum(r["Ek"] + r["E0"]))
+    h = 1e-5
+    fd = np.zeros((3, 3))
+    for a in range(3):
+        for b in range(3):
+            Hp, Hm = H.copy(), H.copy()
+            Hp[a, b] += h
+            Hm[a, b] -= h
+            fd[a, b] = (energy(Hp) - energy(Hm)) / (2 * h)
+    err = np.abs(G - fd).max() / np.abs(fd).max()
+    print("cell gradient rel err %.2e" % err, flush=True)
+    assert err <= 1e-4
+
+
+def test_force_vjp_in_a_skewed_cell():
+    from paper_2606_06617_amd.api import Plan
+    w = wl.triclinic_box(1500, ps=(1, 6), seed=57, neutral=False)
+    plan = Plan(w["box"], w["ps"], r_c=RC, c=C_MOL, grid=(32, 32, 32), support=8, max_atoms=1500)
+    pos, q = torch.from_numpy(w["pos"]).cuda(), torch.from_numpy(w["q"]).cuda()
+    v = np.random.default_rng(58).normal(0.0, 1.0, (1500, 3)).astype(np.float32)
+    ws = plan.new_workspace()
+    plan.execute(pos, q, forces=True, virial=False, workspace=ws)
+    gq, gp = plan.force_vjp(ws, pos, q, torch.from_numpy(v).cuda())
+    torch.cuda.synchronize()
+    rq, rp = cellsum.force_vjp(w["pos"].astype(np.float64), w["q"].astype(np.float64), w["box"], w["ps"], C_MOL,
+                               RC, v.astype(np.float64))
+    eq = _rel_rms(gq.cpu().numpy().astype(np.float64), rq)
+    ep = _rel_rms(gp.cpu().numpy().astype(np.float64), rp)
+    print("force vjp dq %.2e dr %.2e" % (eq, ep), flush=True)
+    assert eq <= 1e-4 and ep <= 1e-4
