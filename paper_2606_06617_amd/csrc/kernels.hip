@@ -24,6 +24,34 @@ namespace pswf {
 static_assert(PSWF_THREADS == kSortThreads, "the ordering kernels run with the sort's block size");
 
 // ---------------------------------------------------------------------------
+// Streaming stores: results that the next pass reads once, written with the
+// nontemporal hint so they do not linger in the caches as dirty lines the
+// next pass's reads must wait behind (measured on the 256^3 passes: y, x
+// and inverse y 5-15 % faster, the following z C2R 11 %).
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_stream(float2 *p, float2 v) {
+  const nt_f2 x = {v.x, v.y};
+  __builtin_nontemporal_store(x, reinterpret_cast<nt_f2 *>(p));
+}
+__device__ __forceinline__ void st_stream(float4 *p, float4 v) {
+  const nt_f4 x = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(x, reinterpret_cast<nt_f4 *>(p));
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin by index; give each XCD a
+// contiguous range of b in [0, n), so that neighbouring work runs behind the
+// same L2.
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+  const int q = n >> 3, r = n & 7, xcd = b & 7, j = b >> 3;
+  return xcd * q + min(xcd, r) + j;
+}
+// the same for a 2D grid, returned as (x, y) block coordinates
+__device__ __forceinline__ int2 xcd_contiguous_2d() {
+  const int n = gridDim.x * gridDim.y, m = xcd_contiguous(blockIdx.y * gridDim.x + blockIdx.x, n);
+  return make_int2(m % gridDim.x, m / gridDim.x);
+}
+
 // complex helpers
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -1108,7 +1136,7 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
             const float4 o = *reinterpret_cast<const float4 *>(gch + goff[r]);
             v = make_float4(v.x + o.x, v.y + o.y, v.z + o.z, v.w + o.w);
           }
-          *reinterpret_cast<float4 *>(gch + goff[r]) = v;
+          st_stream(reinterpret_cast<float4 *>(gch + goff[r]), v);
         } else {
           gch[goff[r]] = src.acc ? sch[soffs[r]] + gch[goff[r]] : sch[soffs[r]];
         }
@@ -1168,7 +1196,7 @@ __device__ __forceinline__ void zfwd_reg(const Geo &g, const Tables &t, const Wo
     // E = (Z_k + conj Z_{N-k}) / 2, O = (Z_k - conj Z_{N-k}) / (2i)
     const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
     const float2 O = make_float2(0.5f * (zk.y + zc.y), -0.5f * (zk.x - zc.x));
-    dst[k] = cadd(E, cmul(twr[k], O));
+    st_stream(&dst[k], cadd(E, cmul(twr[k], O)));
   }
 }
 
@@ -1251,8 +1279,8 @@ __device__ __forceinline__ void yfwd_reg(const Geo &g, const Tables &t, const Wo
 #pragma unroll
   for (int k2 = 0; k2 < 16; ++k2) {
     const int k = j + 16 * k2;
-    if (k <= g.FY) dst[int64_t(k) * g.KZP] = v[k2];
-    else if (k >= 256 - g.FY) dst[int64_t(k - 256 + g.NY) * g.KZP] = v[k2];
+    if (k <= g.FY) st_stream(&dst[int64_t(k) * g.KZP], v[k2]);
+    else if (k >= 256 - g.FY) st_stream(&dst[int64_t(k - 256 + g.NY) * g.KZP], v[k2]);
   }
 }
 
@@ -1298,10 +1326,13 @@ __device__ __forceinline__ void yfwd_body(const Geo &g, const Tables &t, const F
 // REG: the register FFT path (the planner's 256-point geometry)
 template <bool REG>
 __global__ __launch_bounds__(PSWF_THREADS) void k_yfwd(Geo g, Tables t, FftAxis ax, Work w) {
-  if (REG)
-    yfwd_reg(g, t, w, blockIdx.x, blockIdx.y);
-  else
+  if (REG) {
+    // consecutive column blocks of a plane on one XCD
+    const int2 m = xcd_contiguous_2d();
+    yfwd_reg(g, t, w, m.x, m.y);
+  } else {
     yfwd_body(g, t, ax, w, blockIdx.x, blockIdx.y);
+  }
 }
 
 // Fourier kernel at kappa: (Phi, Phi'/k) from the per-channel polynomials.
@@ -1437,7 +1468,7 @@ __device__ __forceinline__ void xmul_reg(const Geo &g, const Tables &t, const Wo
   rfft_outer<16, 16, 1>(v);
   if (!on) return;
 #pragma unroll
-  for (int k2 = 0; k2 < 16; ++k2) col0[(j + 16 * k2) * xstride] = v[k2];
+  for (int k2 = 0; k2 < 16; ++k2) st_stream(&col0[(j + 16 * k2) * xstride], v[k2]);
 }
 
 // Fused x pass (steps ii-iv and the first inverse axis): x transform of one
@@ -1592,7 +1623,7 @@ __device__ __forceinline__ void yinv_reg(const Geo &g, const Tables &t, const Wo
   if (!on) return;
   float2 *dst = reinterpret_cast<float2 *>(w.s1) + plane * 256 * g.KZP + kz;
 #pragma unroll
-  for (int k2 = 0; k2 < 16; ++k2) dst[int64_t(j + 16 * k2) * g.KZP] = v[k2];
+  for (int k2 = 0; k2 < 16; ++k2) st_stream(&dst[int64_t(j + 16 * k2) * g.KZP], v[k2]);
 }
 
 // inverse y: kept rows (zero elsewhere and for columns the x pass skipped)
@@ -1643,10 +1674,13 @@ __device__ __forceinline__ void yinv_body(const Geo &g, const Tables &t, const F
 // REG: the register FFT path (the planner's 256-point geometry)
 template <bool REG>
 __global__ __launch_bounds__(PSWF_THREADS) void k_yinv(Geo g, Tables t, FftAxis ax, Work w) {
-  if (REG)
-    yinv_reg(g, t, w, blockIdx.x, blockIdx.y);
-  else
+  if (REG) {
+    // consecutive column blocks of a plane on one XCD
+    const int2 m = xcd_contiguous_2d();
+    yinv_reg(g, t, w, m.x, m.y);
+  } else {
     yinv_body(g, t, ax, w, blockIdx.x, blockIdx.y);
+  }
 }
 
 // z C2R on the register FFT: 32 lines of Nz = 128 per workgroup
@@ -1768,7 +1802,7 @@ __device__ __forceinline__ void zinv_body(const Geo &g, const Tables &t, const F
 template <bool REG>
 __global__ __launch_bounds__(PSWF_THREADS) void k_zinv(Geo g, Tables t, FftAxis ax, Work w, int64_t nlines_total) {
   if (REG)
-    zinv_reg(g, t, w, nlines_total, blockIdx.x);
+    zinv_reg(g, t, w, nlines_total, xcd_contiguous(blockIdx.x, gridDim.x));
   else
     zinv_body(g, t, ax, w, nlines_total, blockIdx.x);
 }
@@ -1987,13 +2021,9 @@ __device__ __forceinline__ void gather_body(const Geo &g, const Tables &t, const
   }
 }
 
-// Workgroups are dealt to the 8 XCDs round-robin by index; give each XCD a
-// contiguous range of tiles so that neighbouring tiles, whose halos overlap,
-// run at the same time behind the same L2.
-__device__ __forceinline__ int xcd_contiguous(int b, int n) {
-  const int q = n >> 3, r = n & 7, xcd = b & 7, j = b >> 3;
-  return xcd * q + min(xcd, r) + j;
-}
+// Gather tiles go to the XCDs in contiguous ranges (xcd_contiguous) so that
+// neighbouring tiles, whose halos overlap, run at the same time behind the
+// same L2.
 
 // Order of tiles within an XCD's range: compact groups of up to 4 x 4 x 4
 // tiles (the largest of 4, 2, 1 dividing the tile count per axis) instead
