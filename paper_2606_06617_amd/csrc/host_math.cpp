@@ -269,6 +269,26 @@ std::shared_ptr<const Prolate> prolate_cached(double c) {
   return p;
 }
 
+std::shared_ptr<const std::vector<float>> deconvolution_cached(double c_s, int P, int M) {
+  static std::mutex mu;
+  static std::map<std::tuple<double, int, int>, std::shared_ptr<const std::vector<float>>> cache;
+  const auto key = std::make_tuple(c_s, P, M);
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  auto ws = prolate_cached(c_s);
+  auto tab = std::make_shared<std::vector<float>>(M / 2 + 1);
+  for (int f = 0; f <= M / 2; ++f) {
+    const double what_over_h = 0.5 * P * ws->window_ft(kPi * P * double(f) / M);
+    (*tab)[f] = float(1.0 / (what_over_h * what_over_h));
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  cache.emplace(key, tab);
+  return tab;
+}
+
 // ---------------------------------------------------------------------------
 double PiecewisePoly::eval(double x) const {
   double y = x * nseg;

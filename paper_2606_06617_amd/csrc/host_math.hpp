@@ -49,6 +49,12 @@ class Prolate {
 // Shared, cached instances (plan creation is cheap after the first call).
 std::shared_ptr<const Prolate> prolate_cached(double c);
 
+// Deconvolution factors of one grid axis, h^2 / What(k)^2 at the grid
+// frequencies k = 2 pi f / (M h), f = 0 .. M / 2: the window transform
+// depends on f / M only (What(k) / h = (P / 2) window_ft(pi P f / M)), so a
+// table serves every box with that (c_s, P, M).  Cached.
+std::shared_ptr<const std::vector<float>> deconvolution_cached(double c_s, int P, int M);
+
 // Device representation of a smooth function on [0, 1]: nseg uniform
 // segments, each a monomial in the local variable tau in [-1, 1] of degree
 // deg (coefficients low to high).  Built by Chebyshev interpolation on each

@@ -470,7 +470,6 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
 
   // ---- tables (host FP64 -> device FP32) ----
   auto wpoly = make_window_poly(cs, kWinSeg, kWinDeg, 1e-9);
-  auto ws = prolate_cached(cs);
   std::vector<ChannelKernel> kers;
   for (int ch = 0; ch < C; ++ch) kers.push_back(make_channel_kernel(p.p[ch], c, p.r_c, 1e-9));
 
@@ -482,18 +481,16 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
     }
     return t;
   };
-  // h^2 / What_a^2 = (2 / (P window_ft(pi P f / M)))^2
-  auto deconv = [&](int Ma, int f) {
-    const double s = kPi * P * double(std::abs(f)) / Ma;
-    const double what_over_h = 0.5 * P * ws->window_ft(s);
-    return float(1.0 / (what_over_h * what_over_h));
-  };
+  // h^2 / What_a^2 = (2 / (P window_ft(pi P f / M)))^2, tabulated per
+  // (c_s, P, M) and shared by every box with those (host cache)
+  const auto dtx = deconvolution_cached(cs, P, M[0]), dty = deconvolution_cached(cs, P, M[1]),
+             dtz = deconvolution_cached(cs, P, M[2]);
   std::vector<float> tw_z = twiddles(g.Nz, g.Nz), tw_zr = twiddles(g.Nz + 1, M[2]), tw_y = twiddles(M[1], M[1]),
                      tw_x = twiddles(M[0], M[0]);
   std::vector<float> Dx(M[0]), Dy(g.NY), Dz(g.KZ);
-  for (int i = 0; i < M[0]; ++i) Dx[i] = deconv(M[0], i <= M[0] / 2 ? i : i - M[0]);
-  for (int i = 0; i < g.NY; ++i) Dy[i] = deconv(M[1], i <= g.FY ? i : i - g.NY);
-  for (int i = 0; i < g.KZ; ++i) Dz[i] = deconv(M[2], i);
+  for (int i = 0; i < M[0]; ++i) Dx[i] = (*dtx)[i <= M[0] / 2 ? i : M[0] - i];
+  for (int i = 0; i < g.NY; ++i) Dy[i] = (*dty)[i <= g.FY ? i : g.NY - i];
+  for (int i = 0; i < g.KZ; ++i) Dz[i] = (*dtz)[i];
   std::vector<float> win(kWinSeg * (kWinDeg + 1));
   for (size_t i = 0; i < win.size(); ++i) win[i] = float(wpoly.coef[i]);
   std::vector<float> kf(size_t(C) * kKerCoef), kg(size_t(C) * kKerCoef);
