@@ -80,7 +80,7 @@ def test_autograd_batch_gradients_against_oracle():
         r = reciprocal.evaluate(st["pos"].astype(np.float64), st["q"].astype(np.float64), st["box"], st["ps"],
                                 12.024, 5.0)
         Er = float((r["Ek"] + r["E0"]).sum())
-        assert abs(float(e[i]) - Er) <= 1e-5 * abs(Er)
+        assert abs(float(e[i].detach()) - Er) <= 1e-5 * abs(Er)
         w = float(weights[i])
         gq = qr.grad[q0:q0 + C * N].view(C, N).cpu().numpy().astype(np.float64)
         gp = posr.grad.view(-1, 3)[a0:a0 + N].cpu().numpy().astype(np.float64)
