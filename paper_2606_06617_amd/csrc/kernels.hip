@@ -269,7 +269,7 @@ __device__ __forceinline__ void fft_stage(float2 *buf, int n, int ns, const Fast
 // (unnormalised in both directions).  tw[m] = exp(-2 pi i m / n).  The
 // caller synchronises the workgroup before (data loaded) and after.
 template <int S, int MAXE>
-__device__ void lds_fft(float2 *buf, const FftAxis &ax, int lw_log2, int ld, const float2 *tw, int tid) {
+__device__ __forceinline__ void lds_fft(float2 *buf, const FftAxis &ax, int lw_log2, int ld, const float2 *tw, int tid) {
   const int lane = tid & 63, wave = tid >> 6;
   int ns = 1;
   for (int s = 0; s < ax.nst; ++s) {
