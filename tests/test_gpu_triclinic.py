@@ -13,7 +13,10 @@ through the C ABI, against the FP64 general-cell oracle:
 * the cell gradient dE/dH (constant-pressure box derivative) against
   central differences of the oracle's energy in H at fixed fractional
   coordinates;
-* the double backward against oracle.cellsum.force_vjp."""
+* the double backward against oracle.cellsum.force_vjp;
+* a batch of general cells equal to the standalone calls bit for bit, and
+  the two-ion primitive cell (narrower than r_c) against the Madelung
+  energy."""
 import math
 import os
 
@@ -193,3 +196,46 @@ def test_force_vjp_in_a_skewed_cell():
     ep = _rel_rms(gp.cpu().numpy().astype(np.float64), rp)
     print("force vjp dq %.2e dr %.2e" % (eq, ep), flush=True)
     assert eq <= 1e-4 and ep <= 1e-4
+
+
+def test_two_ion_primitive_cell_narrower_than_the_cutoff():
+    # one Na+ and one Cl- on the face-centred primitive cell: its widths
+    # across the lattice planes (a / sqrt 3 = 3.26 A) are below r_c = 5 A,
+    # so the real-space sum reaches images two and three cells away
+    from paper_2606_06617_amd.api import Plan
+    with open(os.path.join(GOLDEN, "madelung_nacl.txt")) as f:
+        madelung = float([ln for ln in f if ln.strip() and not ln.startswith("#")][0])
+    a = 5.64
+    w = wl.nacl_primitive(ncell=1, a=a)
+    ref = -madelung / (a / 2)
+    plan = Plan(w["box"], w["ps"], r_c=RC, c=30.0, grid=(16, 16, 16), support=8, max_atoms=2)
+    pos, q = torch.from_numpy(w["pos"]).cuda(), torch.from_numpy(w["q"]).cuda()
+    rec = plan.execute(pos, q, forces=True, virial=False)
+    rs = plan.realspace(pos, q, forces=True, virial=False)
+    torch.cuda.synchronize()
+    e = rec["energy"].cpu().numpy()
+    E = float(rs["energy"].cpu().numpy()[0] + e[-1] - e[2])
+    print("two-ion primitive cell: GPU %.10f exact %.10f rel %.2e" % (E, ref, abs(E / ref - 1)), flush=True)
+    assert E == pytest.approx(ref, rel=2e-6)
+
+
+def test_batch_of_general_cells_equals_standalone():
+    from paper_2606_06617_amd.api import Batch, Plan
+    ws = [wl.triclinic_box(n, ps=(1, 6), seed=60 + i) for i, n in enumerate((700, 1500, 2600))]
+    plans = [Plan(w["box"], w["ps"], r_c=RC, c=C_MOL, tol=1e-5, support=8, max_atoms=w["pos"].shape[0])
+             for w in ws]
+    inputs = [(torch.from_numpy(w["pos"]).cuda(), torch.from_numpy(w["q"]).cuda()) for w in ws]
+    batch = Batch(plans, [x[0].shape[0] for x in inputs])
+    pos, q = Batch.concat(inputs)
+    out = batch.execute(pos, q, forces=True, virial=True)
+    torch.cuda.synchronize()
+    a0 = e0 = 0
+    for i, (plan, (p, qq)) in enumerate(zip(plans, inputs)):
+        ref = plan.execute(p, qq, forces=True, virial=True)
+        torch.cuda.synchronize()
+        n, ne = p.shape[0], 3 * plan.C + 1
+        assert torch.equal(out["energy"][e0:e0 + ne], ref["energy"])
+        assert torch.equal(out["forces"][a0:a0 + n], ref["forces"])
+        assert torch.equal(out["virial"][i], ref["virial"])
+        a0 += n
+        e0 += ne

@@ -38,9 +38,11 @@ def _skew_cell(seed, n=12, charged=True):
     return pos, q
 
 
-def test_rock_salt_madelung_on_the_primitive_cell():
+@pytest.mark.parametrize("ncell", [1, 2])
+def test_rock_salt_madelung_on_the_primitive_cell(ncell):
+    # ncell = 1: two ions in a cell whose widths (a / sqrt 3) are below r_c
     a = 5.64
-    w = wl.nacl_primitive(ncell=2, a=a)
+    w = wl.nacl_primitive(ncell=ncell, a=a)
     pos = w["pos"].astype(np.float64)
     q = w["q"][0].astype(np.float64)
     ref = -0.5 * pos.shape[0] * _madelung() / (a / 2)
