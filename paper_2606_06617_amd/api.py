@@ -6,7 +6,7 @@ import ctypes
 
 import torch
 
-from . import _lib
+from . import _lib, autotune
 
 
 def _ptr(t):
@@ -33,13 +33,24 @@ class Plan:
     def __init__(self, box, ps, r_c=5.0, c=12.024, tol=1e-5, grid=None, support=0, c_spread=0.0,
                  max_atoms=1, tile=None, check_inputs=False):
         L = _lib.lib()
-        self.params = _lib.make_params(box, ps, r_c, c, tol, grid, support, c_spread, tile,
-                                       flags=_lib.FLAG_CHECK_INPUTS if check_inputs else 0)
+        flags = _lib.FLAG_CHECK_INPUTS if check_inputs else 0
+        self.params = _lib.make_params(box, ps, r_c, c, tol, grid, support, c_spread, tile, flags=flags)
         h = ctypes.c_void_p()
         _lib.check(L.pswflr_plan_create(ctypes.byref(self.params), int(max_atoms), ctypes.byref(h)))
         self.handle = h
         inf = _lib.Info()
         _lib.check(L.pswflr_plan_info(h, ctypes.byref(inf)))
+        if tile is None:
+            # the autotuner's cached choice for this shape, if any
+            best = autotune.cached_tile(tuple(inf.grid), inf.support, inf.n_channels, max_atoms)
+            if best is not None and best != tuple(inf.tile):
+                prm = _lib.make_params(box, ps, r_c, inf.c, tol, tuple(inf.grid), inf.support, inf.c_spread,
+                                       best, flags=flags)
+                h2 = ctypes.c_void_p()
+                if L.pswflr_plan_create(ctypes.byref(prm), int(max_atoms), ctypes.byref(h2)) == _lib.OK:
+                    L.pswflr_plan_destroy(h)
+                    self.params, self.handle, h = prm, h2, h2
+                    _lib.check(L.pswflr_plan_info(h, ctypes.byref(inf)))
         self.info_raw = inf
         C = inf.n_channels
         self.info = {

@@ -8,6 +8,8 @@ list of candidate tiles on the device with the caller's stream and keeps
 the fastest.  Results are cached in a JSON file (path from
 PSWFLR_AUTOTUNE_CACHE, default ~/.cache/pswflr/autotune.json) keyed by the
 device architecture, grid, P, C and the atom count rounded to a power of two.
+api.Plan applies a cached tile by default when the caller names none
+(PSWFLR_AUTOTUNE=0 turns that off).
 """
 import json
 import math
@@ -17,6 +19,7 @@ import time
 
 KERNEL_VERSION = 12
 _LOCK = threading.Lock()
+_MEMO = {}   # path -> (mtime, size, parsed cache): the file is read again only when it changes
 
 
 def cache_path():
@@ -25,11 +28,21 @@ def cache_path():
 
 
 def _load():
+    path = cache_path()
     try:
-        with open(cache_path()) as f:
-            return json.load(f)
+        st = os.stat(path)
+    except OSError:
+        return {}
+    got = _MEMO.get(path)
+    if got is not None and got[0] == st.st_mtime_ns and got[1] == st.st_size:
+        return got[2]
+    try:
+        with open(path) as f:
+            db = json.load(f)
     except (OSError, ValueError):
         return {}
+    _MEMO[path] = (st.st_mtime_ns, st.st_size, db)
+    return db
 
 
 def _store(db):
@@ -106,6 +119,29 @@ def key_for(arch, grid, P, C, n_atoms):
 def lookup(arch, grid, P, C, n_atoms):
     with _LOCK:
         return _load().get(key_for(arch, grid, P, C, n_atoms))
+
+
+_ARCH = {}
+
+
+def device_arch(device=None):
+    """gfx architecture name of a CUDA device (cached)."""
+    import torch
+    d = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    if d not in _ARCH:
+        _ARCH[d] = torch.cuda.get_device_properties(d).gcnArchName.split(":")[0]
+    return _ARCH[d]
+
+
+def cached_tile(grid, P, C, n_atoms):
+    """The tuned tile for this shape on the current device, or None (no entry,
+    or PSWFLR_AUTOTUNE=0)."""
+    if os.environ.get("PSWFLR_AUTOTUNE", "1") == "0":
+        return None
+    if not os.path.exists(cache_path()):
+        return None
+    hit = lookup(device_arch(), grid, P, C, n_atoms)
+    return tuple(hit["tile"]) if hit else None
 
 
 def tune(pos, q, box, ps, r_c=5.0, c=12.024, grid=None, support=0, c_spread=0.0, reps=5, verbose=False):

@@ -29,3 +29,19 @@ def test_feasibility_model_matches_library(grid, P):
         assert (got == DEVICE) == want, (grid, P, tile, got, want)
         seen_ok += want
     assert seen_ok > 0
+
+
+def test_cache_is_reread_only_when_the_file_changes(tmp_path, monkeypatch):
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("PSWFLR_AUTOTUNE_CACHE", str(path))
+    key = autotune.key_for("gfx950", (40, 40, 40), 8, 2, 3000)
+    assert autotune.lookup("gfx950", (40, 40, 40), 8, 2, 3000) is None
+    path.write_text('{"%s": {"tile": [8, 8, 8]}}' % key)
+    assert autotune.lookup("gfx950", (40, 40, 40), 8, 2, 3000)["tile"] == [8, 8, 8]
+    path.write_text('{"%s": {"tile": [8, 8, 20]}}' % key)      # same size, new contents
+    import os
+    st = os.stat(path)
+    os.utime(path, ns=(st.st_atime_ns, st.st_mtime_ns + 1_000_000))
+    assert autotune.lookup("gfx950", (40, 40, 40), 8, 2, 3000)["tile"] == [8, 8, 20]
+    monkeypatch.setenv("PSWFLR_AUTOTUNE", "0")
+    assert autotune.cached_tile((40, 40, 40), 8, 2, 3000) is None

@@ -83,7 +83,13 @@ def test_autotuned_tile_is_valid_and_cached(tmp_path, monkeypatch):
     assert tuple(plan.info["tile"]) == tuple(best)
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     assert autotune.lookup(arch, (40, 40, 40), 8, 2, 3000)["tile"] == list(best)
-    ref = Plan(w["box"], w["ps"], grid=(40, 40, 40), support=8, max_atoms=3000).execute(pos, q)
+    # a plan that names no tile takes the cached choice; PSWFLR_AUTOTUNE=0 turns that off
+    auto = Plan(w["box"], w["ps"], grid=(40, 40, 40), support=8, max_atoms=3000)
+    assert tuple(auto.info["tile"]) == tuple(best)
+    monkeypatch.setenv("PSWFLR_AUTOTUNE", "0")
+    dflt = Plan(w["box"], w["ps"], grid=(40, 40, 40), support=8, max_atoms=3000)
+    print("tuned tile", best, "default tile", dflt.info["tile"], flush=True)
+    ref = dflt.execute(pos, q)
     out = plan.execute(pos, q)
     torch.cuda.synchronize()
     e1, e2 = out["energy"].cpu().numpy(), ref["energy"].cpu().numpy()
