@@ -153,79 +153,108 @@ def batch_leg(reps=10):
             "sequential_ms": round(t_seq * 1e3, 3), "sequential_atoms_s": round(atoms / t_seq, 1)}
 
 
-def small_leg(reps=200):
-    """Per-call latency of the two small configurations (rock-salt 512 atoms
-    at 32^3, P = 6; water 3000 atoms, two channels, at 48^3, P = 8), energy,
-    forces and virial: launch-bound work of a few microseconds per kernel.
-    Reported: the host wall time of one call followed by a stream
-    synchronisation (eager launches), the same for a replay of the call
-    captured once as a HIP graph, and the device time of the call's
-    kernels (HIP events around every launch)."""
+def _call_latency(plan, pos, q, reps):
+    """Host wall time of one call plus a stream synchronisation (eager), of a
+    replay of the call captured once as a HIP graph, and the device time of
+    the call's kernels (HIP events around every launch)."""
     import ctypes
 
     import torch
 
     from paper_2606_06617_amd import _lib
+
+    L = _lib.lib()
+    dev = pos.device
+    N, C = pos.shape[0], plan.C
+    ws = plan.new_workspace(dev)
+    res = {"energy": torch.empty(3 * C + 1, dtype=torch.float64, device=dev),
+           "forces": torch.empty((N, 3), dtype=torch.float32, device=dev),
+           "virial": torch.empty(6, dtype=torch.float64, device=dev)}
+    side = torch.cuda.Stream(device=dev)
+
+    def call():
+        plan.execute(pos, q, forces=True, virial=True, workspace=ws, out=res, stream=side)
+
+    with torch.cuda.stream(side):
+        for _ in range(10):
+            call()
+    side.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        call()
+        side.synchronize()
+    eager = (time.perf_counter() - t0) / reps
+    ref = res["energy"].clone()
+    graph_ms = None
+    try:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            call()
+        side.synchronize()
+        for _ in range(10):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+            torch.cuda.synchronize()
+        graph_ms = round((time.perf_counter() - t0) / reps * 1e3, 4)
+        if not torch.equal(res["energy"], ref):
+            graph_ms = None
+    except RuntimeError:
+        graph_ms = None
+    _lib.check(L.pswflr_profile_enable(plan.handle, 1))
+    with torch.cuda.stream(side):
+        for _ in range(20):
+            call()
+    side.synchronize()
+    ms = (ctypes.c_double * len(STAGES))()
+    cnt = (ctypes.c_int64 * len(STAGES))()
+    _lib.check(L.pswflr_profile_read(plan.handle, ms, cnt))
+    _lib.check(L.pswflr_profile_enable(plan.handle, 0))
+    return {"tile": list(plan.info["tile"]), "eager_call_ms": round(eager * 1e3, 4), "graph_replay_ms": graph_ms,
+            "device_ms": round(sum(ms) / 20, 4), "launches_per_call": int(sum(cnt) // 20)}
+
+
+def small_leg(reps=200):
+    """Per-call latency of the two small configurations (rock-salt 512 atoms
+    at 32^3, P = 6; water 3000 atoms, two channels, at 48^3, P = 8), energy,
+    forces and virial: launch-bound work of a few microseconds per kernel.
+    Each is timed with the planner's tile and again with the tile the
+    autotuner picks for it (timed candidates, cached in a temporary file)."""
+    import tempfile
+
+    import torch
+
+    from paper_2606_06617_amd import autotune
     from paper_2606_06617_amd import workloads as wl
     from paper_2606_06617_amd.api import Plan
 
-    L = _lib.lib()
     out = {}
-    for w in (wl.nacl(), wl.water()):
-        N, C = w["pos"].shape[0], len(w["ps"])
-        dev = torch.device("cuda:0")
-        pos = torch.from_numpy(w["pos"]).to(dev)
-        q = torch.from_numpy(w["q"]).to(dev)
-        plan = Plan(w["box"], w["ps"], r_c=R_C, c=C_MOL, grid=w["grid"], support=w["support"], max_atoms=N)
-        ws = plan.new_workspace(dev)
-        res = {"energy": torch.empty(3 * C + 1, dtype=torch.float64, device=dev),
-               "forces": torch.empty((N, 3), dtype=torch.float32, device=dev),
-               "virial": torch.empty(6, dtype=torch.float64, device=dev)}
-        side = torch.cuda.Stream(device=dev)
-
-        def call():
-            plan.execute(pos, q, forces=True, virial=True, workspace=ws, out=res, stream=side)
-
-        with torch.cuda.stream(side):
-            for _ in range(10):
-                call()
-        side.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            call()
-            side.synchronize()
-        eager = (time.perf_counter() - t0) / reps
-        ref = res["energy"].clone()
-        graph_ms = None
+    old = os.environ.get("PSWFLR_AUTOTUNE_CACHE")
+    with tempfile.TemporaryDirectory() as tdir:
+        os.environ["PSWFLR_AUTOTUNE_CACHE"] = os.path.join(tdir, "tune.json")
         try:
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=side):
-                call()
-            side.synchronize()
-            for _ in range(10):
-                g.replay()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                g.replay()
-                torch.cuda.synchronize()
-            graph_ms = round((time.perf_counter() - t0) / reps * 1e3, 4)
-            if not torch.equal(res["energy"], ref):
-                graph_ms = None
-        except RuntimeError:
-            graph_ms = None
-        _lib.check(L.pswflr_profile_enable(plan.handle, 1))
-        with torch.cuda.stream(side):
-            for _ in range(20):
-                call()
-        side.synchronize()
-        ms = (ctypes.c_double * len(STAGES))()
-        cnt = (ctypes.c_int64 * len(STAGES))()
-        _lib.check(L.pswflr_profile_read(plan.handle, ms, cnt))
-        _lib.check(L.pswflr_profile_enable(plan.handle, 0))
-        out[w["name"]] = {"grid": list(plan.info["grid"]), "support": plan.info["support"], "channels": C,
-                          "eager_call_ms": round(eager * 1e3, 4), "graph_replay_ms": graph_ms,
-                          "device_ms": round(sum(ms) / 20, 4), "launches_per_call": int(sum(cnt) // 20)}
+            for w in (wl.nacl(), wl.water()):
+                N, C = w["pos"].shape[0], len(w["ps"])
+                dev = torch.device("cuda:0")
+                pos = torch.from_numpy(w["pos"]).to(dev)
+                q = torch.from_numpy(w["q"]).to(dev)
+                plan = Plan(w["box"], w["ps"], r_c=R_C, c=C_MOL, grid=w["grid"], support=w["support"],
+                            max_atoms=N)
+                rec = {"grid": list(plan.info["grid"]), "support": plan.info["support"], "channels": C}
+                rec.update(_call_latency(plan, pos, q, reps))
+                best = autotune.tune(pos, q, w["box"], w["ps"], r_c=R_C, c=C_MOL, grid=w["grid"],
+                                     support=w["support"], reps=20)
+                tuned = Plan(w["box"], w["ps"], r_c=R_C, c=C_MOL, grid=w["grid"], support=w["support"],
+                             max_atoms=N, tile=best)
+                rec["autotuned"] = _call_latency(tuned, pos, q, reps)
+                out[w["name"]] = rec
+        finally:
+            if old is None:
+                os.environ.pop("PSWFLR_AUTOTUNE_CACHE", None)
+            else:
+                os.environ["PSWFLR_AUTOTUNE_CACHE"] = old
     return out
 
 
