@@ -335,7 +335,10 @@ class Server:
 
     def run_trace(self, reqs, realtime=True, poll_sleep=50e-6):
         """Replay requests at their t_arrival offsets; return them when all
-        have completed."""
+        have completed.  While work is on the device the loop polls without
+        sleeping (a sleep adds its own length to every completion it
+        overlaps); with nothing in flight it sleeps until the next arrival,
+        at most poll_sleep seconds at a time."""
         order = sorted(reqs, key=lambda r: r.t_arrival)
         # the cyclic garbage collector can pause the loop for tens of ms in
         # the middle of a trace; it runs before and after instead
@@ -353,8 +356,12 @@ class Server:
                     self.submit(order[i])
                     i += 1
                 self.poll()
-                if poll_sleep:
-                    time.sleep(poll_sleep)
+                if poll_sleep and not self.inflight and not self.pending:
+                    wait = poll_sleep
+                    if realtime and i < len(order):
+                        wait = min(wait, order[i].t_arrival - self.now())
+                    if wait > 0:
+                        time.sleep(wait)
         finally:
             if gc_on:
                 gc.enable()
