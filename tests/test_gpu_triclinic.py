@@ -239,3 +239,20 @@ def test_batch_of_general_cells_equals_standalone():
         assert torch.equal(out["virial"][i], ref["virial"])
         a0 += n
         e0 += ne
+
+
+def test_left_handed_cell():
+    # the same lattice with two lattice vectors swapped (det H < 0): V = |det H|
+    from paper_2606_06617_amd.api import Plan
+    w = wl.triclinic_box(2000, ps=(1, 6), seed=59, neutral=False)
+    H = w["box"][[0, 2, 1]]
+    assert np.linalg.det(H) < 0
+    w2 = dict(w, box=H, name="left_handed_2000")
+    plan = Plan(H, w["ps"], r_c=RC, c=C_MOL, grid=(36, 36, 36), support=8, max_atoms=2000)
+    _against_cellsum(w2, plan, C_MOL)
+    rs = plan.realspace(torch.from_numpy(w["pos"]).cuda(), torch.from_numpy(w["q"]).cuda(), forces=True, virial=True)
+    torch.cuda.synchronize()
+    r = realspace.evaluate(w["pos"].astype(np.float64), w["q"].astype(np.float64), H, w["ps"], C_MOL, RC)
+    e = rs["energy"].cpu().numpy()
+    assert np.all(np.abs(e - r["Ereal"]) <= 1e-5 * np.abs(r["Ereal"]))
+    assert _rel_rms(rs["forces"].cpu().numpy().astype(np.float64), r["F"]) <= 1e-5
