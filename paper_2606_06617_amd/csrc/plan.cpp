@@ -69,27 +69,54 @@ struct PooledTable {
 };
 std::multimap<size_t, PooledTable> g_table_pool;  // capacity -> block
 
+// Plan tables come in power-of-two size classes (at least 4 KiB) carved
+// from device arenas of 8 MiB, held until the process ends, so creating a
+// plan for a new box costs no hipMalloc once the arenas exist (a serving
+// loop builds a plan per request).
+struct TableArena {
+  int device;
+  char *base;
+  size_t size, used;
+};
+std::vector<TableArena> g_table_arenas;
+constexpr size_t kTableArenaBytes = size_t(8) << 20;
+
+size_t table_class(size_t bytes) {
+  size_t c = 4096;
+  while (c < bytes) c <<= 1;
+  return c;
+}
+
 hipError_t table_alloc(size_t bytes, int device, void **out, size_t *cap) {
-  PooledTable got{-1, nullptr, nullptr};
-  {
-    std::lock_guard<std::mutex> lock(g_table_mu);
-    for (auto it = g_table_pool.lower_bound(bytes); it != g_table_pool.end() && it->first <= 4 * bytes + 65536; ++it) {
-      if (it->second.device != device) continue;
-      // only a block whose last use has completed: never wait here (the
-      // stream's event may stand for newer work queued behind it)
-      if (it->second.done && hipEventQuery(it->second.done) != hipSuccess) continue;
-      got = it->second;
-      *cap = it->first;
-      g_table_pool.erase(it);
-      break;
-    }
-  }
-  if (got.block) {
-    *out = got.block;
+  const size_t cls = table_class(bytes);
+  std::lock_guard<std::mutex> lock(g_table_mu);
+  auto range = g_table_pool.equal_range(cls);
+  for (auto it = range.first; it != range.second; ++it) {
+    if (it->second.device != device) continue;
+    // only a block whose last use has completed: never wait here (the
+    // stream's event may stand for newer work queued behind it)
+    if (it->second.done && hipEventQuery(it->second.done) != hipSuccess) continue;
+    *out = it->second.block;
+    *cap = cls;
+    g_table_pool.erase(it);
     return hipSuccess;
   }
-  *cap = bytes;
-  return hipMalloc(out, bytes);
+  for (auto &a : g_table_arenas) {
+    if (a.device == device && a.used + cls <= a.size) {
+      *out = a.base + a.used;
+      a.used += cls;
+      *cap = cls;
+      return hipSuccess;
+    }
+  }
+  TableArena a{device, nullptr, std::max(kTableArenaBytes, cls), 0};
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(&a.base), a.size);
+  if (e != hipSuccess) return e;
+  *out = a.base;
+  a.used = cls;
+  *cap = cls;
+  g_table_arenas.push_back(a);
+  return hipSuccess;
 }
 
 void table_release(void *p, size_t cap, int device, hipEvent_t done) {
