@@ -72,7 +72,7 @@ def _tile_fits(bx, by, bz, P, lds=160 * 1024):
     cpw = 4 // nbz
     nby = pad(by) // 4
     S = pad(bx) + pad(by) + pad(bz)
-    if nby % cpw or (pad(bx) // 4) * nby > 8 * cpw or S > 64 or bx * by * bz > 256 * (12 + S):
+    if nby % cpw or (pad(bx) // 4) * nby > 8 * cpw or S > 64 or bx * by * bz > 129 * (4 + S):
         return False
     ex, ey, ez = bx + P - 1, by + P - 1, bz + P - 1
     return ex * ey * ez <= 512 * 16 and (2 * 512 * 16 + 96) * 4 <= lds

@@ -146,6 +146,7 @@ struct Geo {
   float invV;
   double V;
   int CG_spread;          // channels per spread pass
+  int scap;               // candidates per flush of the vector-ALU spread (128 or 256)
   int CG_gather;          // channels per gather halo staging (1)
   int nxblk;              // blocks of the fused x pass
   int zlines;             // lines per z-pass block (power of two)

@@ -577,9 +577,9 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nbl
 // is accumulated.  No atomics, no read-modify-write of shared memory; the
 // summation order is fixed, so the result is bitwise reproducible.
 constexpr int kSpreadThreads = 512;
-constexpr int kSpreadCap = 256;     // candidates staged per flush
+constexpr int kSpreadCap = 256;     // candidates staged per flush (matrix-core variant; at most)
+constexpr int kSpreadCapV = 128;    // the vector-ALU variants' smaller flush
 constexpr int kSpreadScreenPer = 1; // atoms screened per thread per round
-constexpr int kSpreadList = kSpreadCap + kSpreadScreenPer * 512;  // screened-candidate list
 constexpr int kSpreadMaxCells = 64; // candidate cells of a tile
 constexpr int kSpreadCGM = 16;      // channels per launch (most)
 // accumulator counts the spread is instantiated for: 2 or 4 channels on the
@@ -587,6 +587,16 @@ constexpr int kSpreadCGM = 16;      // channels per launch (most)
 __host__ __device__ constexpr int spread_cg4(int cg) { return (cg + 3) / 4 * 4; }
 __host__ __device__ constexpr int spread_cg_template(int ncg) { return ncg <= 2 ? 2 : (ncg <= 4 ? 4 : kSpreadCGM); }
 __host__ __device__ constexpr bool spread_mfma(int cg) { return cg == kSpreadCGM; }
+// Candidates per flush.  The vector-ALU variants (2 or 4 channels: the
+// small grids of training batches and serving) take the plan's choice
+// (Geo::scap): 128 when a launch has many more tiles than the chip holds at
+// once, so their LDS footprint (about 36 KB at the largest tile) lets four
+// workgroups share a CU, the most their registers allow; 256 when all its
+// tiles are resident anyway, which saves a second flush on crowded tiles.
+// Flush boundaries do not change the summation order.
+__host__ __device__ constexpr int spread_cap(int cg, int scap) { return spread_mfma(cg) ? kSpreadCap : scap; }
+// screened-candidate list: an unflushed tail (< cap) plus one screening round
+__host__ __device__ constexpr int spread_list(int cap) { return cap + kSpreadScreenPer * kSpreadThreads; }
 constexpr int kSpreadNBW = 4;       // 4x4x4 blocks per wave
 constexpr int kSpreadMaxS = 64;     // padded tile edges Sx + Sy + Sz
 constexpr int kSpreadBias = 8;      // packed window offsets are stored + bias
@@ -602,12 +612,12 @@ constexpr int kSpreadHitList = 68;  // per wave and block: 64 hits padded to who
 // staged charges per candidate: 16 for the matrix-core variant, the
 // accumulator count rounded to 4 otherwise
 __host__ __device__ constexpr int spread_qstride(int cg) { return spread_mfma(cg) ? kSpreadCGM : spread_cg4(cg); }
-__host__ __device__ __forceinline__ int spread_stage_floats(int S, int cg) {
-  return (kSpreadCap + 1) * (spread_qstride(cg) + S);
+__host__ __device__ __forceinline__ int spread_stage_floats(int S, int cg, int cap) {
+  return (cap + 1) * (spread_qstride(cg) + S);
 }
 // the block bits and hit lists only exist for the matrix-core variant
-__host__ __device__ __forceinline__ int spread_lds_floats(int S, int cg) {
-  return spread_stage_floats(S, cg) + 5 * kSpreadList + 2 * kSpreadMaxCells + 1 + 3 + kWinSeg * (kWinDeg + 1) +
+__host__ __device__ __forceinline__ int spread_lds_floats(int S, int cg, int cap) {
+  return spread_stage_floats(S, cg, cap) + 5 * spread_list(cap) + 2 * kSpreadMaxCells + 1 + 3 + kWinSeg * (kWinDeg + 1) +
          (spread_mfma(cg) ? 2 * kSpreadCap + (kSpreadThreads / 64) * kSpreadNBW * kSpreadHitList / 2 : 0);
 }
 __host__ __device__ __forceinline__ int spread_pad4(int b) { return (b + 3) & ~3; }
@@ -719,8 +729,9 @@ __device__ __forceinline__ void spread_flush(const Geo &g, const Work &w, int cg
   // zz is stored at (zz % 4) NBZ + zz / 4.  The window positions of one candidate are
   // distinct (P <= M), so they are plain stores after a zero fill whose
   // start rotates with the candidate (no bank conflicts between lanes).
-  for (int t = tid; t < 3 * kSpreadCap; t += kSpreadThreads) {
-    const int a = t / kSpreadCap, k = t - a * kSpreadCap;
+  const int cap = spread_cap(CG, g.scap);
+  for (int t = tid; t < 3 * cap; t += kSpreadThreads) {
+    const int a = t / cap, k = t - a * cap;
     if (k >= ncand) continue;
     float qv[spread_cg4(CG)];
     if (a == 0) {
@@ -899,22 +910,23 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   const int sz[3] = {spread_pad4(Bx), spread_pad4(By), spread_pad4(Bz)};
   const int S = sz[0] + sz[1] + sz[2];
   float *cq = smem;                                                 // [cap + 1][CGM]
-  float *cw = cq + (kSpreadCap + 1) * spread_qstride(CG);           // [cap + 1][S]
-  float *lf = cw + (kSpreadCap + 1) * S;                            // [list][3] window offsets delta
-  int *ld = reinterpret_cast<int *>(lf + 3 * kSpreadList);          // [list] packed window starts
-  int *li = ld + kSpreadList;                                       // [list] atom index
-  int *rb = li + kSpreadList;                                       // [cells] first atom of a candidate cell
+  const int cap = spread_cap(CG, g.scap);
+  float *cw = cq + (cap + 1) * spread_qstride(CG);           // [cap + 1][S]
+  float *lf = cw + (cap + 1) * S;                            // [list][3] window offsets delta
+  int *ld = reinterpret_cast<int *>(lf + 3 * spread_list(cap));          // [list] packed window starts
+  int *li = ld + spread_list(cap);                                       // [list] atom index
+  int *rb = li + spread_list(cap);                                       // [cells] first atom of a candidate cell
   int *rs = rb + kSpreadMaxCells;                                   // [cells + 1] prefix of their sizes
   float *wcf = smem + ((int(reinterpret_cast<float *>(rs + kSpreadMaxCells + 1) - smem) + 3) & ~3);  // window coefficients, 16-byte aligned
   unsigned short *cbits = reinterpret_cast<unsigned short *>(wcf + kWinSeg * (kWinDeg + 1));  // [cap][4] block bits per axis
-  unsigned short *hl = cbits + 4 * kSpreadCap;                      // [waves][blocks][68] hit lists
+  unsigned short *hl = cbits + 4 * cap;                      // [waves][blocks][68] hit lists
   // (the write-out stage below reuses the cq and cw area)
   __shared__ int wcount[kSpreadScreenPer * (kSpreadThreads / 64)];
 
   const int tid = threadIdx.x, lane = tid & 63;
   // the zero row past the staged candidates (padding of the hit groups)
-  for (int e = tid; e < spread_qstride(CG); e += kSpreadThreads) cq[kSpreadCap * spread_qstride(CG) + e] = 0.0f;
-  for (int e = tid; e < S; e += kSpreadThreads) cw[kSpreadCap * S + e] = 0.0f;
+  for (int e = tid; e < spread_qstride(CG); e += kSpreadThreads) cq[cap * spread_qstride(CG) + e] = 0.0f;
+  for (int e = tid; e < S; e += kSpreadThreads) cw[cap * S + e] = 0.0f;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps block bookkeeping scalar
   const int cell = bx;
   const int cz = cell % g.nc[2], cy = (cell / g.nc[2]) % g.nc[1], cx = cell / (g.nc[2] * g.nc[1]);
@@ -972,7 +984,7 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
 
   // rounds of up to kSpreadScreenPer atoms per thread: screened candidates
   // are appended to the list in screening order (deterministic); the list
-  // is flushed kSpreadCap candidates at a time
+  // is flushed cap candidates at a time
   int nlist = 0, c0 = 0;
   for (int base = 0; base < total || c0 < nlist; base += kSpreadScreenPer * kSpreadThreads) {
     if (base < total) {
@@ -1035,13 +1047,13 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
       __syncthreads();
     }
     const bool last = base + kSpreadScreenPer * kSpreadThreads >= total;
-    while (nlist - c0 >= kSpreadCap || (last && c0 < nlist)) {
-      const int n = min(kSpreadCap, nlist - c0);
+    while (nlist - c0 >= cap || (last && c0 < nlist)) {
+      const int n = min(cap, nlist - c0);
       spread_flush<P, NBZ, CG>(g, w, cg0, ncg, n, sz, cq, cw, ld + c0, lf + 3 * c0, li + c0, wcf, bo, wval, cbits, hl,
                                acc, src);
       c0 += n;
     }
-    // keep the unflushed tail (fewer than kSpreadCap <= threads entries)
+    // keep the unflushed tail (fewer than cap <= threads entries)
     // at the front of the list
     if (c0 > 0) {
       const int rem = nlist - c0;
@@ -1073,7 +1085,7 @@ __device__ __forceinline__ void spread_body(const Geo &g, const Tables &t, const
   // same (x, y, z) element(s) of every channel.
   float *stage = smem;  // reuses the candidate area
   const int nt = Bx * By * Bz;
-  const int cpp = max(1, min(ncg, spread_stage_floats(S, CG) / nt));
+  const int cpp = max(1, min(ncg, spread_stage_floats(S, CG, cap) / nt));
   const bool vec = (Bz & 3) == 0;
   const int epr = vec ? 4 : 1;                       // floats per element
   const int nel = nt / epr;                          // elements per channel
@@ -2259,9 +2271,13 @@ static inline unsigned nblocks(int64_t n, int per) { return unsigned((n + per - 
 size_t spread_lds_bytes(const Geo &g, int ncg) {
   (void)ncg;
   const int S = spread_pad4(g.B[0]) + spread_pad4(g.B[1]) + spread_pad4(g.B[2]);
-  return size_t(spread_lds_floats(S, spread_cg_template(ncg))) * 4;
+  const int cgt = spread_cg_template(ncg);
+  return size_t(spread_lds_floats(S, cgt, spread_cap(cgt, g.scap))) * 4;
 }
 int spread_max_cells() { return kSpreadMaxCells; }
+// vector-ALU spread: the larger flush when a launch's tiles all fit on the
+// chip at once at its occupancy (two workgroups per CU), else the smaller
+int spread_flush_cap(int64_t tiles) { return tiles <= 2 * 256 ? kSpreadCap : kSpreadCapV; }
 // candidate cells a tile of edges b has to screen (see spread_body)
 int spread_candidate_cells(const int *nc, const int *b, int P) {
   int n = 1;
@@ -2275,7 +2291,7 @@ bool spread_tile_ok(int bx, int by, int bz) {
   const int cpw = kSpreadNBW / nbz, nby = spread_pad4(by) / 4, ncol = (spread_pad4(bx) / 4) * nby;
   const int S = spread_pad4(bx) + spread_pad4(by) + spread_pad4(bz);
   return nby % cpw == 0 && ncol <= cpw * (kSpreadThreads / 64) && S <= kSpreadMaxS &&
-         bx * by * bz <= spread_stage_floats(S, 2);
+         bx * by * bz <= spread_stage_floats(S, 2, kSpreadCapV);
 }
 size_t gather_lds_bytes(const Geo &g, int ncg) {
   (void)ncg;
@@ -2672,19 +2688,33 @@ size_t batch_stage_lds(const BatchItem &it, int stage) {
   return 0;
 }
 
-// Spreading of a batch: one launch per kernel variant (support, z blocks,
-// channel accumulators) present in the batch, each over every block; a
-// block whose structure has another variant returns at once.  One kernel
-// holding every variant would be large and spill scalar registers.
+// Spreading of a batch: one launch per kernel variant present in the batch,
+// each over every block; a block whose structure has another variant
+// returns at once.  The matrix-core variant has a launch per (support, z
+// blocks); a vector-ALU variant (NBZ = 0 here) has one per (support,
+// channel accumulators) and takes each structure's z-block count inside,
+// so structures with different tile depths share one launch and its tail.
+// One kernel holding every variant would be large and spill scalar
+// registers.
 template <int P, int NBZ, int CG>
-__global__ __launch_bounds__(kSpreadThreads, 4) void k_batch_spread(const BatchItem *__restrict__ items,
+__global__ __launch_bounds__(kSpreadThreads, NBZ == 0 ? 8 : 4) void k_batch_spread(const BatchItem *__restrict__ items,
                                                                      const int *__restrict__ prefix, int n) {
   const int b = blockIdx.x;
   const int s = find_item(prefix, n, b);
   const BatchItem &it = items[s];
   const Geo &g = it.g;
-  if (g.P != P || spread_nbz(g.B[2]) != NBZ || spread_cg_template(g.C) != CG) return;
-  spread_body<P, NBZ, CG>(g, it.t, it.w, 0, g.C, b - prefix[s], SpreadSrc{});
+  if (g.P != P || spread_cg_template(g.C) != CG) return;
+  const int vb = b - prefix[s];
+  if constexpr (NBZ == 0) {
+    switch (spread_nbz(g.B[2])) {
+      case 1: spread_body<P, 1, CG>(g, it.t, it.w, 0, g.C, vb, SpreadSrc{}); break;
+      case 2: spread_body<P, 2, CG>(g, it.t, it.w, 0, g.C, vb, SpreadSrc{}); break;
+      default: spread_body<P, 4, CG>(g, it.t, it.w, 0, g.C, vb, SpreadSrc{}); break;
+    }
+  } else {
+    if (spread_nbz(g.B[2]) != NBZ) return;
+    spread_body<P, NBZ, CG>(g, it.t, it.w, 0, g.C, vb, SpreadSrc{});
+  }
 }
 
 template <int P, int NBZ, int CG>
@@ -2698,29 +2728,24 @@ static hipError_t bspread_launch(const BatchItem *d_items, const int *d_prefix, 
   return hipSuccess;
 }
 
-template <int P, int NBZ>
-static hipError_t bspread_pz(int cgt, const BatchItem *d_items, const int *d_prefix, int n, int total_blocks,
-                             size_t lds, hipStream_t st) {
-  switch (cgt) {
-    case 2: return bspread_launch<P, NBZ, 2>(d_items, d_prefix, n, total_blocks, lds, st);
-    case 4: return bspread_launch<P, NBZ, 4>(d_items, d_prefix, n, total_blocks, lds, st);
-    default: return bspread_launch<P, NBZ, kSpreadCGM>(d_items, d_prefix, n, total_blocks, lds, st);
-  }
-}
-
 template <int P>
 static hipError_t bspread_p(int nbz, int cgt, const BatchItem *d_items, const int *d_prefix, int n,
                             int total_blocks, size_t lds, hipStream_t st) {
+  if (cgt == 2) return bspread_launch<P, 0, 2>(d_items, d_prefix, n, total_blocks, lds, st);
+  if (cgt == 4) return bspread_launch<P, 0, 4>(d_items, d_prefix, n, total_blocks, lds, st);
   switch (nbz) {
-    case 1: return bspread_pz<P, 1>(cgt, d_items, d_prefix, n, total_blocks, lds, st);
-    case 2: return bspread_pz<P, 2>(cgt, d_items, d_prefix, n, total_blocks, lds, st);
-    case 4: return bspread_pz<P, 4>(cgt, d_items, d_prefix, n, total_blocks, lds, st);
+    case 1: return bspread_launch<P, 1, kSpreadCGM>(d_items, d_prefix, n, total_blocks, lds, st);
+    case 2: return bspread_launch<P, 2, kSpreadCGM>(d_items, d_prefix, n, total_blocks, lds, st);
+    case 4: return bspread_launch<P, 4, kSpreadCGM>(d_items, d_prefix, n, total_blocks, lds, st);
   }
   return hipErrorInvalidValue;
 }
 
+// P * 100 + z blocks * 10 (matrix-core variant; 0 for the vector-ALU ones,
+// which cover every z-block count) + channel accumulators (0 for 16)
 int batch_spread_variant(const Geo &g) {
-  return g.P * 100 + spread_nbz(g.B[2]) * 10 + (spread_cg_template(g.C) == kSpreadCGM ? 0 : spread_cg_template(g.C));
+  const int cgt = spread_cg_template(g.C);
+  return cgt == kSpreadCGM ? g.P * 100 + spread_nbz(g.B[2]) * 10 : g.P * 100 + cgt;
 }
 
 hipError_t launch_batch_spread(const BatchItem *d_items, const int *d_prefix, int n, int total_blocks, size_t lds,

@@ -29,6 +29,7 @@ bool x_register_path(const Geo &g);  // the fused x pass runs the 256-point regi
 bool spread_tile_ok(int bx, int by, int bz);  // tile fits the spreading kernel's blocks and LDS
 int spread_candidate_cells(const int *nc, const int *b, int P);  // cells a tile screens
 int spread_max_cells();
+int spread_flush_cap(int64_t tiles);  // candidates per flush of the vector-ALU spread for a launch of this many tiles
 
 hipError_t enqueue_sort(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st);
 hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t st);

@@ -397,6 +397,7 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
     }
   }
   g.ncell = g.nc[0] * g.nc[1] * g.nc[2];
+  g.scap = spread_flush_cap(g.ncell);
   // channel groups: the spreading kernel keeps kSpreadCGM channels in
   // registers (groups are balanced); the gather walks all channels, one
   // staged halo tile at a time.
@@ -1193,11 +1194,16 @@ pswflr_status batch_impl(int32_t n, const pswflr_plan *plans, const BatchEntry *
   int *prefix = reinterpret_cast<int *>(blob + align256(size_t(n) * sizeof(BatchItem)));
   std::vector<bool> adj(n);
   size_t off = hdr;
+  // the vector-ALU spread's flush size follows the tiles of the whole batch
+  int64_t batch_tiles = 0;
+  for (int i = 0; i < n; ++i) batch_tiles += plans[i]->geo.ncell;
+  const int scap = spread_flush_cap(batch_tiles);
   for (int i = 0; i < n; ++i) {
     const pswflr_plan_s &pl = *plans[i];
     BatchItem &it = items[i];
     it.g = pl.geo;
     it.g.N = io[i].n_atoms;
+    it.g.scap = scap;
     it.t = pl.tab;
     it.w = carve(pl, ws + off, io[i].n_atoms);
     it.az = pl.az;
@@ -1229,11 +1235,21 @@ pswflr_status batch_impl(int32_t n, const pswflr_plan *plans, const BatchEntry *
     prefix[stg * (n + 1) + n] = acc;
     total[stg] = acc;
   }
-  std::vector<int> spread_variants;  // kernel variants of the spreading stage present in the batch
+  // kernel variants of the spreading stage present in the batch, each with
+  // the largest LDS footprint among its own structures
+  std::vector<int> spread_variants;
+  std::vector<size_t> spread_lds;
   for (int i = 0; i < n; ++i) {
     const int v = batch_spread_variant(items[i].g);
-    if (std::find(spread_variants.begin(), spread_variants.end(), v) == spread_variants.end())
+    const size_t l = batch_stage_lds(items[i], kBsSpread);
+    const auto it = std::find(spread_variants.begin(), spread_variants.end(), v);
+    if (it == spread_variants.end()) {
       spread_variants.push_back(v);
+      spread_lds.push_back(l);
+    } else {
+      size_t &m = spread_lds[size_t(it - spread_variants.begin())];
+      m = std::max(m, l);
+    }
   }
   hipError_t e = hipMemcpyAsync(ws, blob, hdr, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipEventRecord(g_header.ev, st);
@@ -1250,8 +1266,9 @@ pswflr_status batch_impl(int32_t n, const pswflr_plan *plans, const BatchEntry *
       if (stg != kBsSpread)
         return launch_batch_stage(d_items, d_prefix + stg * (n + 1), n, stg, total[stg], lds[stg], 1, st);
       hipError_t r = hipSuccess;
-      for (int v : spread_variants)
-        if (r == hipSuccess) r = launch_batch_spread(d_items, d_prefix + stg * (n + 1), n, total[stg], lds[stg], v, st);
+      for (size_t k = 0; k < spread_variants.size(); ++k)
+        if (r == hipSuccess)
+          r = launch_batch_spread(d_items, d_prefix + stg * (n + 1), n, total[stg], spread_lds[k], spread_variants[k], st);
       return r;
     });
     if (e != hipSuccess) return fail(PSWFLR_ERR_DEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
