@@ -101,7 +101,9 @@ def batch_leg(reps=10):
     evaluated one call after another, both with workspaces and outputs
     reused; and the training step of the batch: energy-only batched forward
     plus the batched hand-written adjoint (dE/dq, dE/dr of every structure).
-    atoms/s over the batch, host wall time per call."""
+    The plans take the planner's tiles; the batched call is timed again with
+    the tiles the autotuner picks one structure at a time.  atoms/s over the
+    batch, host wall time per call."""
     import torch
 
     from paper_2606_06617_amd import workloads as wl
@@ -110,7 +112,7 @@ def batch_leg(reps=10):
     structs = wl.diff_batch()
     dev = torch.device("cuda:0")
     plans = [Plan(st["box"], st["ps"], r_c=R_C, c=C_MOL, grid=st["grid"], support=st["support"] or 0,
-                  max_atoms=st["pos"].shape[0]) for st in structs]
+                  max_atoms=st["pos"].shape[0], autotune=False) for st in structs]
     inputs = [(torch.from_numpy(st["pos"]).to(dev), torch.from_numpy(st["q"]).to(dev)) for st in structs]
     batch = Batch(plans, [x[0].shape[0] for x in inputs])
     pos, q = Batch.concat(inputs)
@@ -147,10 +149,56 @@ def batch_leg(reps=10):
             p.execute(ps_, qs_, forces=True, virial=True, workspace=w_)
     torch.cuda.synchronize()
     t_seq = (time.perf_counter() - t0) / reps
+    t_tuned = _batch_with_tuned_tiles(structs, inputs, plans, reps)
     return {"structures": len(structs), "atoms": atoms, "support": plans[0].info["support"],
             "batched_ms": round(t_batch * 1e3, 3), "batched_atoms_s": round(atoms / t_batch, 1),
+            "batched_standalone_tuned_tiles_ms": round(t_tuned * 1e3, 3),
             "forward_adjoint_ms": round(t_train * 1e3, 3), "forward_adjoint_atoms_s": round(atoms / t_train, 1),
             "sequential_ms": round(t_seq * 1e3, 3), "sequential_atoms_s": round(atoms / t_seq, 1)}
+
+
+def _batch_with_tuned_tiles(structs, inputs, plans, reps):
+    """The same batched call with each structure's tile from the autotuner
+    (timed one structure at a time, cached in a temporary file): host wall
+    time per call."""
+    import tempfile
+
+    import torch
+
+    from paper_2606_06617_amd import autotune
+    from paper_2606_06617_amd.api import Batch, Plan
+
+    old = os.environ.get("PSWFLR_AUTOTUNE_CACHE")
+    with tempfile.TemporaryDirectory() as tdir:
+        os.environ["PSWFLR_AUTOTUNE_CACHE"] = os.path.join(tdir, "tune.json")
+        try:
+            best, tuned = {}, []
+            for st, (pos, q), p in zip(structs, inputs, plans):
+                key = (p.info["grid"], p.info["support"], p.C, autotune.key_for("", p.info["grid"], p.info["support"],
+                                                                               p.C, pos.shape[0]))
+                if key not in best:
+                    best[key] = autotune.tune(pos, q, st["box"], st["ps"], r_c=R_C, c=C_MOL, grid=p.info["grid"],
+                                              support=p.info["support"], reps=10)
+                tuned.append(Plan(st["box"], st["ps"], r_c=R_C, c=C_MOL, grid=p.info["grid"],
+                                  support=p.info["support"], max_atoms=pos.shape[0], tile=best[key]))
+        finally:
+            if old is None:
+                os.environ.pop("PSWFLR_AUTOTUNE_CACHE", None)
+            else:
+                os.environ["PSWFLR_AUTOTUNE_CACHE"] = old
+    dev = inputs[0][0].device
+    batch = Batch(tuned, [x[0].shape[0] for x in inputs])
+    pos, q = Batch.concat(inputs)
+    ws = batch.new_workspace(dev)
+    out = batch.execute(pos, q, forces=True, virial=True, workspace=ws)
+    for _ in range(2):
+        batch.execute(pos, q, forces=True, virial=True, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        batch.execute(pos, q, forces=True, virial=True, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
 
 
 def _call_latency(plan, pos, q, reps):

@@ -151,7 +151,7 @@ def tune(pos, q, box, ps, r_c=5.0, c=12.024, grid=None, support=0, c_spread=0.0,
 
     from .api import Plan
     base = Plan(box, ps, r_c=r_c, c=c, grid=grid, support=support, c_spread=c_spread,
-                max_atoms=max(1, pos.shape[0]))
+                max_atoms=max(1, pos.shape[0]), autotune=False)
     g, P, C = base.info["grid"], base.info["support"], base.info["n_channels"]
     arch = torch.cuda.get_device_properties(pos.device).gcnArchName.split(":")[0]
     key = key_for(arch, g, P, C, pos.shape[0])
