@@ -393,20 +393,9 @@ __device__ __forceinline__ void zero_body(const Geo &g, const Work &w, int bx) {
 
 __global__ __launch_bounds__(PSWF_THREADS) void k_zero(Geo g, Work w) { zero_body(g, w, blockIdx.x); }
 
-__device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const float *__restrict__ pos,
-                                         const float *__restrict__ q, int bx) {
-  // atoms staged in caller order as records of g.srec floats: window
-  // offsets and packed start, then the C charges (padded to a multiple of
-  // four), so the reorder reads one aligned record per atom; consecutive
-  // threads write consecutive charge words of the block's records
-  const int64_t b0 = int64_t(bx) * PSWF_THREADS;
-  const int nrow = g.N - b0 < PSWF_THREADS ? int(g.N - b0) : PSWF_THREADS;
-  for (int f = threadIdx.x; f < nrow * g.C; f += PSWF_THREADS) {
-    const int a = f / g.C, ch = f - a * g.C;
-    w.q_b[(b0 + a) * g.srec + 4 + ch] = q[int64_t(ch) * g.N + b0 + a];
-  }
-  const int64_t i = b0 + threadIdx.x;
-  if (i >= g.N) return;
+// one atom: its record (window offsets and packed window start), its tile
+// and its slot in the tile (arbitrary order; the ordering pass fixes it)
+__device__ __forceinline__ void bin_atom(const Geo &g, const Work &w, const float *__restrict__ pos, int64_t i) {
   unsigned packed = 0;
   float dl[3];
   int cell[3];
@@ -437,6 +426,22 @@ __device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const floa
   w.slot[i] = atomicAdd(&w.cell_count[c], 1);
   float4 r = make_float4(dl[0], dl[1], dl[2], __uint_as_float(packed));
   *reinterpret_cast<float4 *>(w.q_b + i * g.srec) = r;
+}
+
+__device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const float *__restrict__ pos,
+                                         const float *__restrict__ q, int bx) {
+  // atoms staged in caller order as records of g.srec floats: window
+  // offsets and packed start, then the C charges (padded to a multiple of
+  // four), so the reorder reads one aligned record per atom; consecutive
+  // threads write consecutive charge words of the block's records
+  const int64_t b0 = int64_t(bx) * PSWF_THREADS;
+  const int nrow = g.N - b0 < PSWF_THREADS ? int(g.N - b0) : PSWF_THREADS;
+  for (int f = threadIdx.x; f < nrow * g.C; f += PSWF_THREADS) {
+    const int a = f / g.C, ch = f - a * g.C;
+    w.q_b[(b0 + a) * g.srec + 4 + ch] = q[int64_t(ch) * g.N + b0 + a];
+  }
+  const int64_t i = b0 + threadIdx.x;
+  if (i < g.N) bin_atom(g, w, pos, i);
 }
 
 __global__ __launch_bounds__(PSWF_THREADS) void k_bin(Geo g, Work w, const float *__restrict__ pos,
@@ -559,6 +564,80 @@ __device__ __forceinline__ void qreduce_body(const Geo &g, const Work &w, int nb
 }
 
 __global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nblk) { qreduce_body(g, w, nblk); }
+
+// Small structures (N <= kPrepSmallMax): the steps above in one workgroup
+// of 1024 threads and one launch, with the same results bit for bit --
+// records, tile counts and starts, the order inside each tile (ascending
+// caller index) and the charge sums.  Phases are separated by workgroup
+// barriers.  The order inside a tile is found by counting, for each atom,
+// the atoms of its tile with a smaller caller index: quadratic in the
+// tile's size, bounded by N^2 / 1024 reads per thread.
+constexpr int kPrepThreads = 1024;
+__global__ __launch_bounds__(kPrepThreads) void k_prep_small(Geo g, Work w, const float *__restrict__ pos,
+                                                             const float *__restrict__ q) {
+  __shared__ double s0[PSWF_THREADS], s1[PSWF_THREADS];
+  __shared__ int lperm[kPrepSmallMax];
+  const int tid = threadIdx.x;
+  const int N = int(g.N);
+  for (int i = tid; i < g.ncell; i += kPrepThreads) w.cell_count[i] = 0;
+  if (tid == 0) w.status[0] = 0;
+  __syncthreads();
+  for (int f = tid; f < N * g.C; f += kPrepThreads) {
+    const int a = f / g.C, ch = f - a * g.C;
+    w.q_b[int64_t(a) * g.srec + 4 + ch] = q[int64_t(ch) * N + a];
+  }
+  for (int i = tid; i < N; i += kPrepThreads) bin_atom(g, w, pos, i);
+  __syncthreads();
+  scan_counts(w.cell_count, w.cell_start, g.ncell, g.N);
+  __syncthreads();
+  // caller indices in tile order (arbitrary inside a tile), kept in LDS
+  for (int i = tid; i < N; i += kPrepThreads) lperm[w.cell_start[w.cell_of[i]] + w.slot[i]] = i;
+  __syncthreads();
+  for (int k = tid; k < N; k += kPrepThreads) {
+    const int key = lperm[k];
+    const int c = w.cell_of[key];
+    const int s = w.cell_start[c], e = w.cell_start[c + 1];
+    int rank = 0;
+    for (int m = s; m < e; ++m) rank += lperm[m] < key;
+    order_move(g, w, key, s + rank);
+  }
+  // charge sums per channel, in the order of k_qsum (one block of 256
+  // threads, as N <= kQChunk) followed by k_qreduce over that one block
+  for (int c = 0; c < g.C; ++c) {
+    for (int pass = 0; pass < 2; ++pass) {
+      double a = 0.0, b = 0.0;
+      if (pass == 0) {
+        if (tid < PSWF_THREADS)
+          for (int i = tid; i < N; i += PSWF_THREADS) {
+            const double v = double(q[int64_t(c) * N + i]);
+            a += v;
+            b += v * v;
+          }
+      } else if (tid == 0) {
+        a = w.qpart[2 * c];
+        b = w.qpart[2 * c + 1];
+      }
+      if (tid < PSWF_THREADS) {
+        s0[tid] = a;
+        s1[tid] = b;
+      }
+      __syncthreads();
+      for (int off = PSWF_THREADS / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+          s0[tid] += s0[tid + off];
+          s1[tid] += s1[tid + off];
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        double *dst = pass == 0 ? w.qpart + 2 * c : w.qsum + 2 * c;
+        dst[0] = s0[0];
+        dst[1] = s1[0];
+      }
+      __syncthreads();
+    }
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Spread (step i), output-stationary.  One workgroup of 8 waves per tile.
@@ -2367,6 +2446,14 @@ hipError_t enqueue_sort(const Geo &g, const Work &w, const float *pos, const flo
 }
 
 int qsum_blocks(const Geo &g) { return int(std::max<int64_t>(1, (g.N + kQChunk - 1) / kQChunk)); }
+
+bool prep_small(const Geo &g) { return g.N <= kPrepSmallMax; }
+
+hipError_t enqueue_prep_small(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st) {
+  hipLaunchKernelGGL(k_prep_small, dim3(1), dim3(kPrepThreads), 0, st, g, w, pos, q);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
 
 hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t st) {
   const int nb = qsum_blocks(g);

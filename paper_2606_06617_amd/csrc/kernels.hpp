@@ -10,6 +10,8 @@
 namespace pswf {
 
 constexpr int kQChunk = 8192;   // atoms per block of the charge sums
+constexpr int kPrepSmallMax = 2048;  // structures up to this size bin, order and sum in one launch
+static_assert(kPrepSmallMax <= kQChunk, "the one-launch charge sums assume a single block");
 constexpr size_t kNoallocScratchBytes = size_t(64) << 20;  // workspace of pswflr_execute_noalloc
 constexpr int kNoallocMaxDevices = 64;
 
@@ -33,6 +35,9 @@ int spread_flush_cap(int64_t tiles);  // candidates per flush of the vector-ALU 
 
 hipError_t enqueue_sort(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st);
 hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t st);
+// one launch for enqueue_sort + enqueue_qsum when prep_small(g)
+bool prep_small(const Geo &g);
+hipError_t enqueue_prep_small(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st);
 hipError_t launch_spread(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st,
                          const SpreadSrc &src = SpreadSrc{});
 hipError_t launch_zfwd(const Geo &g, const Tables &t, const FftAxis &az, const Work &w, hipStream_t st);

@@ -839,8 +839,12 @@ hipError_t run_forward(pswflr_plan_s *pl, hipStream_t st, const Geo &g, const Wo
   StageRunner run{pl, st, timing};
   const Tables &t = pl->tab;
   hipError_t e;
-  if ((e = run(PSWFLR_STAGE_SORT, [&] { return enqueue_sort(g, w, pos, q, st); })) != hipSuccess) return e;
-  if ((e = run(PSWFLR_STAGE_QSUM, [&] { return enqueue_qsum(g, w, q, st); })) != hipSuccess) return e;
+  if (prep_small(g)) {
+    if ((e = run(PSWFLR_STAGE_SORT, [&] { return enqueue_prep_small(g, w, pos, q, st); })) != hipSuccess) return e;
+  } else {
+    if ((e = run(PSWFLR_STAGE_SORT, [&] { return enqueue_sort(g, w, pos, q, st); })) != hipSuccess) return e;
+    if ((e = run(PSWFLR_STAGE_QSUM, [&] { return enqueue_qsum(g, w, q, st); })) != hipSuccess) return e;
+  }
   for (int cg0 = 0; cg0 < g.C; cg0 += g.CG_spread) {
     const int ncg = std::min(g.CG_spread, g.C - cg0);
     if ((e = run(PSWFLR_STAGE_SPREAD, [&] { return launch_spread(g, t, w, cg0, ncg, st); })) != hipSuccess)
