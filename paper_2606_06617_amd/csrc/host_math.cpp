@@ -611,6 +611,29 @@ static double search_c_spread(int P, double eta, double c_moll) {
   return 0.5 * (a + b);
 }
 
+double spread_error_bound(int P, double eta, double c_moll) {
+  // The estimate grows with eta, so it is taken at the grid point of step
+  // 1/40 at or above eta, with that point's window bandwidth: an upper
+  // bound for the plan's own eta.  Grid points are computed on first use
+  // and cached, so choosing the support costs no quadrature once plans of
+  // a similar coarseness have been made (each evaluation takes a few ms).
+  static std::mutex mu;
+  static std::map<std::tuple<int, long, long>, double> cache;
+  const double step = 1.0 / 40.0;
+  const long i = std::max(1L, long(std::ceil(eta / step - 1e-9)));
+  const auto key = std::make_tuple(P, i, std::lround(c_moll * 1e6));
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  const double eu = std::min(0.99, i * step);
+  const double v = estimate_spread_error(P, eu, choose_c_spread(P, eu, c_moll), c_moll);
+  std::lock_guard<std::mutex> lock(mu);
+  cache[key] = v;
+  return v;
+}
+
 double choose_c_spread(int P, double eta, double c_moll) {
   // The minimiser is a smooth, slowly varying function of eta (the error
   // is flat near it), so it is searched on a grid of eta with step 1/40 and

@@ -102,6 +102,9 @@ double phi_hat_deriv(const Prolate &ps, int p, double k, double c, double r_c);
 // of the truncated PSWF window over the k-ball (see host_math.cpp).
 double estimate_spread_error(int P, double eta, double c_s, double c_mollifier);
 double choose_c_spread(int P, double eta, double c_mollifier);
+// estimate_spread_error at the next grid point of eta (step 1/40) with its
+// chosen window bandwidth, cached: a conservative value for the support choice
+double spread_error_bound(int P, double eta, double c_mollifier);
 
 // Smallest M >= x whose only prime factors are 2, 3, 5 (and even if asked).
 int smooth_size(double x, bool even);

@@ -299,11 +299,11 @@ pswflr_status build_plan(const pswflr_params &in, int64_t max_atoms, pswflr_plan
   double cs = p.c_spread;
   if (P <= 0) {
     // smallest P whose estimated force error (about 25x the aliasing
-    // estimate) stays below eps_spread = tol / 3
+    // estimate, bounded from above on a cached grid of eta) stays below
+    // eps_spread = tol / 3
     P = 8;
     for (int cand = 4; cand <= 8; ++cand) {
-      const double cc = choose_c_spread(cand, eta, c);
-      if (25.0 * estimate_spread_error(cand, eta, cc, c) <= p.tol / 3.0) {
+      if (25.0 * spread_error_bound(cand, eta, c) <= p.tol / 3.0) {
         P = cand;
         break;
       }

@@ -33,5 +33,11 @@ int main(int argc, char **argv) {
   for (double t : {0.0, 0.33, 0.8, 0.999}) std::printf("win %.17g %.17g %.17g\n", t, wp.eval(t), w20(t));
   for (double s : {0.0, 5.0, 19.0}) std::printf("wft %.17g %.17g %.17g\n", s, w20.window_ft(s), w20.lambda() * w20(s / 20.0));
   std::printf("cs6 %.6f\ncs8 %.6f\n", pswf::choose_c_spread(6, 0.54, 12.024), pswf::choose_c_spread(8, 0.54, 12.024));
+  // the support choice's cached bound against the estimate itself
+  for (int P : {5, 7, 8})
+    for (double eta : {0.31, 0.4603, 0.54, 0.6442})
+      std::printf("ebound %d %.6f %.17g %.17g\n", P, eta,
+                  pswf::estimate_spread_error(P, eta, pswf::choose_c_spread(P, eta, 12.024), 12.024),
+                  pswf::spread_error_bound(P, eta, 12.024));
   return 0;
 }

@@ -81,3 +81,17 @@ def test_window_bandwidth_choice_tracks_measured_optimum(probe):
     # 20.5-21.0 (P = 8) at eta = 0.54
     assert 15.8 <= _get(probe, "cs6")[0][0] <= 16.8
     assert 20.3 <= _get(probe, "cs8")[0][0] <= 21.5
+
+
+def test_support_choice_bound_is_conservative_and_tight(probe):
+    # the cached bound used to choose P is the estimate at the next grid
+    # point of eta (step 1/40): never below the estimate at eta itself, and
+    # close to it (the estimate varies smoothly with eta)
+    rows = _get(probe, "ebound")
+    assert len(rows) == 12
+    for P, eta, est, bound in rows:
+        assert bound >= est * (1 - 1e-12), (P, eta, est, bound)
+        assert bound <= 3.0 * est, (P, eta, est, bound)
+    for P in (5, 7, 8):
+        b = [r[3] for r in rows if r[0] == P]
+        assert all(x < y for x, y in zip(b, b[1:])), (P, b)
