@@ -344,6 +344,13 @@ enum {
   PSWFLR_NUM_STAGES = 10
 };
 pswflr_status pswflr_profile_enable(pswflr_plan plan, int enable);
+/* As pswflr_profile_enable, restricted to the stages whose bit
+ * (1u << PSWFLR_STAGE_*) is set in stage_mask; 0 turns timing off, and
+ * pswflr_profile_enable(plan, 1) is the mask of every stage.  The other
+ * launches then carry no event records, so one stage can be timed inside a
+ * throughput measurement without slowing the rest.
+ * Errors: INVALID_ARG (NULL plan, a bit above the last stage). */
+pswflr_status pswflr_profile_stages(pswflr_plan plan, uint32_t stage_mask);
 pswflr_status pswflr_profile_read(pswflr_plan plan, double *ms_total, int64_t *launches);
 
 /* Static text naming a status (not a passage of the paper: error

@@ -103,6 +103,7 @@ def lib():
     L.pswflr_backward_batch_flat.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(i64), vp, vp, vp, vp,
                                              vp, vp, vp, sz]
     L.pswflr_profile_enable.argtypes = [vp, ctypes.c_int]
+    L.pswflr_profile_stages.argtypes = [vp, ctypes.c_uint32]
     L.pswflr_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     L.pswflr_status_string.argtypes = [ctypes.c_int]
     L.pswflr_status_string.restype = ctypes.c_char_p
@@ -111,7 +112,7 @@ def lib():
                  "pswflr_execute_noalloc", "pswflr_realspace", "pswflr_force_vjp", "pswflr_cell_gradient",
                  "pswflr_backward", "pswflr_batch_workspace", "pswflr_execute_batch",
                  "pswflr_execute_batch_flat", "pswflr_backward_batch_flat",
-                 "pswflr_profile_enable", "pswflr_profile_read"):
+                 "pswflr_profile_enable", "pswflr_profile_stages", "pswflr_profile_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -200,7 +200,7 @@ struct pswflr_plan_s {
          off_rs_slot = 0, off_rs_count = 0, off_rs_start = 0, off_rs_part = 0;
   size_t off_dd = 0;  // scratch of the second-derivative call: [3 C N + C N + 3 N] floats
   // optional per-stage event timing (measurement only)
-  bool prof = false;
+  uint32_t prof_mask = 0;  // bit s: launches of stage s are timed
   std::mutex prof_mu;
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> prof_ev;
 };
@@ -815,14 +815,14 @@ pswflr_status pswflr_plan_destroy(pswflr_plan plan) {
 namespace {
 
 // Runs one stage (one kernel launch, or the small sort/charge-sum groups)
-// and, while profiling is on, brackets it with events on the same stream.
+// and, while its stage is timed, brackets it with events on the same stream.
 struct StageRunner {
   pswflr_plan_s *pl;
   hipStream_t st;
   bool timing = true;  // false: never create timing events (allocation-free calls)
   template <class F>
   hipError_t operator()(int stage, F &&f) {
-    if (!pl->prof || !timing) return f();
+    if (!timing || stage < 0 || stage >= 32 || !((pl->prof_mask >> stage) & 1u)) return f();
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return hipErrorOutOfMemory;
     (void)hipEventRecord(a, st);
@@ -1021,8 +1021,13 @@ pswflr_status pswflr_backward(pswflr_plan plan, pswflr_stream stream, void *work
 }
 
 pswflr_status pswflr_profile_enable(pswflr_plan plan, int enable) {
+  return pswflr_profile_stages(plan, enable != 0 ? (1u << PSWFLR_NUM_STAGES) - 1u : 0u);
+}
+
+pswflr_status pswflr_profile_stages(pswflr_plan plan, uint32_t stage_mask) {
   if (!plan) return fail(PSWFLR_ERR_INVALID_ARG, "plan is NULL");
-  plan->prof = enable != 0;
+  if (stage_mask >> PSWFLR_NUM_STAGES) return fail(PSWFLR_ERR_INVALID_ARG, "stage mask names no stage");
+  plan->prof_mask = stage_mask;
   return PSWFLR_OK;
 }
 
