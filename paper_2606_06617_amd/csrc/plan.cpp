@@ -1104,12 +1104,17 @@ hipError_t header_buffer(size_t bytes, char **out) {
     h.device = dev;
   }
   if (h.cap < bytes) {
+    // hipHostFree synchronizes with the device, so growth is kept rare: at
+    // least 1 MiB (a few hundred structures) and at least double the last
+    // size, instead of a new buffer each time a batch has more structures
+    // than any before.
+    const size_t want = std::max(bytes, std::max(2 * h.cap, size_t(1) << 20));
     if (h.buf) (void)hipHostFree(h.buf);
     h.buf = nullptr;
     h.cap = 0;
-    e = hipHostMalloc(reinterpret_cast<void **>(&h.buf), bytes, hipHostMallocDefault);
+    e = hipHostMalloc(reinterpret_cast<void **>(&h.buf), want, hipHostMallocDefault);
     if (e != hipSuccess) return e;
-    h.cap = bytes;
+    h.cap = want;
   }
   *out = h.buf;
   return hipSuccess;
