@@ -2689,10 +2689,10 @@ __device__ __forceinline__ int find_item(const int *__restrict__ prefix, int n, 
   return lo;
 }
 
-template <int STAGE, int THREADS>
-__global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather) ? 4 : 3)) void k_batch(const BatchItem *__restrict__ items,
-                                                    const int *__restrict__ prefix, int n, int mode) {
-  const int b = blockIdx.x;
+// Virtual block b of one stage over the batch.
+template <int STAGE>
+__device__ __forceinline__ void batch_stage_block(const BatchItem *__restrict__ items, const int *__restrict__ prefix,
+                                                  int n, int b) {
   const int s = find_item(prefix, n, b);
   const BatchItem &it = items[s];
   const int vb = b - prefix[s];
@@ -2732,6 +2732,28 @@ __global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather
       }
       break;
   }
+}
+
+template <int STAGE, int THREADS>
+__global__ __launch_bounds__(THREADS, ((STAGE == kBsSpread || STAGE == kBsGather) ? 4 : 3)) void k_batch(const BatchItem *__restrict__ items,
+                                                    const int *__restrict__ prefix, int n, int mode) {
+  (void)mode;
+  batch_stage_block<STAGE>(items, prefix, n, blockIdx.x);
+}
+
+// Two independent stages of the same workgroup shape in one launch: blocks
+// [0, total_a) run stage A, the rest stage B.  Used for stages whose inputs
+// an earlier launch has finished (the charge sums beside the binning, their
+// reduction beside the scatter), so the batch takes two launches fewer.
+template <int STAGE_A, int STAGE_B>
+__global__ __launch_bounds__(PSWF_THREADS, 3) void k_batch_pair(const BatchItem *__restrict__ items,
+                                                                const int *__restrict__ prefix_a, int total_a,
+                                                                const int *__restrict__ prefix_b, int n) {
+  const int b = blockIdx.x;
+  if (b < total_a)
+    batch_stage_block<STAGE_A>(items, prefix_a, n, b);
+  else
+    batch_stage_block<STAGE_B>(items, prefix_b, n, b - total_a);
 }
 
 int batch_stage_threads(int stage) {
@@ -2861,6 +2883,22 @@ static hipError_t launch_stage_t(const BatchItem *d_items, const int *d_prefix, 
   hipError_t e = lds_request(reinterpret_cast<const void *>(&k_batch<STAGE, T>), lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_batch<STAGE, T>), dim3(total_blocks), dim3(T), lds, st, d_items, d_prefix, n, mode);
+  LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t launch_batch_pair(const BatchItem *d_items, const int *d_prefix_a, int total_a, const int *d_prefix_b,
+                             int total_b, int n, int stage_a, hipStream_t st) {
+  const int total = total_a + total_b;
+  if (total <= 0) return hipSuccess;
+  if (stage_a == kBsBin)
+    hipLaunchKernelGGL((k_batch_pair<kBsBin, kBsQsum>), dim3(total), dim3(PSWF_THREADS), 0, st, d_items, d_prefix_a,
+                       total_a, d_prefix_b, n);
+  else if (stage_a == kBsScatter)
+    hipLaunchKernelGGL((k_batch_pair<kBsScatter, kBsQreduce>), dim3(total), dim3(PSWF_THREADS), 0, st, d_items,
+                       d_prefix_a, total_a, d_prefix_b, n);
+  else
+    return hipErrorInvalidValue;
   LAUNCH_CHECK();
   return hipSuccess;
 }

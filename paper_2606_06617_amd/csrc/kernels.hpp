@@ -76,6 +76,9 @@ hipError_t launch_realspace(const RsGeo &g, const RsTables &t, const RsWork &w, 
 
 // batched execution (one launch per stage over every structure)
 int batch_stage_threads(int stage);
+// stage_a = kBsBin (with kBsQsum) or kBsScatter (with kBsQreduce) in one launch
+hipError_t launch_batch_pair(const BatchItem *d_items, const int *d_prefix_a, int total_a, const int *d_prefix_b,
+                             int total_b, int n, int stage_a, hipStream_t st);
 int batch_stage_blocks(const BatchItem &it, int stage, bool adjoint);
 size_t batch_stage_lds(const BatchItem &it, int stage);
 hipError_t launch_batch_stage(const BatchItem *d_items, const int *d_prefix, int n, int stage, int total_blocks,

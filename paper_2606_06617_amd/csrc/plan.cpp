@@ -1276,7 +1276,15 @@ pswflr_status batch_impl(int32_t n, const pswflr_plan *plans, const BatchEntry *
     // the adjoint runs the scaled x pass and what follows it, minus the
     // energy reduction
     if (adjoint_call && (stg < kBsXmul || stg == kBsFinalize)) continue;
+    // the charge sums ride in the binning launch, their reduction in the
+    // scatter launch
+    if (stg == kBsQsum || stg == kBsQreduce) continue;
     e = run(stage_profile_id(stg), [&] {
+      if (stg == kBsBin || stg == kBsScatter) {
+        const int pb = stg == kBsBin ? kBsQsum : kBsQreduce;
+        return launch_batch_pair(d_items, d_prefix + stg * (n + 1), total[stg], d_prefix + pb * (n + 1), total[pb], n,
+                                 stg, st);
+      }
       if (stg != kBsSpread)
         return launch_batch_stage(d_items, d_prefix + stg * (n + 1), n, stg, total[stg], lds[stg], 1, st);
       hipError_t r = hipSuccess;
