@@ -332,7 +332,8 @@ pswflr_status pswflr_backward_batch_flat(int32_t n, const pswflr_plan *plans, co
  * one plan from several threads while enabled. */
 enum {
   PSWFLR_STAGE_SORT = 0,       /* binning, cell order                      */
-  PSWFLR_STAGE_QSUM = 1,       /* per-channel sum q, sum q^2               */
+  PSWFLR_STAGE_QSUM = 1,       /* per-channel sum q, sum q^2 (launched with
+                                  the sort and timed as its part)         */
   PSWFLR_STAGE_SPREAD = 2,     /* step (i), one launch per channel group   */
   PSWFLR_STAGE_FFT_Z = 3,      /* z real-to-complex                        */
   PSWFLR_STAGE_FFT_Y = 4,      /* y forward                                */

@@ -565,6 +565,28 @@ __device__ __forceinline__ void qreduce_body(const Geo &g, const Work &w, int nb
 
 __global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nblk) { qreduce_body(g, w, nblk); }
 
+// The charge sums need only the charges, so they share launches with the
+// sort: their per-block partials ride beside the binning (blocks nbin ..
+// of the grid, chunk-major per channel), their reduction beside the
+// scatter (the grid's last block).  Two launches fewer per call.
+__global__ __launch_bounds__(PSWF_THREADS) void k_bin_qsum(Geo g, Work w, const float *__restrict__ pos,
+                                                           const float *__restrict__ q, int nbin, int nq) {
+  const int b = blockIdx.x;
+  if (b < nbin) {
+    bin_body(g, w, pos, q, b);
+  } else {
+    const int k = b - nbin;
+    qsum_body(g, w, q, kQChunk, k % nq, k / nq);
+  }
+}
+
+__global__ __launch_bounds__(PSWF_THREADS) void k_scatter_qreduce(Geo g, Work w, int nscatter, int nq) {
+  if (int(blockIdx.x) < nscatter)
+    scatter_body(g, w, blockIdx.x);
+  else
+    qreduce_body(g, w, nq);
+}
+
 // Small structures (N <= kPrepSmallMax): the steps above in one workgroup
 // of 1024 threads and one launch, with the same results bit for bit --
 // records, tile counts and starts, the order inside each tile (ascending
@@ -2428,18 +2450,19 @@ static hipError_t lds_request(const void *fn, size_t bytes) {
 }
 
 hipError_t enqueue_sort(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st) {
-  // cell offsets are produced even for N = 0 (the spread reads them)
+  // cell offsets are produced even for N = 0 (the spread reads them); the
+  // charge sums (zero for N = 0) ride in the binning and scatter launches
+  const int nq = qsum_blocks(g);
+  const int nbin = g.N > 0 ? int(nblocks(g.N, PSWF_THREADS)) : 0;
   hipLaunchKernelGGL(k_zero, dim3(nblocks(g.ncell, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, w);
   LAUNCH_CHECK();
-  if (g.N > 0) {
-    hipLaunchKernelGGL(k_bin, dim3(nblocks(g.N, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, w, pos, q);
-    LAUNCH_CHECK();
-  }
+  hipLaunchKernelGGL(k_bin_qsum, dim3(nbin + nq * g.C), dim3(PSWF_THREADS), 0, st, g, w, pos, q, nbin, nq);
+  LAUNCH_CHECK();
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, w, g.ncell, g.N);
   LAUNCH_CHECK();
-  if (g.N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter, dim3(nblocks(g.N, PSWF_THREADS)), dim3(PSWF_THREADS), 0, st, g, w);
+  hipLaunchKernelGGL(k_scatter_qreduce, dim3(nbin + 1), dim3(PSWF_THREADS), 0, st, g, w, nbin, nq);
   LAUNCH_CHECK();
+  if (g.N == 0) return hipSuccess;
   hipLaunchKernelGGL(k_order, dim3(g.ncell), dim3(PSWF_THREADS), 0, st, g, w);
   LAUNCH_CHECK();
   return hipSuccess;
@@ -2451,15 +2474,6 @@ bool prep_small(const Geo &g) { return g.N <= kPrepSmallMax; }
 
 hipError_t enqueue_prep_small(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st) {
   hipLaunchKernelGGL(k_prep_small, dim3(1), dim3(kPrepThreads), 0, st, g, w, pos, q);
-  LAUNCH_CHECK();
-  return hipSuccess;
-}
-
-hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t st) {
-  const int nb = qsum_blocks(g);
-  hipLaunchKernelGGL(k_qsum, dim3(nb, g.C), dim3(PSWF_THREADS), 0, st, g, w, q, kQChunk);
-  LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_qreduce, dim3(1), dim3(PSWF_THREADS), 0, st, g, w, nb);
   LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -33,9 +33,9 @@ int spread_candidate_cells(const int *nc, const int *b, int P);  // cells a tile
 int spread_max_cells();
 int spread_flush_cap(int64_t tiles);  // candidates per flush of the vector-ALU spread for a launch of this many tiles
 
+// binning, cell order and the per-channel charge sums (five launches)
 hipError_t enqueue_sort(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st);
-hipError_t enqueue_qsum(const Geo &g, const Work &w, const float *q, hipStream_t st);
-// one launch for enqueue_sort + enqueue_qsum when prep_small(g)
+// the same in one launch when prep_small(g)
 bool prep_small(const Geo &g);
 hipError_t enqueue_prep_small(const Geo &g, const Work &w, const float *pos, const float *q, hipStream_t st);
 hipError_t launch_spread(const Geo &g, const Tables &t, const Work &w, int cg0, int ncg, hipStream_t st,

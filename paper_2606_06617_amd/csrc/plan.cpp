@@ -842,8 +842,8 @@ hipError_t run_forward(pswflr_plan_s *pl, hipStream_t st, const Geo &g, const Wo
   if (prep_small(g)) {
     if ((e = run(PSWFLR_STAGE_SORT, [&] { return enqueue_prep_small(g, w, pos, q, st); })) != hipSuccess) return e;
   } else {
+    // the charge sums ride in the sort's launches (timed as the sort)
     if ((e = run(PSWFLR_STAGE_SORT, [&] { return enqueue_sort(g, w, pos, q, st); })) != hipSuccess) return e;
-    if ((e = run(PSWFLR_STAGE_QSUM, [&] { return enqueue_qsum(g, w, q, st); })) != hipSuccess) return e;
   }
   for (int cg0 = 0; cg0 < g.C; cg0 += g.CG_spread) {
     const int ncg = std::min(g.CG_spread, g.C - cg0);
