@@ -2165,17 +2165,22 @@ __global__ __launch_bounds__(kGatherThreads, 4) void k_gather(Geo g, Tables t, W
 // E_lr = sum_c (E_k + E_0) in channel order) and virial [6].  A non-finite
 // input position (status word set by the binning) makes E_lr, every E_k and
 // the virial NaN.
+template <int THREADS>
 __device__ __forceinline__ void finalize_body(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial) {
-  // one wave per channel at a time (channels c = wave, wave + 4, ...): lane
-  // sums over the x-pass blocks, then a fixed-order wave reduction; the
-  // channels' energy and virial terms are added in channel order by one
-  // thread each
+  // one wave per channel at a time (channels c = wave, wave + THREADS / 64,
+  // ...): lane sums over the x-pass blocks, then a fixed-order wave
+  // reduction; the channels' energy and virial terms are added in channel
+  // order by one thread each.  The result does not depend on THREADS: each
+  // lane adds its blocks in the same order whichever wave holds the channel.
   __shared__ double vch[kMaxChannels][7];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool bad = w.status[0] != 0;
   const double nan = __longlong_as_double(0x7ff8000000000000ll);
-  for (int c = wave; c < g.C; c += PSWF_THREADS / 64) {
+  for (int c = wave; c < g.C; c += THREADS / 64) {
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    // unrolled so that several blocks' partials are in flight at once; the
+    // additions stay in block order
+#pragma unroll 4
     for (int b = lane; b < g.nxblk; b += 64)
 #pragma unroll
       for (int i = 0; i < 7; ++i) acc[i] += w.epart[(int64_t(c) * g.nxblk + b) * 8 + i];
@@ -2209,8 +2214,10 @@ __device__ __forceinline__ void finalize_body(const Geo &g, const Tables &t, con
   }
 }
 
-__global__ __launch_bounds__(PSWF_THREADS) void k_finalize(Geo g, Tables t, Work w, double *energy, double *virial) {
-  finalize_body(g, t, w, energy, virial);
+// one wave per channel (up to 16 channels at once)
+constexpr int kFinalizeThreads = 1024;
+__global__ __launch_bounds__(kFinalizeThreads) void k_finalize(Geo g, Tables t, Work w, double *energy, double *virial) {
+  finalize_body<kFinalizeThreads>(g, t, w, energy, virial);
 }
 // Input validation (plans created with PSWFLR_FLAG_CHECK_INPUTS): bit 0 of
 // word[0] is set when a position is not finite, bit 1 when a charge is not.
@@ -2684,7 +2691,7 @@ hipError_t launch_double_backward(const Geo &g, const Tables &t, const FftAxis &
 
 hipError_t launch_finalize(const Geo &g, const Tables &t, const Work &w, double *energy, double *virial,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(PSWF_THREADS), 0, st, g, t, w, energy, virial);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeThreads), 0, st, g, t, w, energy, virial);
   LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -2727,7 +2734,7 @@ __device__ __forceinline__ void batch_stage_block(const BatchItem *__restrict__ 
       break;
     }
     case kBsXmul: xmul_body(g, it.t, it.ax, it.w, it.mode, it.grad, vb % g.nxblk, vb / g.nxblk); break;
-    case kBsFinalize: finalize_body(g, it.t, it.w, it.energy, it.virial); break;
+    case kBsFinalize: finalize_body<PSWF_THREADS>(g, it.t, it.w, it.energy, it.virial); break;
     case kBsYinv: {
       const int gx = (g.KZ + g.kzq - 1) / g.kzq;
       yinv_body(g, it.t, it.ay, it.w, vb % gx, vb / gx);
