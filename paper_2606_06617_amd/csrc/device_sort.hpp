@@ -11,29 +11,48 @@ namespace pswf {
 constexpr int kSortThreads = 256;  // threads of the ordering kernels
 
 // exclusive scan of count[0..n) into start[0..n], start[n] = total (one
-// block of 1024 threads)
+// block of 1024 threads).  Each thread takes kScanPer consecutive counts
+// and scans them serially; the threads' sums are scanned inside each wave
+// by shuffles, and the waves' totals through LDS: one pass with two
+// barriers per 1024 kScanPer counts.  Integer sums, so the result does not
+// depend on the grouping.
+constexpr int kScanPer = 8;
 __device__ inline void scan_counts(const int *count, int *start, int n, int64_t total) {
-  __shared__ int part[1024];
-  __shared__ int carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < n; base += 1024) {
-    int i = base + threadIdx.x;
-    int v = i < n ? count[i] : 0;
-    part[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      int t = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-      __syncthreads();
-      part[threadIdx.x] += t;
-      __syncthreads();
+  __shared__ int wsum[1024 / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int carry = 0;
+  for (int base = 0; base < n; base += 1024 * kScanPer) {
+    const int i0 = base + tid * kScanPer;
+    int v[kScanPer], s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      v[k] = i0 + k < n ? count[i0 + k] : 0;
+      s += v[k];
     }
-    if (i < n) start[i] = carry + part[threadIdx.x] - v;
+    int x = s;  // inclusive scan of the threads' sums within the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    if (threadIdx.x == 1023) carry += part[1023];
-    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < 1024 / 64; ++k) {
+      before += k < wave ? wsum[k] : 0;
+      all += wsum[k];
+    }
+    int e = carry + before + x - s;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      if (i0 + k < n) start[i0 + k] = e;
+      e += v[k];
+    }
+    carry += all;
+    __syncthreads();  // wsum is rewritten by the next round
   }
-  if (threadIdx.x == 0) start[n] = int(total);
+  if (tid == 0) start[n] = int(total);
 }
 
 // Crowded cell (more keys than fit the LDS rank): stable least-significant-
