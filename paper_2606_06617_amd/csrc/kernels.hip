@@ -428,17 +428,29 @@ __device__ __forceinline__ void bin_atom(const Geo &g, const Work &w, const floa
   *reinterpret_cast<float4 *>(w.q_b + i * g.srec) = r;
 }
 
+constexpr int kBinQChunk = 16;  // channels staged through LDS at a time by the binning
 __device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const float *__restrict__ pos,
                                          const float *__restrict__ q, int bx) {
   // atoms staged in caller order as records of g.srec floats: window
   // offsets and packed start, then the C charges (padded to a multiple of
-  // four), so the reorder reads one aligned record per atom; consecutive
-  // threads write consecutive charge words of the block's records
+  // four), so the reorder reads one aligned record per atom.  The charges
+  // pass through LDS, up to kBinQChunk channels at a time: each channel's
+  // run of the block's charges is read coalesced, then consecutive threads
+  // write consecutive charge words of the block's records
+  __shared__ float qs[kBinQChunk][PSWF_THREADS + 1];
   const int64_t b0 = int64_t(bx) * PSWF_THREADS;
   const int nrow = g.N - b0 < PSWF_THREADS ? int(g.N - b0) : PSWF_THREADS;
-  for (int f = threadIdx.x; f < nrow * g.C; f += PSWF_THREADS) {
-    const int a = f / g.C, ch = f - a * g.C;
-    w.q_b[(b0 + a) * g.srec + 4 + ch] = q[int64_t(ch) * g.N + b0 + a];
+  const int tid = threadIdx.x;
+  for (int c0 = 0; c0 < g.C; c0 += kBinQChunk) {
+    const int nc = min(kBinQChunk, g.C - c0);
+    if (tid < nrow)
+      for (int k = 0; k < nc; ++k) qs[k][tid] = q[int64_t(c0 + k) * g.N + b0 + tid];
+    __syncthreads();
+    for (int f = tid; f < nrow * nc; f += PSWF_THREADS) {
+      const int a = f / nc, ch = f - a * nc;
+      w.q_b[(b0 + a) * g.srec + 4 + c0 + ch] = qs[ch][a];
+    }
+    __syncthreads();
   }
   const int64_t i = b0 + threadIdx.x;
   if (i < g.N) bin_atom(g, w, pos, i);
