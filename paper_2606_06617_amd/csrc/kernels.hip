@@ -580,7 +580,7 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nbl
 // The charge sums need only the charges, so they share launches with the
 // sort: their per-block partials ride beside the binning (blocks nbin ..
 // of the grid, chunk-major per channel), their reduction beside the
-// scatter (the grid's last block).  Two launches fewer per call.
+// scatter (the grid's first block).  Two launches fewer per call.
 __global__ __launch_bounds__(PSWF_THREADS) void k_bin_qsum(Geo g, Work w, const float *__restrict__ pos,
                                                            const float *__restrict__ q, int nbin, int nq) {
   const int b = blockIdx.x;
@@ -592,11 +592,14 @@ __global__ __launch_bounds__(PSWF_THREADS) void k_bin_qsum(Geo g, Work w, const 
   }
 }
 
+// the reduction is block 0, so that its serial channel loop starts first
+// and overlaps the scatter blocks
 __global__ __launch_bounds__(PSWF_THREADS) void k_scatter_qreduce(Geo g, Work w, int nscatter, int nq) {
-  if (int(blockIdx.x) < nscatter)
-    scatter_body(g, w, blockIdx.x);
-  else
+  (void)nscatter;
+  if (blockIdx.x == 0)
     qreduce_body(g, w, nq);
+  else
+    scatter_body(g, w, blockIdx.x - 1);
 }
 
 // Small structures (N <= kPrepSmallMax): the steps above in one workgroup
