@@ -456,11 +456,6 @@ __device__ __forceinline__ void bin_body(const Geo &g, const Work &w, const floa
   if (i < g.N) bin_atom(g, w, pos, i);
 }
 
-__global__ __launch_bounds__(PSWF_THREADS) void k_bin(Geo g, Work w, const float *__restrict__ pos,
-                                                      const float *__restrict__ q) {
-  bin_body(g, w, pos, q, blockIdx.x);
-}
-
 // exclusive scan of cell counts (single block)
 __device__ __forceinline__ void scan_body(const Work &w, int ncell, int64_t N) {
   scan_counts(w.cell_count, w.cell_start, ncell, N);
@@ -476,8 +471,6 @@ __device__ __forceinline__ void scatter_body(const Geo &g, const Work &w, int bx
   const int dst = w.cell_start[w.cell_of[i]] + w.slot[i];
   w.perm_b[dst] = int(i);
 }
-
-__global__ __launch_bounds__(PSWF_THREADS) void k_scatter(Geo g, Work w) { scatter_body(g, w, blockIdx.x); }
 
 // move atom `key` (caller index) to cell-order position dst: its record,
 // its charges and the permutation entry
@@ -545,10 +538,6 @@ __device__ __forceinline__ void qsum_body(const Geo &g, const Work &w, const flo
   }
 }
 
-__global__ __launch_bounds__(PSWF_THREADS) void k_qsum(Geo g, Work w, const float *__restrict__ q, int chunk) {
-  qsum_body(g, w, q, chunk, blockIdx.x, blockIdx.y);
-}
-
 __device__ __forceinline__ void qreduce_body(const Geo &g, const Work &w, int nblk) {
   __shared__ double s0[PSWF_THREADS], s1[PSWF_THREADS];
   for (int c = 0; c < g.C; ++c) {
@@ -574,8 +563,6 @@ __device__ __forceinline__ void qreduce_body(const Geo &g, const Work &w, int nb
     __syncthreads();
   }
 }
-
-__global__ __launch_bounds__(PSWF_THREADS) void k_qreduce(Geo g, Work w, int nblk) { qreduce_body(g, w, nblk); }
 
 // The charge sums need only the charges, so they share launches with the
 // sort: their per-block partials ride beside the binning (blocks nbin ..
@@ -638,8 +625,8 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_small(Geo g, Work w, cons
     for (int m = s; m < e; ++m) rank += lperm[m] < key;
     order_move(g, w, key, s + rank);
   }
-  // charge sums per channel, in the order of k_qsum (one block of 256
-  // threads, as N <= kQChunk) followed by k_qreduce over that one block
+  // charge sums per channel, in the order of qsum_body (one block of 256
+  // threads, as N <= kQChunk) followed by qreduce_body over that one block
   for (int c = 0; c < g.C; ++c) {
     for (int pass = 0; pass < 2; ++pass) {
       double a = 0.0, b = 0.0;
