@@ -1690,7 +1690,7 @@ __device__ __forceinline__ void xmul_body(const Geo &g, const Tables &t, const F
 
 // REG: the register FFT path (the planner's 256-point geometry)
 template <bool REG>
-__global__ __launch_bounds__(PSWF_THREADS) void k_xmul(Geo g, Tables t, FftAxis ax, Work w, int mode,
+__global__ __launch_bounds__(PSWF_THREADS, REG ? 4 : 1) void k_xmul(Geo g, Tables t, FftAxis ax, Work w, int mode,
                                                         const double *__restrict__ grad) {
   if (REG)
     xmul_reg(g, t, w, mode, grad, blockIdx.x, blockIdx.y);
